@@ -1,0 +1,77 @@
+"""Pins of the randomized (randomize-then-orthogonalize) rounding oracle."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import sketch as SK
+from oracle import tt as T
+from paper_2512_07811_amd import inputs as I
+
+
+def _natural(m):
+    n = len(m)
+    return [1] + [int(min(np.prod(m[:k]), np.prod(m[k:]))) for k in range(1, n)] + [1]
+
+
+def test_rto_exact_when_sketch_covers_rank():
+    m = [3, 2, 2, 2, 2, 2]
+    x = I.random_tt(m, [1, 3, 4, 4, 3, 2, 1], seed=31)
+    nat = _natural(m)
+    ells = [1] + [min(nat[k], T.ranks(x)[k] + 3) for k in range(1, len(m))] + [1]
+    om = I.gaussian_sketch(m, ells, seed=32)
+    y = SK.rto(x, om)
+    assert np.max(np.abs(T.full(y) - T.full(x))) < 1e-12 * np.max(np.abs(T.full(x)))
+    for c in y[:-1]:
+        assert np.allclose(T.left_gram(c), np.eye(c.shape[2]), atol=1e-13)
+
+
+def test_rto_is_orthogonal_projection():
+    m = [3] + [2] * 7
+    x = I.graded_tt(m, [1, 3, 6, 8, 8, 8, 6, 4, 1], decay=0.5, seed=33)
+    ells = [1, 2, 3, 4, 4, 4, 3, 2, 1]
+    om = I.gaussian_sketch(m, ells, seed=34)
+    y = SK.rto(x, om)
+    X, Y = T.full(x), T.full(y)
+    # Pythagoras: ||x||^2 = ||y||^2 + ||x - y||^2 and <x - y, y> = 0
+    assert abs(np.vdot(X - Y, Y)) < 1e-12 * np.linalg.norm(X) ** 2
+    assert abs(np.linalg.norm(X) ** 2 - np.linalg.norm(Y) ** 2
+               - np.linalg.norm(X - Y) ** 2) < 1e-12 * np.linalg.norm(X) ** 2
+    assert abs(np.linalg.norm(y[-1]) - np.linalg.norm(Y)) < 1e-13 * np.linalg.norm(X)
+
+
+def test_right_sketch_definition_by_brute_force():
+    # W_k = unfolding_{>=k}(x) times unfolding_{>=k}(Omega)^T
+    m = [3, 2, 2, 2]
+    x = I.random_tt(m, [1, 3, 4, 2, 1], seed=35)
+    ells = [1, 2, 3, 2, 1]
+    om = I.gaussian_sketch(m, ells, seed=36)
+    W = SK.right_sketches(x, om)
+    for k in range(1, len(m)):
+        # explicit: contract x_{>=k} and Omega_{>=k} over all physical indices
+        def right_part(cores):
+            res = cores[-1][:, :, 0]                      # (r, p)
+            for c in reversed(cores[:-1]):
+                r, p, r2 = c.shape
+                res = np.einsum("aib,bj->aij", c, res.reshape(r2, -1)).reshape(r, -1)
+            return res
+        Xr = right_part(x[k:])
+        Or = right_part(om[k:])
+        assert np.allclose(W[k], Xr @ Or.T, atol=1e-12)
+
+
+@pytest.mark.parametrize("eps", [1e-3, 1e-6])
+def test_sketch_round_meets_tolerance_with_oversampling(eps):
+    m = [3] + [2] * 9
+    x = I.graded_tt(m, [1, 3, 6, 10, 12, 12, 12, 10, 6, 3, 1], decay=0.3, seed=37)
+    nat = _natural(m)
+    ells = [1] + [min(nat[k], 16) for k in range(1, len(m))] + [1]
+    om = I.gaussian_sketch(m, ells, seed=38)
+    z, info = SK.sketch_round(x, om, eps)
+    X, Z = T.full(x), T.full(z)
+    assert info["ok"]
+    assert np.linalg.norm(X - Z) <= eps * np.linalg.norm(X) * (1 + 1e-8)
+    # compare with the deterministic SVD rounding: ranks agree within 1
+    _, ref = T.round_tt(x, eps, return_info=True)
+    for k in range(1, len(m)):
+        assert abs(info["ranks"][k] - ref["ranks"][k]) <= 1
