@@ -1,0 +1,176 @@
+/* qtthom.h -- C ABI of the MI355X hot path of SFFT/QTT Lippmann-Schwinger
+ * homogenization (Hauck, Kabel, Gauger, arXiv 2512.07811).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Status: every call returns a qt_status; 0 is success, negative values are
+ *   hard errors, QT_NOT_CONVERGED is informational.  The calling thread's last
+ *   error message is available from qt_last_error().  No C++ exception crosses
+ *   the boundary.
+ * Memory: all tensor data is device memory owned by the caller (the Python
+ *   binding uses PyTorch allocations).  The library owns only its workspace,
+ *   which it allocates at context creation or on first need and reuses.
+ * Streams: calls are asynchronous on the context's stream unless a host
+ *   output is requested (then they synchronize that stream before returning).
+ * Numbers: every TT is complex double, interleaved (re, im).  Core k of a TT
+ *   is stored row-major with shape (r_k, p_k, r_{k+1}) (left bond, physical
+ *   index, right bond) packed with its ACTUAL ranks inside a slot sized by its
+ *   rank CAPACITIES; r_0 = r_n = 1.  (The paper writes a core as
+ *   (r_k x p x r_{k-1}); only the storage order differs.)
+ * Ranks: actual ranks live in DEVICE memory and are updated by the kernels,
+ *   so that a whole iteration needs no host synchronisation; capacities are
+ *   host values fixed by the caller.
+ * Batches: a qt_tt may describe B instances with identical modes and
+ *   capacities; instance b's data starts at data + b*inst_stride elements and
+ *   its ranks at ranks + b*(n+1).
+ */
+#ifndef QTTHOM_H
+#define QTTHOM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t qt_status;
+#define QT_OK             0
+#define QT_NOT_CONVERGED  1   /* informational: iteration cap reached          */
+#define QT_EINVAL        -1   /* bad argument, shape mismatch or aliasing       */
+#define QT_ECAPACITY     -2   /* a result does not fit the output capacities    */
+#define QT_ENOMEM        -3   /* workspace allocation failed                    */
+#define QT_EHIP          -4   /* HIP runtime error                              */
+#define QT_ENUMERIC      -5   /* Jacobi sweep cap reached or non-finite values  */
+
+/* Rounding modes. */
+#define QT_ROUND_SVD      0   /* QR sweep + truncated-SVD sweep (Sec. 2.2)       */
+#define QT_ROUND_SKETCH   1   /* randomized range sketch + SVD truncation        */
+#define QT_ROUND_LEARNED  2   /* sketch at MLP-predicted ranks, SVD fallback     */
+
+/* Contraction precision of the structured (sketch) kernels. */
+#define QT_PREC_F64       0
+#define QT_PREC_F32       1
+
+typedef struct qt_ctx_s* qt_ctx;
+
+/* A batch of B tensor trains with n cores (Sec. 2, eq. tt_format). */
+typedef struct {
+  int32_t n;                /* number of cores                                   */
+  int32_t batch;            /* B >= 1                                            */
+  const int32_t* modes;     /* host [n]: physical dimension p_k                  */
+  const int32_t* cap;       /* host [n+1]: rank capacities, cap[0] = cap[n] = 1  */
+  const int64_t* offsets;   /* host [n]: element offset of core k's slot         */
+  int64_t inst_stride;      /* elements between instances (>= sum of slots)      */
+  int32_t* ranks;           /* device [B][n+1]: actual ranks (ranks[0]=ranks[n]=1) */
+  void* data;               /* device complex double                             */
+} qt_tt;
+
+/* A tensor-train operator (eq. tto_format) with fixed, host-known ranks.
+ * Core k is (r_k, p_out, p_in, r_{k+1}) row-major, or, when diag[k] != 0, a
+ * diagonal core stored as (r_k, p, r_{k+1}) meaning D(a,i,j,b) = B(a,i,b) d(i,j)
+ * (the TT -> TTO lift, eq. tt_to_tto). */
+typedef struct {
+  int32_t n;
+  const int32_t* modes_out; /* host [n] */
+  const int32_t* modes_in;  /* host [n] */
+  const int32_t* ranks;     /* host [n+1] */
+  const int32_t* diag;      /* host [n]  */
+  const int64_t* offsets;   /* host [n]  */
+  const void* data;         /* device complex double */
+} qt_mpo;
+
+typedef struct {
+  double eps;               /* relative tolerance of eq. (rounding_condition_tt) */
+  int32_t max_rank;         /* rank cap (<= output capacities); 0 = capacity     */
+  int32_t mode;             /* QT_ROUND_*                                        */
+  int32_t jacobi_max_sweeps;/* 0 = default (30)                                  */
+  int32_t precision;        /* QT_PREC_* for sketch contractions                 */
+  int32_t oversample;       /* extra sketch columns per bond (sketch modes)      */
+  uint64_t seed;            /* counter-based Gaussian sketch seed                */
+} qt_round_opts;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context on `device` using the borrowed hipStream_t `stream`
+ * (NULL = default stream).  Reserves `ws_bytes` of workspace now (0 = lazily). */
+qt_status qt_ctx_create(int device, void* stream, size_t ws_bytes, qt_ctx* out);
+void      qt_ctx_destroy(qt_ctx ctx);
+/* Last error message of the calling thread ("" if none). */
+const char* qt_last_error(void);
+/* Block until every call issued on the context's stream has finished. */
+qt_status qt_ctx_sync(qt_ctx ctx);
+
+/* ---- TT algebra (Sec. 2.1) --------------------------------------------- */
+
+/* out = a (Hadamard) b: C_k(i) = A_k(i) (Kronecker) B_k(i); exact, ranks
+ * r_a*r_b with a's bond index slow.  Needs out->cap[k] >= a->cap[k]*b->cap[k].
+ * out must not alias a or b.  Batch sizes must match (or a->batch == 1, which
+ * broadcasts a over b's instances). */
+qt_status tt_hadamard(qt_ctx ctx, const qt_tt* a, const qt_tt* b, qt_tt* out);
+
+/* out = A x: B_k(i) = sum_j D_k(i,j) (Kronecker) X_k(j) (TT x TTO contraction);
+ * exact, ranks r_A*r_x with the operator bond slow. */
+qt_status tt_mpo_apply(qt_ctx ctx, const qt_mpo* A, const qt_tt* x, qt_tt* out);
+
+/* out = alpha*x + beta*y by block-diagonal cores (addition, constant
+ * multiplication and subtraction of Sec. 2.1); ranks r_x + r_y. */
+qt_status tt_add(qt_ctx ctx, double alpha_re, double alpha_im, const qt_tt* x,
+                 double beta_re, double beta_im, const qt_tt* y, qt_tt* out);
+
+/* ---- stability (Sec. 2.2) ----------------------------------------------- */
+
+/* In-place rounding.  QT_ROUND_SVD: left QR orthogonalization sweep, then a
+ * right-to-left truncated-SVD sweep keeping, per bond, the smallest rank whose
+ * discarded singular-value tail does not exceed eps*||x||/sqrt(n-1), capped by
+ * max_rank.  On return cores 1..n-1 are right-orthogonal.
+ * err_out (device [B], may be NULL): sqrt(sum of squared discarded tails)/||x||.
+ * norm_out (device [B], may be NULL): ||x||_F before rounding. */
+qt_status tt_round(qt_ctx ctx, qt_tt* x, const qt_round_opts* opts, double* err_out,
+                   double* norm_out);
+
+/* out[b] = sum_i conj(a_i) b_i for every instance (device [B][2] doubles). */
+qt_status tt_dot(qt_ctx ctx, const qt_tt* a, const qt_tt* b, double* out);
+
+/* ---- Algorithm 2 ------------------------------------------------------------ */
+
+/* Operands of one cell problem on a 2^L-per-axis grid: core 0 is the
+ * component (control) core of mode 3, cores 1..3L the x, y, z bits. */
+typedef struct {
+  int32_t L;
+  qt_tt kp;                 /* k' = k - k0, all-ones control core                */
+  qt_mpo S;                 /* SFFT operator (Q_L per axis, identity on core 0)  */
+  qt_mpo Sinv;              /* its adjoint                                       */
+  qt_mpo G;                 /* Green operator, momentum convention, diag spatial */
+  qt_tt E;                  /* rank-1 mean field(s), batch = field batch         */
+  const double* E_norm;     /* host [B]: |E| of each load                        */
+} qt_operands;
+
+typedef struct {
+  qt_round_opts round;      /* applied after every step                          */
+  double tol;               /* residual tolerance delta_tol                      */
+  int32_t max_iter;
+} qt_solve_opts;
+
+/* n_iter basic-scheme iterations (Algorithm 2) on the field batch e (in/out):
+ *   tau = round(k' (.) e); tau^ = round(S tau); eps^ = round(G tau^);
+ *   e' = round(E - S^dagger eps^); r = ||e' - e||_F / (|E| N^{3/2}).
+ * residual_out: device [n_iter][B] doubles (may be NULL).
+ * e->cap must hold opts->round.max_rank on every bond. */
+qt_status ls_iterate(qt_ctx ctx, const qt_operands* ops, qt_tt* e, const qt_solve_opts* opts,
+                     int32_t n_iter, double* residual_out);
+
+/* Full solve: e_0 = E (per instance), iterate until every residual < tol or
+ * max_iter; then A_eff[b][c] = Re <k_sel[c], e_b> / N^3 (Appendix A).
+ * k_sel: three single-instance TTs of k (not k') with unit control cores.
+ * e: field batch used as the iterate (capacities as for ls_iterate).
+ * A_eff: host [B][3]; iters: host [B] (iterations to convergence);
+ * residuals: host [max_iter][B] (may be NULL). */
+qt_status homogenize(qt_ctx ctx, const qt_operands* ops, const qt_tt* k_sel, qt_tt* e,
+                     const qt_solve_opts* opts, double* A_eff, int32_t* iters,
+                     double* residuals);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QTTHOM_H */

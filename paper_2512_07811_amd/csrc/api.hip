@@ -1,0 +1,452 @@
+// Context, workspace, validation and the Algorithm 2 entry points
+// (ls_iterate, homogenize) of the qtthom C ABI.
+#include <algorithm>
+#include <cstring>
+
+#include "kernels.h"
+#include "round.h"
+
+namespace qt {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+std::string hip_msg(hipError_t e, const char* what) {
+  return std::string(what) + ": " + hipGetErrorString(e);
+}
+
+qt_status ws_reserve(qt_ctx ctx, size_t bytes) {
+  bytes = (bytes + 255) & ~(size_t)255;
+  if (ctx->ws_top + bytes <= ctx->ws_size) return QT_OK;
+  size_t want = std::max(ctx->ws_top + bytes, ctx->ws_size + ctx->ws_size / 2);
+  // earlier work on the stream may still read the old arena
+  QT_HIP(hipStreamSynchronize(ctx->stream));
+  if (ctx->ws_top != 0) {
+    // live allocations inside the current call would move: refuse
+    set_error("workspace grew inside a call (internal sizing error)");
+    return QT_ENOMEM;
+  }
+  if (ctx->ws) QT_HIP(hipFree(ctx->ws));
+  ctx->ws = nullptr;
+  ctx->ws_size = 0;
+  hipError_t e = hipMalloc((void**)&ctx->ws, want);
+  if (e != hipSuccess) {
+    set_error(hip_msg(e, "hipMalloc(workspace)"));
+    return QT_ENOMEM;
+  }
+  ctx->ws_size = want;
+  return QT_OK;
+}
+
+void* ws_take(qt_ctx ctx, size_t bytes) {
+  bytes = (bytes + 255) & ~(size_t)255;
+  if (ctx->ws_top + bytes > ctx->ws_size) return nullptr;
+  void* p = ctx->ws + ctx->ws_top;
+  ctx->ws_top += bytes;
+  return p;
+}
+
+int64_t tt_slot_elems(const qt_tt* t, int k) {
+  return (int64_t)t->cap[k] * t->modes[k] * t->cap[k + 1];
+}
+
+qt_status tt_validate(const qt_tt* t, const char* name) {
+  std::string nm(name);
+  QT_CHECK(t->n >= 1 && t->n <= QT_MAX_CORES, QT_EINVAL, nm + ": core count out of range");
+  QT_CHECK(t->batch >= 1, QT_EINVAL, nm + ": batch < 1");
+  QT_CHECK(t->modes && t->cap && t->offsets && t->ranks && t->data, QT_EINVAL,
+           nm + ": null pointer in descriptor");
+  QT_CHECK(t->cap[0] == 1 && t->cap[t->n] == 1, QT_EINVAL, nm + ": boundary capacities must be 1");
+  int64_t end = 0;
+  for (int k = 0; k < t->n; ++k) {
+    QT_CHECK(t->modes[k] >= 1, QT_EINVAL, nm + ": mode < 1");
+    QT_CHECK(t->cap[k + 1] >= 1, QT_EINVAL, nm + ": capacity < 1");
+    QT_CHECK(t->offsets[k] >= 0, QT_EINVAL, nm + ": negative offset");
+    end = std::max(end, t->offsets[k] + tt_slot_elems(t, k));
+  }
+  QT_CHECK(t->batch == 1 || t->inst_stride >= end, QT_EINVAL, nm + ": instance stride too small");
+  return QT_OK;
+}
+
+TTLayout make_layout(const std::vector<int32_t>& modes, const std::vector<int32_t>& cap) {
+  TTLayout L;
+  L.modes = modes;
+  L.cap = cap;
+  int64_t off = 0;
+  for (size_t k = 0; k < modes.size(); ++k) {
+    L.off.push_back(off);
+    int64_t s = (int64_t)cap[k] * modes[k] * cap[k + 1];
+    off += (s + 31) & ~(int64_t)31;
+  }
+  L.stride = off;
+  return L;
+}
+
+__global__ void k_copy_ranks(int n1, int batch, const int32_t* src, int ss, int32_t* dst) {
+  int b = blockIdx.x;
+  if (b >= batch) return;
+  for (int k = threadIdx.x; k < n1; k += blockDim.x) dst[(int64_t)b * n1 + k] = src[(int64_t)b * ss + k];
+}
+
+// Copy every core (actual ranks) of src into dst's slots; src may broadcast (batch 1).
+static qt_status tt_copy(qt_ctx ctx, const qt_tt* src, qt_tt* dst) {
+  const int n = dst->n, B = dst->batch;
+  const int64_t sS = src->batch == 1 ? 0 : src->inst_stride;
+  const int srs = src->batch == 1 ? 0 : n + 1;
+  for (int k = 0; k < n; ++k) {
+    int64_t cap = (int64_t)std::min(src->cap[k], dst->cap[k]) * src->modes[k] *
+                  std::min(src->cap[k + 1], dst->cap[k + 1]);
+    copy(ctx->stream, B, dref(src->ranks + k, srs, src->modes[k]), dref(src->ranks + k + 1, srs),
+         cap, (const cplx*)src->data + src->offsets[k], sS, (cplx*)dst->data + dst->offsets[k],
+         dst->inst_stride);
+  }
+  k_copy_ranks<<<B, 64, 0, ctx->stream>>>(n + 1, B, src->ranks, srs, dst->ranks);
+  QT_HIP(hipGetLastError());
+  return QT_OK;
+}
+
+static std::vector<int32_t> natural_caps(const std::vector<int32_t>& modes) {
+  const int n = (int)modes.size();
+  std::vector<int32_t> nat(n + 1, 1);
+  for (int k = 1; k < n; ++k) {
+    double left = 1, right = 1;
+    for (int j = 0; j < k; ++j) left *= modes[j];
+    for (int j = k; j < n; ++j) right *= modes[j];
+    nat[k] = (int32_t)std::min(std::min(left, right), 1e9);
+  }
+  return nat;
+}
+
+static qt_status validate_ops(const qt_operands* ops, const qt_tt* e) {
+  QT_TRY(tt_validate(&ops->kp, "operands.kp"));
+  QT_TRY(tt_validate(&ops->E, "operands.E"));
+  QT_TRY(tt_validate(e, "e"));
+  const int n = e->n;
+  QT_CHECK(n == 3 * ops->L + 1, QT_EINVAL, "operands: n != 3L+1");
+  QT_CHECK(ops->kp.n == n && ops->E.n == n && ops->S.n == n && ops->Sinv.n == n && ops->G.n == n,
+           QT_EINVAL, "operands: core counts differ");
+  QT_CHECK(ops->kp.batch == 1, QT_EINVAL, "operands: kp must be a single train");
+  QT_CHECK(ops->E.batch == e->batch, QT_EINVAL, "operands: E batch must equal e batch");
+  QT_CHECK(ops->E_norm != nullptr, QT_EINVAL, "operands: E_norm missing");
+  for (int k = 0; k < n; ++k) QT_CHECK(e->modes[k] == (k == 0 ? 3 : 2), QT_EINVAL, "e: modes must be [3,2,...]");
+  return QT_OK;
+}
+
+// The field must hold every train a rounding can leave: min(natural rank, max_rank).
+static qt_status validate_field_cap(const qt_tt* e, int rmax) {
+  std::vector<int32_t> nat = natural_caps(std::vector<int32_t>(e->modes, e->modes + e->n));
+  for (int k = 0; k <= e->n; ++k) {
+    int need = rmax > 0 ? std::min(nat[k], rmax) : nat[k];
+    QT_CHECK(e->cap[k] >= need, QT_ECAPACITY, "e: capacity below min(natural rank, max_rank)");
+  }
+  return QT_OK;
+}
+
+// Capacities of the intermediates of one iteration.
+struct IterPlan {
+  std::vector<int32_t> modes, rc, c1, c2, c3, c4, c5, c6;
+  TTLayout l1, l2, l3, l4, l5, l6, lr;
+  size_t bytesA = 0, bytesB = 0;
+};
+
+static int32_t clampi(int64_t v) { return (int32_t)std::min<int64_t>(v, 1 << 30); }
+
+static IterPlan plan_iteration(const qt_operands* ops, const qt_tt* e, int rmax) {
+  IterPlan P;
+  const int n = e->n;
+  P.modes.assign(e->modes, e->modes + n);
+  std::vector<int32_t> nat = natural_caps(P.modes);
+  P.rc.resize(n + 1);
+  P.c1.resize(n + 1); P.c2.resize(n + 1); P.c3.resize(n + 1); P.c4.resize(n + 1);
+  P.c5.resize(n + 1); P.c6.resize(n + 1);
+  for (int k = 0; k <= n; ++k) {
+    int ce = e->cap[k];
+    P.rc[k] = std::min(std::min(nat[k], rmax > 0 ? rmax : ce), ce);
+    P.c1[k] = clampi((int64_t)ops->kp.cap[k] * ce);
+    int r1 = std::min<int64_t>(P.c1[k], std::min<int64_t>(nat[k], rmax > 0 ? rmax : P.c1[k]));
+    P.c2[k] = clampi((int64_t)ops->S.ranks[k] * r1);
+    int r2 = std::min<int64_t>(P.c2[k], std::min<int64_t>(nat[k], rmax > 0 ? rmax : P.c2[k]));
+    P.c3[k] = clampi((int64_t)ops->G.ranks[k] * r2);
+    int r3 = std::min<int64_t>(P.c3[k], std::min<int64_t>(nat[k], rmax > 0 ? rmax : P.c3[k]));
+    P.c4[k] = clampi((int64_t)ops->Sinv.ranks[k] * r3);
+    int r4 = std::min<int64_t>(P.c4[k], std::min<int64_t>(nat[k], rmax > 0 ? rmax : P.c4[k]));
+    P.c5[k] = (k == 0 || k == n) ? 1 : clampi((int64_t)ops->E.cap[k] + r4);
+    int r5 = std::min<int64_t>(P.c5[k], std::min<int64_t>(nat[k], rmax > 0 ? rmax : P.c5[k]));
+    P.c6[k] = (k == 0 || k == n) ? 1 : clampi((int64_t)r5 + ce);
+  }
+  P.l1 = make_layout(P.modes, P.c1);
+  P.l2 = make_layout(P.modes, P.c2);
+  P.l3 = make_layout(P.modes, P.c3);
+  P.l4 = make_layout(P.modes, P.c4);
+  P.l5 = make_layout(P.modes, P.c5);
+  P.l6 = make_layout(P.modes, P.c6);
+  const int B = e->batch;
+  P.bytesA = sizeof(cplx) * B * std::max({P.l1.stride, P.l3.stride, P.l5.stride});
+  P.bytesB = sizeof(cplx) * B * std::max({P.l2.stride, P.l4.stride, P.l6.stride});
+  return P;
+}
+
+// View of a rounded train with capacities reduced to what rounding can leave.
+static qt_tt shrink(const qt_tt& t, const std::vector<int32_t>& capv, int rmax,
+                    std::vector<int32_t>& store) {
+  const int n = t.n;
+  std::vector<int32_t> nat = natural_caps(std::vector<int32_t>(t.modes, t.modes + n));
+  store.resize(n + 1);
+  for (int k = 0; k <= n; ++k)
+    store[k] = std::min<int32_t>(capv[k], std::min<int32_t>(nat[k], rmax > 0 ? rmax : capv[k]));
+  qt_tt v = t;
+  v.cap = store.data();
+  return v;
+}
+
+static size_t round_bytes(const TTLayout& L, int B, int rmax) {
+  qt_tt t = L.view(nullptr, nullptr, B);
+  return round_ws_layout(&t, rmax > 0 ? rmax : (1 << 30)).bytes;
+}
+
+static size_t iteration_bytes(const IterPlan& P, int B, int rmax) {
+  size_t r = 0;
+  for (const TTLayout* L : {&P.l1, &P.l2, &P.l3, &P.l4, &P.l5, &P.l6})
+    r = std::max(r, round_bytes(*L, B, rmax));
+  const int n = (int)P.modes.size();
+  return P.bytesA + P.bytesB + r + sizeof(int32_t) * B * (n + 1) * 2 + sizeof(double) * B * 4 +
+         4096;
+}
+
+__global__ void k_residual(int batch, const double* norm, const double* inv_scale, double* out) {
+  int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < batch) out[b] = norm[b] * inv_scale[b];
+}
+
+// One iteration of Algorithm 2 with materialized products and SVD rounding.
+static qt_status iterate_once(qt_ctx ctx, const qt_operands* ops, qt_tt* e, const IterPlan& P,
+                              const qt_round_opts& ro, char* bufA, char* bufB, int32_t* rA,
+                              int32_t* rB, double* dnorm, const double* dinv, double* res_out) {
+  const int B = e->batch;
+  const int rmax = ro.max_rank;
+  const size_t mark = ctx->ws_top;
+  std::vector<int32_t> s1, s2, s3, s4, s5;
+  // tau = round(k' (.) e)
+  qt_tt t1 = P.l1.view(bufA, rA, B);
+  QT_TRY(hadamard_impl(ctx, &ops->kp, e, &t1));
+  QT_TRY(round_impl(ctx, &t1, &ro, nullptr, nullptr, false, nullptr, 0, 0));
+  ctx->ws_top = mark;
+  qt_tt t1r = shrink(t1, P.c1, rmax, s1);
+  // tau^ = round(S tau)
+  qt_tt t2 = P.l2.view(bufB, rB, B);
+  QT_TRY(mpo_impl(ctx, &ops->S, &t1r, &t2));
+  QT_TRY(round_impl(ctx, &t2, &ro, nullptr, nullptr, false, nullptr, 0, 0));
+  ctx->ws_top = mark;
+  qt_tt t2r = shrink(t2, P.c2, rmax, s2);
+  // eps^ = round(G tau^)
+  qt_tt t3 = P.l3.view(bufA, rA, B);
+  QT_TRY(mpo_impl(ctx, &ops->G, &t2r, &t3));
+  QT_TRY(round_impl(ctx, &t3, &ro, nullptr, nullptr, false, nullptr, 0, 0));
+  ctx->ws_top = mark;
+  qt_tt t3r = shrink(t3, P.c3, rmax, s3);
+  // S^dagger eps^
+  qt_tt t4 = P.l4.view(bufB, rB, B);
+  QT_TRY(mpo_impl(ctx, &ops->Sinv, &t3r, &t4));
+  QT_TRY(round_impl(ctx, &t4, &ro, nullptr, nullptr, false, nullptr, 0, 0));
+  ctx->ws_top = mark;
+  qt_tt t4r = shrink(t4, P.c4, rmax, s4);
+  // e' = round(E - S^dagger eps^)
+  qt_tt t5 = P.l5.view(bufA, rA, B);
+  QT_TRY(add_impl(ctx, 1.0, 0.0, &ops->E, -1.0, 0.0, &t4r, &t5));
+  QT_TRY(round_impl(ctx, &t5, &ro, nullptr, nullptr, false, nullptr, 0, 0));
+  ctx->ws_top = mark;
+  qt_tt t5r = shrink(t5, P.c5, rmax, s5);
+  // residual ||e' - e|| by left orthogonalization of the difference
+  qt_tt t6 = P.l6.view(bufB, rB, B);
+  QT_TRY(add_impl(ctx, 1.0, 0.0, &t5r, -1.0, 0.0, e, &t6));
+  QT_TRY(round_impl(ctx, &t6, &ro, nullptr, dnorm, true, nullptr, 0, 0));
+  ctx->ws_top = mark;
+  if (res_out) {
+    k_residual<<<(B + 127) / 128, 128, 0, ctx->stream>>>(B, dnorm, dinv, res_out);
+    QT_HIP(hipGetLastError());
+  }
+  // e <- e'
+  QT_TRY(tt_copy(ctx, &t5r, e));
+  return QT_OK;
+}
+
+static qt_status check_status(qt_ctx ctx) {
+  int32_t st = 0;
+  QT_HIP(hipMemcpyAsync(&st, ctx->status, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+  QT_HIP(hipStreamSynchronize(ctx->stream));
+  if (st) {
+    QT_HIP(hipMemsetAsync(ctx->status, 0, sizeof(int32_t), ctx->stream));
+    if (st & ST_NONFINITE) { set_error("non-finite values in a rounding"); return QT_ENUMERIC; }
+    if (st & ST_JACOBI_CAP) { set_error("Jacobi SVD reached its sweep cap"); return QT_ENUMERIC; }
+  }
+  return QT_OK;
+}
+
+struct IterSetup {
+  IterPlan P;
+  char* bufA = nullptr;
+  char* bufB = nullptr;
+  int32_t* rA = nullptr;
+  int32_t* rB = nullptr;
+  double* dnorm = nullptr;
+  double* dinv = nullptr;
+};
+
+static qt_status setup_iteration(qt_ctx ctx, const qt_operands* ops, qt_tt* e,
+                                 const qt_solve_opts* opts, IterSetup& S, size_t extra) {
+  const int B = e->batch, n = e->n;
+  const int rmax = opts->round.max_rank;
+  S.P = plan_iteration(ops, e, rmax);
+  ctx->ws_top = 0;
+  QT_TRY(ws_reserve(ctx, iteration_bytes(S.P, B, rmax) + extra));
+  S.bufA = (char*)ws_take(ctx, S.P.bytesA);
+  S.bufB = (char*)ws_take(ctx, S.P.bytesB);
+  S.rA = (int32_t*)ws_take(ctx, sizeof(int32_t) * B * (n + 1));
+  S.rB = (int32_t*)ws_take(ctx, sizeof(int32_t) * B * (n + 1));
+  S.dnorm = (double*)ws_take(ctx, sizeof(double) * B);
+  S.dinv = (double*)ws_take(ctx, sizeof(double) * B);
+  QT_CHECK(S.bufA && S.bufB && S.rA && S.rB && S.dnorm && S.dinv, QT_ENOMEM, "iteration workspace");
+  std::vector<double> inv(B);
+  const double N3 = std::ldexp(1.0, 3 * ops->L);
+  for (int b = 0; b < B; ++b) inv[b] = 1.0 / (ops->E_norm[b] * std::sqrt(N3));
+  QT_HIP(hipMemcpy(S.dinv, inv.data(), sizeof(double) * B, hipMemcpyHostToDevice));
+  return QT_OK;
+}
+
+}  // namespace qt
+
+using namespace qt;
+
+extern "C" {
+
+const char* qt_last_error(void) { return g_last_error.c_str(); }
+
+qt_status qt_ctx_create(int device, void* stream, size_t ws_bytes, qt_ctx* out) {
+  QT_CHECK(out, QT_EINVAL, "qt_ctx_create: null out");
+  *out = nullptr;
+  QT_HIP(hipSetDevice(device));
+  qt_ctx c = new qt_ctx_s();
+  c->device = device;
+  c->stream = (hipStream_t)stream;
+  hipError_t e = hipMalloc((void**)&c->status, sizeof(int32_t));
+  if (e != hipSuccess) {
+    delete c;
+    set_error(hip_msg(e, "hipMalloc(status)"));
+    return QT_ENOMEM;
+  }
+  e = hipMemset(c->status, 0, sizeof(int32_t));
+  if (e != hipSuccess) {
+    hipFree(c->status);
+    delete c;
+    set_error(hip_msg(e, "hipMemset(status)"));
+    return QT_EHIP;
+  }
+  if (ws_bytes) {
+    qt_status s = ws_reserve(c, ws_bytes);
+    if (s != QT_OK) {
+      hipFree(c->status);
+      delete c;
+      return s;
+    }
+  }
+  *out = c;
+  return QT_OK;
+}
+
+void qt_ctx_destroy(qt_ctx ctx) {
+  if (!ctx) return;
+  hipStreamSynchronize(ctx->stream);
+  if (ctx->ws) hipFree(ctx->ws);
+  if (ctx->status) hipFree(ctx->status);
+  delete ctx;
+}
+
+qt_status qt_ctx_sync(qt_ctx ctx) {
+  QT_CHECK(ctx, QT_EINVAL, "qt_ctx_sync: null ctx");
+  return check_status(ctx);
+}
+
+qt_status ls_iterate(qt_ctx ctx, const qt_operands* ops, qt_tt* e, const qt_solve_opts* opts,
+                     int32_t n_iter, double* residual_out) {
+  QT_CHECK(ctx && ops && e && opts, QT_EINVAL, "ls_iterate: null argument");
+  QT_TRY(validate_ops(ops, e));
+  QT_CHECK(n_iter >= 0, QT_EINVAL, "ls_iterate: n_iter < 0");
+  QT_CHECK(opts->round.mode == QT_ROUND_SVD, QT_EINVAL, "ls_iterate: rounding mode not available");
+  QT_TRY(validate_field_cap(e, opts->round.max_rank));
+  IterSetup S;
+  QT_TRY(setup_iteration(ctx, ops, e, opts, S, 0));
+  for (int it = 0; it < n_iter; ++it) {
+    QT_TRY(iterate_once(ctx, ops, e, S.P, opts->round, S.bufA, S.bufB, S.rA, S.rB, S.dnorm, S.dinv,
+                        residual_out ? residual_out + (int64_t)it * e->batch : nullptr));
+  }
+  return QT_OK;
+}
+
+qt_status homogenize(qt_ctx ctx, const qt_operands* ops, const qt_tt* k_sel, qt_tt* e,
+                     const qt_solve_opts* opts, double* A_eff, int32_t* iters,
+                     double* residuals) {
+  QT_CHECK(ctx && ops && k_sel && e && opts && A_eff && iters, QT_EINVAL, "homogenize: null argument");
+  QT_TRY(validate_ops(ops, e));
+  for (int c = 0; c < 3; ++c) {
+    QT_TRY(tt_validate(&k_sel[c], "k_sel"));
+    QT_CHECK(k_sel[c].batch == 1 && k_sel[c].n == e->n, QT_EINVAL, "homogenize: k_sel shape");
+  }
+  QT_CHECK(opts->max_iter >= 1, QT_EINVAL, "homogenize: max_iter < 1");
+  QT_CHECK(opts->round.mode == QT_ROUND_SVD, QT_EINVAL, "homogenize: rounding mode not available");
+  QT_TRY(validate_field_cap(e, opts->round.max_rank));
+  const int B = e->batch;
+  IterSetup S;
+  size_t dot_need = 4096 + sizeof(double) * 4 * B;
+  {
+    int64_t env = 1, tcap = 1;
+    for (int k = 0; k <= e->n; ++k) env = std::max<int64_t>(env, (int64_t)k_sel[0].cap[k] * e->cap[k]);
+    for (int k = 0; k < e->n; ++k)
+      tcap = std::max<int64_t>(tcap, (int64_t)k_sel[0].cap[k] * e->modes[k] * e->cap[k + 1]);
+    dot_need += sizeof(cplx) * B * (2 * env + tcap) + 1024;
+  }
+  QT_TRY(setup_iteration(ctx, ops, e, opts, S, dot_need));
+  double* dres = (double*)ws_take(ctx, sizeof(double) * B);
+  QT_CHECK(dres, QT_ENOMEM, "homogenize: workspace");
+  QT_TRY(tt_copy(ctx, &ops->E, e));
+  std::vector<double> hres(B);
+  std::vector<int> done(B, 0);
+  for (int b = 0; b < B; ++b) iters[b] = opts->max_iter;
+  int it = 0;
+  bool all = false;
+  for (it = 1; it <= opts->max_iter && !all; ++it) {
+    QT_TRY(iterate_once(ctx, ops, e, S.P, opts->round, S.bufA, S.bufB, S.rA, S.rB, S.dnorm, S.dinv,
+                        dres));
+    QT_HIP(hipMemcpyAsync(hres.data(), dres, sizeof(double) * B, hipMemcpyDeviceToHost, ctx->stream));
+    QT_TRY(check_status(ctx));
+    all = true;
+    for (int b = 0; b < B; ++b) {
+      if (residuals) residuals[(int64_t)(it - 1) * B + b] = hres[b];
+      if (!done[b] && hres[b] < opts->tol) { done[b] = 1; iters[b] = it; }
+      all = all && done[b];
+    }
+  }
+  // A_eff[b][c] = Re <k_sel[c], e_b> / N^3
+  const size_t mark = ctx->ws_top;
+  double* dd = (double*)ws_take(ctx, sizeof(double) * 2 * B);
+  QT_CHECK(dd, QT_ENOMEM, "homogenize: workspace");
+  std::vector<double> hd(2 * B);
+  const double N3 = std::ldexp(1.0, 3 * ops->L);
+  for (int c = 0; c < 3; ++c) {
+    ctx->ws_top = mark + 256 * ((sizeof(double) * 2 * B + 255) / 256);
+    // dot workspace must fit in what setup reserved: environments are small
+    qt_status s = dot_impl(ctx, &k_sel[c], e, dd, false);
+    if (s == QT_ENOMEM || ctx->ws_top > ctx->ws_size) {
+      set_error("homogenize: dot workspace");
+      return QT_ENOMEM;
+    }
+    QT_TRY(s);
+    QT_HIP(hipMemcpyAsync(hd.data(), dd, sizeof(double) * 2 * B, hipMemcpyDeviceToHost, ctx->stream));
+    QT_HIP(hipStreamSynchronize(ctx->stream));
+    for (int b = 0; b < B; ++b) A_eff[(int64_t)b * 3 + c] = hd[2 * b] / N3;
+  }
+  QT_TRY(check_status(ctx));
+  return all ? QT_OK : QT_NOT_CONVERGED;
+}
+
+}  // extern "C"

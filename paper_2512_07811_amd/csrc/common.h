@@ -1,0 +1,122 @@
+// Shared definitions of the qtthom HIP library (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/qtthom.h"
+
+#define QT_MAX_CORES 64
+
+namespace qt {
+
+typedef double2 cplx;
+
+__host__ __device__ inline cplx cmul(cplx a, cplx b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// conj(a) * b
+__host__ __device__ inline cplx cmulc(cplx a, cplx b) {
+  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__host__ __device__ inline cplx cadd(cplx a, cplx b) { return make_double2(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline cplx csub(cplx a, cplx b) { return make_double2(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline cplx cscale(cplx a, double s) { return make_double2(a.x * s, a.y * s); }
+__host__ __device__ inline cplx cconj(cplx a) { return make_double2(a.x, -a.y); }
+__host__ __device__ inline double cabs2(cplx a) { return a.x * a.x + a.y * a.y; }
+__device__ inline cplx czero() { return make_double2(0.0, 0.0); }
+// c += a * b
+__device__ inline void cfma(cplx& c, cplx a, cplx b) {
+  c.x = fma(a.x, b.x, c.x);
+  c.x = fma(-a.y, b.y, c.x);
+  c.y = fma(a.x, b.y, c.y);
+  c.y = fma(a.y, b.x, c.y);
+}
+
+// A dimension read from device memory: value = mul * p[b * stride] (or cst if p == null).
+struct Dim {
+  const int32_t* p;
+  int32_t stride;
+  int32_t mul;
+  int32_t cst;
+};
+__device__ inline int dimv(const Dim& d, int b) { return d.p ? d.mul * d.p[(int64_t)b * d.stride] : d.cst; }
+inline Dim dconst(int v) { return Dim{nullptr, 0, 0, v}; }
+inline Dim dref(const int32_t* p, int stride, int mul = 1) { return Dim{p, stride, mul, 0}; }
+
+// Wave-level reductions (wave64).
+__device__ inline double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+__device__ inline cplx wave_sum(cplx v) {
+  v.x = wave_sum(v.x);
+  v.y = wave_sum(v.y);
+  return v;
+}
+
+// Error reporting ---------------------------------------------------------
+void set_error(const std::string& msg);
+std::string hip_msg(hipError_t e, const char* what);
+
+#define QT_HIP(call)                                  \
+  do {                                                \
+    hipError_t _e = (call);                           \
+    if (_e != hipSuccess) {                           \
+      ::qt::set_error(::qt::hip_msg(_e, #call));      \
+      return QT_EHIP;                                 \
+    }                                                 \
+  } while (0)
+
+#define QT_CHECK(cond, code, msg)                     \
+  do {                                                \
+    if (!(cond)) {                                    \
+      ::qt::set_error(msg);                           \
+      return code;                                    \
+    }                                                 \
+  } while (0)
+
+#define QT_TRY(call)                                  \
+  do {                                                \
+    qt_status _s = (call);                            \
+    if (_s < 0) return _s;                            \
+  } while (0)
+
+// Device status word bits (written by kernels, read by the host on sync).
+enum : int32_t { ST_JACOBI_CAP = 1, ST_NONFINITE = 2 };
+
+}  // namespace qt
+
+// Context: device, stream and a growable workspace arena.
+struct qt_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  size_t ws_size = 0;
+  size_t ws_top = 0;
+  int32_t* status = nullptr;  // device status word
+  int jacobi_default = 30;
+};
+
+namespace qt {
+
+// Workspace arena: a bump allocator reset at the start of each entry point.
+// Growing the arena synchronizes the stream and reallocates.
+struct Arena {
+  qt_ctx ctx;
+  size_t need = 0;
+  explicit Arena(qt_ctx c) : ctx(c) { ctx->ws_top = 0; }
+};
+qt_status ws_reserve(qt_ctx ctx, size_t bytes);
+void* ws_take(qt_ctx ctx, size_t bytes);
+
+// Host-side helpers for qt_tt metadata.
+int64_t tt_slot_elems(const qt_tt* t, int k);
+qt_status tt_validate(const qt_tt* t, const char* name);
+
+}  // namespace qt

@@ -1,0 +1,53 @@
+// Host-side launchers of the qtthom kernels (internal; not part of the C ABI).
+#pragma once
+
+#include "common.h"
+
+namespace qt {
+
+// C_b = alpha * op(A_b) op(B_b) (+ C_b when accumulate), complex double,
+// row-major packed matrices whose sizes M, N, K are read from device memory.
+//   A stored M x K (conjA = false) or K x M (conjA = true, A^dagger used)
+//   B stored K x N (conjB = false) or N x K (conjB = true, B^dagger used)
+// Grid covers the capacities Mcap x Ncap; instances b = 0..batch-1 use base
+// pointers advanced by the element strides sA, sB, sC (0 broadcasts).
+void gemm(hipStream_t st, int batch, Dim M, Dim N, Dim K, int Mcap, int Ncap, bool conjA,
+          const cplx* A, int64_t sA, bool conjB, const cplx* B, int64_t sB, cplx* C, int64_t sC,
+          cplx alpha, bool accumulate);
+
+// Householder QR of the packed m x n matrix A (one workgroup per instance):
+// A = Q R with Q (m x s) and R (s x n) packed, s = min(m, n) written to s_out.
+// W is an m x n scratch matrix per instance (stride sW), tau a scratch vector.
+void qr(hipStream_t st, int batch, Dim m, Dim n, const cplx* A, int64_t sA, cplx* W, int64_t sW,
+        double* tau, int64_t sTau, cplx* Q, int64_t sQ, cplx* R, int64_t sR, int32_t* s_out,
+        int s_stride);
+
+// Truncated SVD of the packed m x c matrix A by one-sided (Hestenes) Jacobi:
+// keeps the smallest l >= 1 whose discarded tail does not exceed delta[b],
+// l <= lmax; writes V^dagger[:l] (l x c) to core, U Sigma[:, :l] (m x l) to
+// carry, l to l_out, adds the squared discarded tail to disc2[b].  Scratch:
+// B (mb x nb), V (nb x nb) per instance.  svlog (may be null) receives the
+// sorted singular values (nb entries, stride svstride).
+void svd_trunc(hipStream_t st, int batch, Dim m, Dim c, const cplx* A, int64_t sA, cplx* Bw,
+               int64_t sB, cplx* Vw, int64_t sV, cplx* core, int64_t sCore, cplx* carry,
+               int64_t sCarry, int32_t* l_out, int l_stride, const double* delta, double* disc2,
+               int lmax, int max_sweeps, int32_t* status, double* svlog, int64_t svstride,
+               int nbcap);
+
+// Frobenius norm of a packed rows x cols matrix per instance; also sets
+// delta[b] = eps * norm / sqrt(nb_bonds) (0 when nb_bonds == 0) and disc2[b] = 0.
+void norm_delta(hipStream_t st, int batch, Dim rows, Dim cols, const cplx* X, int64_t sX,
+                double* norm, double* delta, double* disc2, double eps, int nb_bonds);
+
+// dst = src for a packed block of rows*cols elements per instance.
+void copy(hipStream_t st, int batch, Dim rows, Dim cols, int64_t cap_elems, const cplx* src,
+          int64_t sS, cplx* dst, int64_t sD);
+
+// err[b] = sqrt(disc2[b]) / norm[b];  optional norm_out[b] = norm[b].
+void finalize_err(hipStream_t st, int batch, const double* disc2, const double* norm, double* err,
+                  double* norm_out);
+
+// r[b] = scale_b * value[b] for residual bookkeeping (scale from host array uploaded to dev).
+void scale_vec(hipStream_t st, int batch, const double* in, const double* scale, double* out);
+
+}  // namespace qt

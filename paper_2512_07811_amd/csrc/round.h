@@ -1,0 +1,45 @@
+// Internal interfaces shared by the entry points.
+#pragma once
+
+#include "kernels.h"
+
+namespace qt {
+
+struct RoundWs {
+  int64_t slot = 1, rr = 1, vv = 1, carry = 1, tau = 1, max_nb = 0;
+  size_t bytes = 0;
+};
+RoundWs round_ws_layout(const qt_tt* x, int lmax_cap);
+
+// left_only: orthogonalize (QR sweep) and report the norm without truncating.
+// svlog: optional [bond][instance][nb] log of sorted singular values.
+qt_status round_impl(qt_ctx ctx, qt_tt* x, const qt_round_opts* o, double* err_out,
+                     double* norm_out, bool left_only, double* svlog, int64_t svstride_bond,
+                     int64_t svstride_inst);
+qt_status hadamard_impl(qt_ctx ctx, const qt_tt* a, const qt_tt* b, qt_tt* out);
+qt_status mpo_impl(qt_ctx ctx, const qt_mpo* A, const qt_tt* x, qt_tt* out);
+qt_status add_impl(qt_ctx ctx, double are, double aim, const qt_tt* x, double bre, double bim,
+                   const qt_tt* y, qt_tt* out);
+qt_status dot_impl(qt_ctx ctx, const qt_tt* a, const qt_tt* b, double* out, bool reserve);
+
+// Host-side description of a train laid out in a caller buffer.
+struct TTLayout {
+  std::vector<int32_t> modes, cap;
+  std::vector<int64_t> off;
+  int64_t stride = 0;
+  qt_tt view(void* data, int32_t* ranks, int batch) const {
+    qt_tt t;
+    t.n = (int32_t)modes.size();
+    t.batch = batch;
+    t.modes = modes.data();
+    t.cap = cap.data();
+    t.offsets = off.data();
+    t.inst_stride = stride;
+    t.ranks = ranks;
+    t.data = data;
+    return t;
+  }
+};
+TTLayout make_layout(const std::vector<int32_t>& modes, const std::vector<int32_t>& cap);
+
+}  // namespace qt

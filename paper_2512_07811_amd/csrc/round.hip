@@ -1,0 +1,138 @@
+// TT rounding on device (Sec. 2.2 of arXiv 2512.07811):
+//   left sweep:  [Q_k, R_k] = qr(core_k as (r'_k p_k x r_{k+1})); core_{k+1} <- R_k core_{k+1}
+//   ||x|| = ||core_{n-1}||;  delta = eps ||x|| / sqrt(n-1)
+//   right sweep: SVD of core_k as (r'_k x p_k l_{k+1}); keep the smallest l whose
+//                discarded tail <= delta (cap max_rank); core_k <- V^H[:l];
+//                core_{k-1} <- core_{k-1} U[:, :l] Sigma[:l]
+// Every size is read by the kernels from device rank arrays, so the sweep is a
+// fixed launch sequence with no host synchronisation.
+#include "kernels.h"
+#include "round.h"
+
+namespace qt {
+
+__global__ void k_init_left(int n, int batch, const int32_t* ranks, int32_t* rk_left) {
+  int b = blockIdx.x;
+  if (b >= batch) return;
+  for (int k = threadIdx.x; k <= n; k += blockDim.x)
+    rk_left[(int64_t)b * (n + 1) + k] = (k == 0 || k == n) ? 1 : ranks[(int64_t)b * (n + 1) + k];
+}
+
+RoundWs round_ws_layout(const qt_tt* x, int lmax_cap) {
+  RoundWs w;
+  const int n = x->n;
+  int64_t slot = 1, rr = 1, vv = 1, carry = 1, tau = 1;
+  for (int k = 0; k < n; ++k) {
+    int64_t s = (int64_t)x->cap[k] * x->modes[k] * x->cap[k + 1];
+    slot = std::max(slot, s);
+    rr = std::max<int64_t>(rr, (int64_t)x->cap[k + 1] * x->cap[k + 1]);
+    int lnext = std::min(x->cap[k + 1], lmax_cap);
+    int64_t nb = std::min<int64_t>(x->cap[k], (int64_t)x->modes[k] * lnext);
+    vv = std::max(vv, nb * nb);
+    carry = std::max<int64_t>(carry, (int64_t)x->cap[k] * std::min(x->cap[k], lmax_cap));
+    tau = std::max<int64_t>(tau, x->cap[k + 1]);
+    w.max_nb = std::max<int64_t>(w.max_nb, nb);
+  }
+  w.slot = slot; w.rr = rr; w.vv = vv; w.carry = carry; w.tau = tau;
+  const int B = x->batch;
+  w.bytes = sizeof(cplx) * B * (3 * slot + rr + vv + carry) + sizeof(double) * B * (tau + 4) +
+            sizeof(int32_t) * B * (n + 1) + 16 * 256;
+  return w;
+}
+
+qt_status round_impl(qt_ctx ctx, qt_tt* x, const qt_round_opts* o, double* err_out,
+                     double* norm_out, bool left_only, double* svlog, int64_t svstride_bond,
+                     int64_t svstride_inst) {
+  const int n = x->n, B = x->batch;
+  hipStream_t st = ctx->stream;
+  const int lmax_cap = o->max_rank > 0 ? o->max_rank : (1 << 30);
+  RoundWs w = round_ws_layout(x, lmax_cap);
+  QT_CHECK(w.max_nb <= 1024, QT_ECAPACITY, "tt_round: SVD block above 1024 columns");
+  const int sweeps = o->jacobi_max_sweeps > 0 ? o->jacobi_max_sweeps : ctx->jacobi_default;
+  cplx* scratch = (cplx*)ws_take(ctx, sizeof(cplx) * B * w.slot);
+  cplx* Wq = (cplx*)ws_take(ctx, sizeof(cplx) * B * w.slot);
+  cplx* Bsv = (cplx*)ws_take(ctx, sizeof(cplx) * B * w.slot);
+  cplx* Rb = (cplx*)ws_take(ctx, sizeof(cplx) * B * w.rr);
+  cplx* Vb = (cplx*)ws_take(ctx, sizeof(cplx) * B * w.vv);
+  cplx* Cb = (cplx*)ws_take(ctx, sizeof(cplx) * B * w.carry);
+  double* tau = (double*)ws_take(ctx, sizeof(double) * B * w.tau);
+  double* norm = (double*)ws_take(ctx, sizeof(double) * B);
+  double* delta = (double*)ws_take(ctx, sizeof(double) * B);
+  double* disc2 = (double*)ws_take(ctx, sizeof(double) * B);
+  int32_t* rkl = (int32_t*)ws_take(ctx, sizeof(int32_t) * B * (n + 1));
+  QT_CHECK(scratch && Wq && Bsv && Rb && Vb && Cb && tau && norm && delta && disc2 && rkl,
+           QT_ENOMEM, "tt_round: workspace too small");
+  cplx* X = (cplx*)x->data;
+  const int64_t sX = x->inst_stride;
+  const int rs = n + 1;
+  int32_t* rk = x->ranks;
+  const cplx one = make_double2(1.0, 0.0);
+
+  if (n == 1) {
+    norm_delta(st, B, dconst(1), dconst(x->modes[0]), X + x->offsets[0], sX, norm, delta, disc2,
+               0.0, 0);
+    finalize_err(st, B, disc2, norm, err_out, norm_out);
+    QT_HIP(hipGetLastError());
+    return QT_OK;
+  }
+  k_init_left<<<B, 64, 0, st>>>(n, B, rk, rkl);
+  // ---- left orthogonalization sweep
+  for (int k = 0; k < n - 1; ++k) {
+    const int p = x->modes[k];
+    const cplx* in = (k == 0) ? X + x->offsets[0] : scratch;
+    const int64_t sin = (k == 0) ? sX : w.slot;
+    qr(st, B, dref(rkl + k, rs, p), dref(rk + k + 1, rs), in, sin, Wq, w.slot, tau, w.tau,
+       X + x->offsets[k], sX, Rb, w.rr, rkl + k + 1, rs);
+    const int p1 = x->modes[k + 1];
+    // scratch (s x p1 r_{k+2}) = R (s x r_{k+1}) * core_{k+1} (r_{k+1} x p1 r_{k+2})
+    gemm(st, B, dref(rkl + k + 1, rs), dref(rk + k + 2, rs, p1), dref(rk + k + 1, rs),
+         x->cap[k + 1], p1 * x->cap[k + 2], false, Rb, w.rr, false, X + x->offsets[k + 1], sX,
+         scratch, w.slot, one, false);
+  }
+  // the last core (r'_{n-1} x p_{n-1}) is in scratch: ||x|| and delta
+  norm_delta(st, B, dref(rkl + n - 1, rs), dconst(x->modes[n - 1]), scratch, w.slot, norm, delta,
+             disc2, o->eps, n - 1);
+  if (left_only) {
+    // keep the orthogonalized train: copy the centre back and publish left ranks
+    copy(st, B, dref(rkl + n - 1, rs), dconst(x->modes[n - 1]),
+         (int64_t)x->cap[n - 1] * x->modes[n - 1], scratch, w.slot, X + x->offsets[n - 1], sX);
+    QT_HIP(hipMemcpyAsync(rk, rkl, sizeof(int32_t) * B * (n + 1), hipMemcpyDeviceToDevice, st));
+    finalize_err(st, B, disc2, norm, err_out, norm_out);
+    QT_HIP(hipGetLastError());
+    return QT_OK;
+  }
+  // ---- right truncation sweep
+  for (int k = n - 1; k >= 1; --k) {
+    const int p = x->modes[k];
+    const int lmax = std::min(lmax_cap, x->cap[k]);
+    svd_trunc(st, B, dref(rkl + k, rs), dref(rk + k + 1, rs, p), scratch, w.slot, Bsv, w.slot, Vb,
+              w.vv, X + x->offsets[k], sX, Cb, w.carry, rk + k, rs, delta, disc2, lmax, sweeps,
+              ctx->status, svlog ? svlog + k * svstride_bond : nullptr, svstride_inst,
+              (int)w.max_nb);
+    const int pp = x->modes[k - 1];
+    // scratch (r'_{k-1} p x l_k) = core_{k-1} (r'_{k-1} p x r'_k) * carry (r'_k x l_k)
+    gemm(st, B, dref(rkl + k - 1, rs, pp), dref(rk + k, rs), dref(rkl + k, rs),
+         x->cap[k - 1] * pp, x->cap[k], false, X + x->offsets[k - 1], sX, false, Cb, w.carry,
+         scratch, w.slot, one, false);
+  }
+  copy(st, B, dconst(x->modes[0]), dref(rk + 1, rs), (int64_t)x->modes[0] * x->cap[1], scratch,
+       w.slot, X + x->offsets[0], sX);
+  finalize_err(st, B, disc2, norm, err_out, norm_out);
+  QT_HIP(hipGetLastError());
+  return QT_OK;
+}
+
+}  // namespace qt
+
+extern "C" qt_status tt_round(qt_ctx ctx, qt_tt* x, const qt_round_opts* opts, double* err_out,
+                              double* norm_out) {
+  QT_CHECK(ctx && x && opts, QT_EINVAL, "tt_round: null argument");
+  QT_TRY(qt::tt_validate(x, "x"));
+  QT_CHECK(opts->eps >= 0.0, QT_EINVAL, "tt_round: eps < 0");
+  QT_CHECK(opts->mode == QT_ROUND_SVD, QT_EINVAL,
+           "tt_round: only QT_ROUND_SVD applies to a materialized train");
+  ctx->ws_top = 0;
+  const int lmax_cap = opts->max_rank > 0 ? opts->max_rank : (1 << 30);
+  QT_TRY(qt::ws_reserve(ctx, qt::round_ws_layout(x, lmax_cap).bytes));
+  return qt::round_impl(ctx, x, opts, err_out, norm_out, false, nullptr, 0, 0);
+}

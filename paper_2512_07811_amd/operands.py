@@ -1,0 +1,247 @@
+"""Host-side set-up of the operands of Algorithm 2 (not on the hot path).
+
+Builds, once per problem, the trains that the HIP iteration consumes:
+  * k' = k - k0 in the binary (QTT) discretization of eq. (binary_discretization),
+    grid bits of x, then y, then z, most significant first, with an all-ones
+    component core in front (Sec. 3.2 of arXiv 2512.07811);
+  * the SFFT operator Q_L (the QFT without its final bit-reversal, Sec. 3.2)
+    assembled from its gate structure: every output bit m picks up the phase
+    exp(-2 pi i k'_m j_m' 2^(m-1-m')) from each input bit m' >= m, i.e. one
+    Hadamard-type factor per qubit and one controlled phase per pair; each
+    factor is an exact rank <= 2 operator train, they are multiplied
+    elementwise and recompressed as the product grows;
+  * the Green operator Gamma_0(q) = q q^T/(k0 |q|^2) sampled in the SFFT's
+    momentum convention (each axis' bit order reversed), compressed to a
+    train with a 3 x 3 component core and diagonal spatial cores;
+  * the rank-1 mean field E and the selector trains k * e_c used for A_eff.
+Compression uses its own host TT-SVD (QR of the long side, SVD of the small
+factor), independent of the test oracle.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+# ------------------------------------------------------------- host TT kit
+
+def _keep(s, delta, rmax=None):
+    """Smallest l >= 1 whose discarded tail sqrt(sum_{j>=l} s_j^2) <= delta."""
+    tail = np.sqrt(np.cumsum((s ** 2)[::-1]))[::-1]
+    ok = np.nonzero(tail <= delta)[0]
+    l = int(ok[0]) if ok.size else len(s)
+    l = max(l, 1)
+    return min(l, rmax) if rmax else l
+
+
+def _svd_wide(M):
+    """Thin SVD of a matrix with few rows, through a QR of its transpose."""
+    r, c = M.shape
+    if c <= 2 * r:
+        return np.linalg.svd(M, full_matrices=False)
+    Q, R = np.linalg.qr(M.T)                 # M^T = Q R   (c x r) (r x r)
+    U, s, Wt = np.linalg.svd(R.T)            # M = R^T Q^T = U s Wt Q^T
+    return U, s, Wt @ Q.T
+
+
+def ttsvd(a, modes, eps, rmax=None):
+    """Train of a dense array by successive truncated SVDs (threshold eps*||a||/sqrt(n-1))."""
+    n = len(modes)
+    rest = np.asarray(a).reshape(-1)
+    delta = eps * np.linalg.norm(rest) / math.sqrt(max(n - 1, 1))
+    cores, r = [], 1
+    for k in range(n - 1):
+        U, s, Vt = _svd_wide(rest.reshape(r * modes[k], -1))
+        l = _keep(s, delta, rmax)
+        cores.append(U[:, :l].reshape(r, modes[k], l))
+        rest = s[:l, None] * Vt[:l]
+        r = l
+    cores.append(rest.reshape(r, modes[-1], 1))
+    return cores
+
+
+def compress(cores, eps, rmax=None):
+    """Host rounding: right-to-left LQ orthogonalization, then left-to-right SVD truncation."""
+    cs = [np.array(c) for c in cores]
+    n = len(cs)
+    for k in range(n - 1, 0, -1):
+        r, p, r2 = cs[k].shape
+        Q, R = np.linalg.qr(cs[k].reshape(r, p * r2).T)       # core^T = Q R
+        s = Q.shape[1]
+        cs[k] = Q.T.reshape(s, p, r2)
+        cs[k - 1] = np.tensordot(cs[k - 1], R.T, axes=(2, 0))
+    nrm = np.linalg.norm(cs[0])
+    delta = eps * nrm / math.sqrt(max(n - 1, 1))
+    for k in range(n - 1):
+        r, p, r2 = cs[k].shape
+        U, s, Vt = np.linalg.svd(cs[k].reshape(r * p, r2), full_matrices=False)
+        l = _keep(s, delta, rmax)
+        cs[k] = U[:, :l].reshape(r, p, l)
+        cs[k + 1] = np.tensordot(s[:l, None] * Vt[:l], cs[k + 1], axes=(1, 0))
+    return cs
+
+
+def elementwise(x, y):
+    """Elementwise product of two trains with equal modes (Kronecker of slices)."""
+    out = []
+    for a, b in zip(x, y):
+        ra, p, ra2 = a.shape
+        rb, _, rb2 = b.shape
+        c = (a[:, None, :, :, None] * b[None, :, :, None, :]).reshape(ra * rb, p, ra2 * rb2)
+        out.append(c)
+    return out
+
+
+# --------------------------------------------------------------- geometry
+
+def bit_reversal(L):
+    idx = np.arange(2 ** L)
+    rev = np.zeros_like(idx)
+    for b in range(L):
+        rev = (rev << 1) | ((idx >> b) & 1)
+    return rev
+
+
+def signed_freq(N):
+    k = np.arange(N)
+    return np.where(k < N // 2, k, k - N).astype(np.float64)
+
+
+# ------------------------------------------------------------------ SFFT
+
+def sfft_1d(L, eps=1e-13):
+    """Q_L as (r, 2, 2, r') cores, built from its per-qubit and per-pair phase factors.
+
+    Merged physical index (k'_c, j_c) -> 2*k'_c + j_c; the output position
+    k' holds frequency rev(k').
+    """
+    ones = [np.ones((1, 4, 1), dtype=np.complex128) for _ in range(L)]
+    kk = np.array([0, 0, 1, 1])
+    jj = np.array([0, 1, 0, 1])
+    train = [c.copy() for c in ones]
+    for m in range(L):
+        # qubit factor: (-1)^(k'_m j_m) / sqrt(2)
+        g = [c.copy() for c in ones]
+        g[m] = (np.where(kk * jj == 1, -1.0, 1.0) / math.sqrt(2.0)).astype(np.complex128).reshape(1, 4, 1)
+        train = elementwise(train, g)
+        for mp in range(m + 1, L):
+            # controlled phase between output bit m and input bit mp
+            ang = -2.0 * math.pi * 2.0 ** (m - mp - 1)
+            g = [c.copy() for c in ones]
+            first = np.zeros((1, 4, 2), dtype=np.complex128)
+            first[0, kk == 0, 0] = 1.0
+            first[0, kk == 1, 1] = 1.0
+            g[m] = first
+            for c in range(m + 1, mp):
+                mid = np.zeros((2, 4, 2), dtype=np.complex128)
+                mid[0, :, 0] = 1.0
+                mid[1, :, 1] = 1.0
+                g[c] = mid
+            last = np.zeros((2, 4, 1), dtype=np.complex128)
+            last[0, :, 0] = 1.0
+            last[1, :, 0] = np.exp(1j * ang * jj)
+            g[mp] = last
+            train = compress(elementwise(train, g), eps * 1e-2)
+    train = compress(train, eps)
+    return [c.reshape(c.shape[0], 2, 2, c.shape[2]) for c in train]
+
+
+def sfft_3d(L, eps=1e-13):
+    """Identity on the component core, Q_L on each axis group; and its adjoint."""
+    one = sfft_1d(L, eps)
+    eye3 = np.eye(3, dtype=np.complex128).reshape(1, 3, 3, 1)
+    S = [eye3] + [c.copy() for _ in range(3) for c in one]
+    Sinv = [np.conj(np.transpose(c, (0, 2, 1, 3))) for c in S]
+    return S, Sinv
+
+
+# ------------------------------------------------------------------ Green
+
+def green_momentum_dense(L, k0):
+    """Gamma[a, b, x', y', z'] where position x' along an axis holds frequency rev(x')."""
+    N = 2 ** L
+    f = signed_freq(N)[bit_reversal(L)]
+    q = [f[:, None, None], f[None, :, None], f[None, None, :]]
+    q2 = q[0] ** 2 + q[1] ** 2 + q[2] ** 2
+    bad = (q2 == 0) | (q[0] == -N // 2) | (q[1] == -N // 2) | (q[2] == -N // 2)
+    inv = np.where(bad, 0.0, 1.0 / np.where(q2 == 0, 1.0, q2)) / k0
+    G = np.empty((3, 3, N, N, N))
+    for a in range(3):
+        for b in range(a, 3):
+            G[a, b] = q[a] * q[b] * inv
+            if b != a:
+                G[b, a] = G[a, b]
+    return G
+
+
+def green_tt(L, k0, eps=1e-10):
+    """Green operator: component core (1, 3, 3, r) and diagonal spatial cores (r, 2, r')."""
+    G = green_momentum_dense(L, k0)
+    cores = ttsvd(G.reshape(-1), [9] + [2] * (3 * L), eps)
+    ctrl = cores[0].reshape(1, 3, 3, cores[0].shape[2])
+    return [ctrl.astype(np.complex128)] + [c.astype(np.complex128) for c in cores[1:]]
+
+
+# ------------------------------------------------------- material, loads
+
+def material_tt(kvox, shift=0.0, eps=1e-10):
+    """Spatial train of (k - shift) on an N^3 grid (x bits, y bits, z bits, MSB first)."""
+    N = kvox.shape[0]
+    L = int(round(math.log2(N)))
+    return ttsvd(np.asarray(kvox, dtype=np.float64) - shift, [2] * (3 * L), eps)
+
+
+def material_tt_z_invariant(section, shift=0.0, eps=1e-10):
+    """k(x, y, z) = section(x, y): train of the section followed by all-ones z cores."""
+    N = section.shape[0]
+    L = int(round(math.log2(N)))
+    sp = ttsvd(np.asarray(section, dtype=np.float64) - shift, [2] * (2 * L), eps)
+    return sp + [np.ones((1, 2, 1)) for _ in range(L)]
+
+
+def with_component_core(spatial, control):
+    """Prepend a (1, 3, 1) component core to a spatial train (complex cores)."""
+    return [np.asarray(control, dtype=np.complex128).reshape(1, 3, 1)] + \
+        [c.astype(np.complex128) for c in spatial]
+
+
+def mean_field(E, L):
+    return with_component_core([np.ones((1, 2, 1)) for _ in range(3 * L)], E)
+
+
+def build_problem(kvox=None, k0=None, L=None, section=None, op_eps=1e-10, sfft_eps=1e-13):
+    """All host trains of one cell problem (k given as N^3 voxels or a z-invariant section)."""
+    if kvox is not None:
+        sp_k = material_tt(kvox, 0.0, op_eps)
+        sp_kp = material_tt(kvox, k0, op_eps)
+        L = int(round(math.log2(kvox.shape[0])))
+    else:
+        sp_k = material_tt_z_invariant(section, 0.0, op_eps)
+        sp_kp = material_tt_z_invariant(section, k0, op_eps)
+        L = int(round(math.log2(section.shape[0])))
+    kp = with_component_core(sp_kp, np.ones(3))
+    ksel = [with_component_core(sp_k, np.eye(3)[c]) for c in range(3)]
+    S, Sinv = sfft_3d(L, sfft_eps)
+    G = green_tt(L, k0, op_eps)
+    return {"L": L, "kp": kp, "k_sel": ksel, "S": S, "Sinv": Sinv, "G": G}
+
+
+def upload(prob, loads, max_rank, device=0):
+    """Device operands for a batch of loads (rows of `loads`) plus an empty field batch."""
+    from . import qtt
+    L = prob["L"]
+    B = len(loads)
+    kp = qtt.DeviceTT.from_cores(prob["kp"], device=device)
+    S = qtt.DeviceMPO.from_cores(prob["S"], device=device)
+    Sinv = qtt.DeviceMPO.from_cores(prob["Sinv"], device=device)
+    n = 3 * L + 1
+    G = qtt.DeviceMPO.from_cores(prob["G"], [0] + [1] * (n - 1), device=device)
+    E = qtt.DeviceTT.from_cores([mean_field(np.asarray(Ej, dtype=float), L) for Ej in loads],
+                                device=device)
+    ksel = [qtt.DeviceTT.from_cores(c, device=device) for c in prob["k_sel"]]
+    E_norm = np.array([np.linalg.norm(Ej) for Ej in loads], dtype=np.float64)
+    ops = qtt.DeviceOperands(L, kp, S, Sinv, G, E, E_norm, ksel)
+    modes, cap = qtt.field_capacity(L, max_rank)
+    e = qtt.DeviceTT.empty(modes, cap, B, device)
+    return ops, e

@@ -1,0 +1,387 @@
+"""Thin Python binding of libqtthom.so (argument marshalling only).
+
+Every computation runs in the HIP library; this module only moves cores
+between numpy and PyTorch device tensors, fills the C descriptors and calls the
+C ABI declared in include/qtthom.h.  There is no CPU fallback: loading fails
+loudly when the library or a GPU is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqtthom.so")
+
+QT_OK, QT_NOT_CONVERGED = 0, 1
+ROUND_SVD, ROUND_SKETCH, ROUND_LEARNED = 0, 1, 2
+PREC_F64, PREC_F32 = 0, 1
+
+EXPORTS = ["qt_ctx_create", "qt_ctx_destroy", "qt_last_error", "qt_ctx_sync", "tt_hadamard",
+           "tt_mpo_apply", "tt_add", "tt_round", "tt_dot", "ls_iterate", "homogenize"]
+
+
+class QtError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"qtthom status {status}: {msg}")
+        self.status = status
+
+
+class TTDesc(C.Structure):
+    _fields_ = [("n", C.c_int32), ("batch", C.c_int32), ("modes", C.POINTER(C.c_int32)),
+                ("cap", C.POINTER(C.c_int32)), ("offsets", C.POINTER(C.c_int64)),
+                ("inst_stride", C.c_int64), ("ranks", C.c_void_p), ("data", C.c_void_p)]
+
+
+class MPODesc(C.Structure):
+    _fields_ = [("n", C.c_int32), ("modes_out", C.POINTER(C.c_int32)),
+                ("modes_in", C.POINTER(C.c_int32)), ("ranks", C.POINTER(C.c_int32)),
+                ("diag", C.POINTER(C.c_int32)), ("offsets", C.POINTER(C.c_int64)),
+                ("data", C.c_void_p)]
+
+
+class RoundOpts(C.Structure):
+    _fields_ = [("eps", C.c_double), ("max_rank", C.c_int32), ("mode", C.c_int32),
+                ("jacobi_max_sweeps", C.c_int32), ("precision", C.c_int32),
+                ("oversample", C.c_int32), ("seed", C.c_uint64)]
+
+
+class Operands(C.Structure):
+    _fields_ = [("L", C.c_int32), ("kp", TTDesc), ("S", MPODesc), ("Sinv", MPODesc),
+                ("G", MPODesc), ("E", TTDesc), ("E_norm", C.POINTER(C.c_double))]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("round", RoundOpts), ("tol", C.c_double), ("max_iter", C.c_int32)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libqtthom.so; raises if it is missing (no fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: run __graft_entry__.build() first")
+    lib = C.CDLL(path)
+    vp, i32, dbl = C.c_void_p, C.c_int32, C.c_double
+    lib.qt_ctx_create.argtypes = [C.c_int, vp, C.c_size_t, C.POINTER(vp)]
+    lib.qt_ctx_destroy.argtypes = [vp]
+    lib.qt_ctx_destroy.restype = None
+    lib.qt_last_error.restype = C.c_char_p
+    lib.qt_ctx_sync.argtypes = [vp]
+    lib.tt_hadamard.argtypes = [vp, C.POINTER(TTDesc), C.POINTER(TTDesc), C.POINTER(TTDesc)]
+    lib.tt_mpo_apply.argtypes = [vp, C.POINTER(MPODesc), C.POINTER(TTDesc), C.POINTER(TTDesc)]
+    lib.tt_add.argtypes = [vp, dbl, dbl, C.POINTER(TTDesc), dbl, dbl, C.POINTER(TTDesc),
+                           C.POINTER(TTDesc)]
+    lib.tt_round.argtypes = [vp, C.POINTER(TTDesc), C.POINTER(RoundOpts), vp, vp]
+    lib.tt_dot.argtypes = [vp, C.POINTER(TTDesc), C.POINTER(TTDesc), vp]
+    lib.ls_iterate.argtypes = [vp, C.POINTER(Operands), C.POINTER(TTDesc), C.POINTER(SolveOpts),
+                               i32, vp]
+    lib.homogenize.argtypes = [vp, C.POINTER(Operands), C.POINTER(TTDesc), C.POINTER(TTDesc),
+                               C.POINTER(SolveOpts), C.POINTER(C.c_double), C.POINTER(C.c_int32),
+                               C.POINTER(C.c_double)]
+    for name in EXPORTS:
+        if name not in ("qt_ctx_destroy", "qt_last_error"):
+            getattr(lib, name).restype = C.c_int32
+    _lib = lib
+    return lib
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("qtthom needs a HIP device (torch.cuda.is_available() is False)")
+    return torch
+
+
+def _check(status):
+    if status < 0:
+        raise QtError(status, load_library().qt_last_error().decode())
+    return status
+
+
+def _i32(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+
+
+def _i64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int64))
+
+
+def _p32(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def _p64(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int64))
+
+
+class Context:
+    """A library context bound to torch's current stream on `device`."""
+
+    def __init__(self, device: int = 0, ws_bytes: int = 0):
+        torch = _torch()
+        self.lib = load_library()
+        self.device = device
+        torch.cuda.set_device(device)
+        self.stream = torch.cuda.current_stream(device)
+        h = C.c_void_p()
+        _check(self.lib.qt_ctx_create(device, C.c_void_p(self.stream.cuda_stream), ws_bytes,
+                                      C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.qt_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sync(self):
+        _check(self.lib.qt_ctx_sync(self.h))
+
+
+def natural_caps(modes):
+    n = len(modes)
+    nat = [1] * (n + 1)
+    for k in range(1, n):
+        nat[k] = int(min(np.prod(modes[:k], dtype=float), np.prod(modes[k:], dtype=float), 2 ** 30))
+    return nat
+
+
+@dataclass
+class DeviceTT:
+    """A batch of trains in device memory with fixed rank capacities."""
+    modes: np.ndarray
+    cap: np.ndarray
+    offsets: np.ndarray
+    stride: int
+    batch: int
+    data: object          # torch complex128 tensor [batch * stride]
+    ranks: object         # torch int32 tensor [batch, n+1]
+    _desc: TTDesc = field(default=None, repr=False)
+
+    @property
+    def n(self):
+        return len(self.modes)
+
+    @staticmethod
+    def empty(modes, cap, batch: int = 1, device: int = 0):
+        torch = _torch()
+        modes = _i32(modes)
+        cap = _i32(cap)
+        off = []
+        o = 0
+        for k in range(len(modes)):
+            off.append(o)
+            s = int(cap[k]) * int(modes[k]) * int(cap[k + 1])
+            o += (s + 31) & ~31
+        stride = max(o, 1)
+        data = torch.zeros(batch * stride, dtype=torch.complex128, device=f"cuda:{device}")
+        ranks = torch.ones((batch, len(modes) + 1), dtype=torch.int32, device=f"cuda:{device}")
+        return DeviceTT(modes, cap, _i64(off), stride, batch, data, ranks)
+
+    @staticmethod
+    def from_cores(cores_list, cap=None, device: int = 0):
+        """cores_list: one list of cores per instance (all with equal modes)."""
+        torch = _torch()
+        if cores_list and not isinstance(cores_list[0], (list, tuple)):
+            cores_list = [cores_list]
+        modes = [c.shape[1] for c in cores_list[0]]
+        n = len(modes)
+        rk = np.array([[c.shape[0] for c in cs] + [1] for cs in cores_list], dtype=np.int32)
+        if cap is None:
+            cap = rk.max(axis=0)
+        cap = _i32(cap)
+        if np.any(rk > cap[None, :]):
+            raise ValueError("ranks exceed capacities")
+        t = DeviceTT.empty(modes, cap, len(cores_list), device)
+        host = np.zeros(t.batch * t.stride, dtype=np.complex128)
+        for b, cs in enumerate(cores_list):
+            for k, c in enumerate(cs):
+                o = b * t.stride + int(t.offsets[k])
+                host[o:o + c.size] = np.ascontiguousarray(c, dtype=np.complex128).reshape(-1)
+        t.data.copy_(torch.from_numpy(host))
+        t.ranks.copy_(torch.from_numpy(rk))
+        return t
+
+    def desc(self) -> TTDesc:
+        d = TTDesc(self.n, self.batch, _p32(self.modes), _p32(self.cap), _p64(self.offsets),
+                   self.stride, C.c_void_p(self.ranks.data_ptr()), C.c_void_p(self.data.data_ptr()))
+        self._desc = d
+        return d
+
+    def rank_array(self):
+        return self.ranks.cpu().numpy()
+
+    def to_cores(self):
+        rk = self.rank_array()
+        host = self.data.cpu().numpy()
+        out = []
+        for b in range(self.batch):
+            cs = []
+            for k in range(self.n):
+                r0, r1, p = int(rk[b, k]), int(rk[b, k + 1]), int(self.modes[k])
+                o = b * self.stride + int(self.offsets[k])
+                cs.append(host[o:o + r0 * p * r1].reshape(r0, p, r1).copy())
+            out.append(cs)
+        return out
+
+
+@dataclass
+class DeviceMPO:
+    modes_out: np.ndarray
+    modes_in: np.ndarray
+    ranks: np.ndarray
+    diag: np.ndarray
+    offsets: np.ndarray
+    data: object
+    _desc: MPODesc = field(default=None, repr=False)
+
+    @property
+    def n(self):
+        return len(self.ranks) - 1
+
+    @staticmethod
+    def from_cores(cores, diag_flags=None, device: int = 0):
+        """cores: (r, p_out, p_in, r') arrays, or (r, p, r') where diag_flags[k] is set."""
+        torch = _torch()
+        n = len(cores)
+        diag_flags = [0] * n if diag_flags is None else [int(d) for d in diag_flags]
+        mo, mi, rk, off = [], [], [], []
+        o = 0
+        for c, d in zip(cores, diag_flags):
+            if d:
+                mo.append(c.shape[1]); mi.append(c.shape[1])
+            else:
+                mo.append(c.shape[1]); mi.append(c.shape[2])
+            rk.append(c.shape[0])
+            off.append(o)
+            o += (c.size + 31) & ~31
+        rk.append(cores[-1].shape[-1])
+        host = np.zeros(max(o, 1), dtype=np.complex128)
+        for c, s in zip(cores, off):
+            host[s:s + c.size] = np.ascontiguousarray(c, dtype=np.complex128).reshape(-1)
+        data = torch.from_numpy(host).to(f"cuda:{device}")
+        return DeviceMPO(_i32(mo), _i32(mi), _i32(rk), _i32(diag_flags), _i64(off), data)
+
+    def desc(self) -> MPODesc:
+        d = MPODesc(self.n, _p32(self.modes_out), _p32(self.modes_in), _p32(self.ranks),
+                    _p32(self.diag), _p64(self.offsets), C.c_void_p(self.data.data_ptr()))
+        self._desc = d
+        return d
+
+
+def round_opts(eps=0.0, max_rank=0, mode=ROUND_SVD, jacobi_max_sweeps=0, precision=PREC_F64,
+               oversample=0, seed=0):
+    return RoundOpts(eps, max_rank, mode, jacobi_max_sweeps, precision, oversample, seed)
+
+
+# ------------------------------------------------------------- entry points
+
+def tt_hadamard(ctx: Context, a: DeviceTT, b: DeviceTT, out: DeviceTT = None) -> DeviceTT:
+    if out is None:
+        out = DeviceTT.empty(b.modes, a.cap * b.cap, b.batch, ctx.device)
+    _check(ctx.lib.tt_hadamard(ctx.h, C.byref(a.desc()), C.byref(b.desc()), C.byref(out.desc())))
+    return out
+
+
+def tt_mpo_apply(ctx: Context, A: DeviceMPO, x: DeviceTT, out: DeviceTT = None) -> DeviceTT:
+    if out is None:
+        out = DeviceTT.empty(A.modes_out, A.ranks * x.cap, x.batch, ctx.device)
+    _check(ctx.lib.tt_mpo_apply(ctx.h, C.byref(A.desc()), C.byref(x.desc()), C.byref(out.desc())))
+    return out
+
+
+def tt_add(ctx: Context, alpha, x: DeviceTT, beta, y: DeviceTT, out: DeviceTT = None) -> DeviceTT:
+    if out is None:
+        cap = x.cap + y.cap
+        cap[0] = cap[-1] = 1
+        out = DeviceTT.empty(x.modes, cap, x.batch, ctx.device)
+    alpha, beta = complex(alpha), complex(beta)
+    _check(ctx.lib.tt_add(ctx.h, alpha.real, alpha.imag, C.byref(x.desc()), beta.real, beta.imag,
+                          C.byref(y.desc()), C.byref(out.desc())))
+    return out
+
+
+def tt_round(ctx: Context, x: DeviceTT, eps: float, max_rank: int = 0, **kw):
+    """In-place rounding; returns (err, norm) as device tensors of shape [batch]."""
+    torch = _torch()
+    err = torch.zeros(x.batch, dtype=torch.float64, device=x.data.device)
+    nrm = torch.zeros(x.batch, dtype=torch.float64, device=x.data.device)
+    o = round_opts(eps, max_rank, **kw)
+    _check(ctx.lib.tt_round(ctx.h, C.byref(x.desc()), C.byref(o), C.c_void_p(err.data_ptr()),
+                            C.c_void_p(nrm.data_ptr())))
+    return err, nrm
+
+
+def tt_dot(ctx: Context, a: DeviceTT, b: DeviceTT):
+    """sum conj(a) b per instance, as a complex128 device tensor [batch]."""
+    torch = _torch()
+    out = torch.zeros(2 * b.batch, dtype=torch.float64, device=b.data.device)
+    _check(ctx.lib.tt_dot(ctx.h, C.byref(a.desc()), C.byref(b.desc()), C.c_void_p(out.data_ptr())))
+    return torch.view_as_complex(out.view(b.batch, 2))
+
+
+@dataclass
+class DeviceOperands:
+    L: int
+    kp: DeviceTT
+    S: DeviceMPO
+    Sinv: DeviceMPO
+    G: DeviceMPO
+    E: DeviceTT
+    E_norm: np.ndarray
+    k_sel: list
+    _struct: Operands = field(default=None, repr=False)
+
+    def struct(self) -> Operands:
+        s = Operands(self.L, self.kp.desc(), self.S.desc(), self.Sinv.desc(), self.G.desc(),
+                     self.E.desc(), self.E_norm.ctypes.data_as(C.POINTER(C.c_double)))
+        self._struct = s
+        return s
+
+
+def field_capacity(L: int, max_rank: int):
+    modes = [3] + [2] * (3 * L)
+    nat = natural_caps(modes)
+    return modes, [min(r, max_rank) if max_rank > 0 else r for r in nat]
+
+
+def solve_opts(eps, max_rank, tol=1e-8, max_iter=200, mode=ROUND_SVD, **kw):
+    return SolveOpts(round_opts(eps, max_rank, mode, **kw), tol, max_iter)
+
+
+def ls_iterate(ctx: Context, ops: DeviceOperands, e: DeviceTT, opts: SolveOpts, n_iter: int):
+    torch = _torch()
+    res = torch.zeros(max(n_iter, 1) * e.batch, dtype=torch.float64, device=e.data.device)
+    st = ops.struct()
+    _check(ctx.lib.ls_iterate(ctx.h, C.byref(st), C.byref(e.desc()), C.byref(opts), n_iter,
+                              C.c_void_p(res.data_ptr())))
+    return res.view(-1, e.batch)[:n_iter]
+
+
+def homogenize(ctx: Context, ops: DeviceOperands, e: DeviceTT, opts: SolveOpts):
+    """Returns (A_eff columns [batch, 3], iterations [batch], residuals [max_iter, batch], status)."""
+    B = e.batch
+    A = np.zeros((B, 3))
+    its = np.zeros(B, dtype=np.int32)
+    res = np.full((opts.max_iter, B), np.nan)
+    ksel = (TTDesc * 3)(*[t.desc() for t in ops.k_sel])
+    st = ops.struct()
+    s = _check(ctx.lib.homogenize(ctx.h, C.byref(st), ksel, C.byref(e.desc()), C.byref(opts),
+                                  A.ctypes.data_as(C.POINTER(C.c_double)),
+                                  its.ctypes.data_as(C.POINTER(C.c_int32)),
+                                  res.ctypes.data_as(C.POINTER(C.c_double))))
+    return A, its, res, s

@@ -1,0 +1,173 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Gauge-invariant comparisons only: dense reconstructions, ranks, norms, dot
+products and reported errors (TT cores are unique only up to gauge).
+FP64 bar: relative error <= 1e-10 (per operation the kernels reach ~1e-13).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import ls_tt
+from oracle import ops as O
+from oracle import tt as T
+from paper_2512_07811_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def q():
+    from paper_2512_07811_amd import qtt
+    return qtt
+
+
+@pytest.fixture(scope="module")
+def ctx(q):
+    c = q.Context(0)
+    yield c
+    c.close()
+
+
+def rel(a, b):
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-300)
+
+
+def ragged_pair(modes, seed):
+    n = len(modes)
+    nat = [1] + [min(int(np.prod(modes[:k])), int(np.prod(modes[k:]))) for k in range(1, n)] + [1]
+    g = I.rng(seed)
+    r1 = [1] + [int(min(nat[k], g.integers(1, 7))) for k in range(1, n)] + [1]
+    r2 = [1] + [int(min(nat[k], g.integers(1, 7))) for k in range(1, n)] + [1]
+    return r1, r2
+
+
+def test_hadamard_mpo_add_dot(q, ctx):
+    modes = [3, 2, 2, 2, 2, 2, 2]
+    r1, r2 = ragged_pair(modes, 1)
+    xs = [I.random_tt(modes, r1, seed=10 + b) for b in range(2)]
+    ys = [I.random_tt(modes, r2, seed=20 + b) for b in range(2)]
+    cap = [1] + [7] * (len(modes) - 1) + [1]
+    X = q.DeviceTT.from_cores(xs, cap)
+    Y = q.DeviceTT.from_cores(ys, cap)
+    # Hadamard (batched)
+    H = q.tt_hadamard(ctx, X, Y)
+    out = H.to_cores()
+    for b in range(2):
+        ref = T.hadamard(xs[b], ys[b])
+        assert T.ranks(out[b]) == T.ranks(ref)
+        assert rel(T.full(out[b]), T.full(ref)) < 1e-13
+    # broadcast of a single train over the batch
+    X1 = q.DeviceTT.from_cores([xs[0]], cap)
+    H1 = q.tt_hadamard(ctx, X1, Y).to_cores()
+    assert rel(T.full(H1[1]), T.full(T.hadamard(xs[0], ys[1]))) < 1e-13
+    # general and diagonal operators
+    A = I.random_mpo(modes, modes, [1, 2, 3, 2, 3, 2, 2, 1], seed=30)
+    Ad = q.DeviceMPO.from_cores(A)
+    Z = q.tt_mpo_apply(ctx, Ad, X).to_cores()
+    for b in range(2):
+        assert rel(T.full(Z[b]), T.full(T.mpo_apply(A, xs[b]))) < 1e-13
+    dcores = I.random_tt(modes, [1, 2, 2, 3, 2, 2, 2, 1], seed=31)
+    Dd = q.DeviceMPO.from_cores(dcores, [1] * len(modes))
+    Zd = q.tt_mpo_apply(ctx, Dd, X).to_cores()
+    assert rel(T.full(Zd[0]), T.full(xs[0]) * T.full(dcores)) < 1e-13
+    # scaled addition
+    S = q.tt_add(ctx, 0.5 - 1j, X, 2.0, Y).to_cores()
+    for b in range(2):
+        assert rel(T.full(S[b]), (0.5 - 1j) * T.full(xs[b]) + 2.0 * T.full(ys[b])) < 1e-13
+    # dot
+    d = q.tt_dot(ctx, X, Y).cpu().numpy()
+    for b in range(2):
+        ref = np.vdot(T.full(xs[b]), T.full(ys[b]))
+        assert abs(d[b] - ref) < 1e-12 * abs(ref) + 1e-14
+
+
+@pytest.mark.parametrize("eps,rmax", [(0.0, 0), (1e-3, 0), (1e-8, 0), (1e-12, 5)])
+def test_round_matches_oracle(q, ctx, eps, rmax):
+    modes = [3] + [2] * 9
+    ranks = [1, 3, 6, 10, 14, 16, 14, 10, 6, 2, 1]
+    xs = [I.graded_tt(modes, ranks, decay=0.4, seed=40 + b) for b in range(3)]
+    X = q.DeviceTT.from_cores(xs)
+    err, nrm = q.tt_round(ctx, X, eps, rmax)
+    ctx.sync()
+    out = X.to_cores()
+    err = err.cpu().numpy()
+    nrm = nrm.cpu().numpy()
+    for b in range(3):
+        ref, info = T.round_tt(xs[b], eps, rmax or None, return_info=True)
+        assert T.ranks(out[b]) == T.ranks(ref)
+        assert rel(T.full(out[b]), T.full(ref)) < 1e-10
+        assert abs(nrm[b] - info["norm"]) < 1e-13 * info["norm"]
+        assert abs(err[b] - info["err"]) <= 1e-10 * max(info["err"], 1e-300) + 1e-15
+        # right-orthogonal cores after the sweep
+        for c in out[b][1:]:
+            G = T.right_gram(c)
+            assert np.allclose(G, np.eye(G.shape[0]), atol=1e-12)
+
+
+def test_round_product_train_and_ragged_batch(q, ctx):
+    # a materialized Hadamard product is rounded exactly like the oracle does
+    modes = [3] + [2] * 8
+    a = I.random_tt(modes, [1, 2, 4, 5, 6, 5, 4, 3, 2, 1], seed=50)
+    b = I.random_tt(modes, [1, 3, 3, 4, 4, 4, 3, 2, 2, 1], seed=51)
+    prod = T.hadamard(a, b)
+    X = q.DeviceTT.from_cores([prod, T.hadamard(b, b)])
+    q.tt_round(ctx, X, 1e-6)
+    out = X.to_cores()
+    for got, src in zip(out, [prod, T.hadamard(b, b)]):
+        ref = T.round_tt(src, 1e-6)
+        assert T.ranks(got) == T.ranks(ref)
+        assert rel(T.full(got), T.full(ref)) < 1e-10
+
+
+@pytest.mark.parametrize("L", [2, 3])
+def test_ls_iterates_match_oracle_without_truncation(q, ctx, L):
+    from paper_2512_07811_amd import operands as P
+    N = 2 ** L
+    g = I.rng(60 + L)
+    k = g.uniform(1.0, 3.0, size=(N, N, N))
+    k0 = 2.0
+    E = np.array([1.0, 0.0, 0.0])
+    prob = P.build_problem(kvox=k, k0=k0, op_eps=1e-14, sfft_eps=1e-14)
+    ops, e = P.upload(prob, [E], max_rank=0)
+    oprob = ls_tt.Problem(k, k0, op_eps=1e-14, sfft_eps=1e-14)
+    opts = q.solve_opts(0.0, 0)
+    # start from E
+    e_cores = [O.mean_field_tt(E, L)]
+    e = q.DeviceTT.from_cores(e_cores, e.cap)
+    e_ref = O.mean_field_tt(E, L)
+    E_tt = O.mean_field_tt(E, L)
+    for m in range(3):
+        res = q.ls_iterate(ctx, ops, e, opts, 1).cpu().numpy()
+        e_ref, r_ref = ls_tt.ls_iterate(e_ref, oprob.kp, oprob.S, oprob.G, oprob.Sinv, E_tt, E, 0.0)
+        got = T.full(e.to_cores()[0])
+        assert rel(got, T.full(e_ref)) < 1e-10
+        assert abs(res[0, 0] - r_ref) < 1e-9 * max(r_ref, 1e-6)
+
+
+def test_homogenize_laminate_closed_form(q, ctx):
+    from paper_2512_07811_amd import operands as P
+    k = I.laminate(5)
+    prob = P.build_problem(kvox=k, k0=5.5)
+    ops, e = P.upload(prob, [[1, 0, 0], [0, 1, 0]], max_rank=64)
+    A, its, res, st = q.homogenize(ctx, ops, e, q.solve_opts(1e-10, 64, tol=1e-8, max_iter=200))
+    assert st == q.QT_OK
+    assert abs(A[0, 0] - 20.0 / 11.0) < 1e-10 * (20.0 / 11.0)
+    assert abs(A[1, 1] - 5.5) < 1e-10 * 5.5
+    assert np.all(np.abs(A[0, 1:]) < 1e-10) and abs(A[1, 0]) < 1e-10 and abs(A[1, 2]) < 1e-10
+    assert its[0] <= 3 and its[1] <= 2
+
+
+def test_homogenize_boxes_matches_oracle_tt(q, ctx):
+    from paper_2512_07811_amd import operands as P
+    L = 3
+    k = I.random_boxes(L, 5, edge_min=2, edge_max=5, k_min=2.0, k_max=6.0)
+    k0 = (k.min() + k.max()) / 2
+    prob = P.build_problem(kvox=k, k0=k0)
+    ops, e = P.upload(prob, [[1, 0, 0]], max_rank=0)
+    A, its, res, st = q.homogenize(ctx, ops, e, q.solve_opts(1e-6, 0, tol=1e-9, max_iter=300))
+    oprob = ls_tt.Problem(k, k0)
+    A_ref, its_ref = ls_tt.effective_tensor(oprob, [0], eps=1e-6, tol=1e-9, max_iter=300)
+    assert abs(its[0] - its_ref[0]) <= 1
+    assert np.max(np.abs(A[0] - A_ref[:, 0])) < 1e-8 * abs(A_ref[0, 0])

@@ -1,0 +1,39 @@
+"""Host set-up of the product path against closed forms and the oracle (CPU)."""
+import numpy as np
+import pytest
+
+from oracle import ops as O
+from oracle import tt as T
+from paper_2512_07811_amd import inputs as I
+from paper_2512_07811_amd import operands as P
+
+
+@pytest.mark.parametrize("L", [1, 2, 4, 7, 9])
+def test_circuit_sfft_equals_bit_reversed_fft(L):
+    N = 2 ** L
+    M = T.full_operator(P.sfft_1d(L))
+    g = I.rng(100 + L)
+    x = g.standard_normal((N, 2)) + 1j * g.standard_normal((N, 2))
+    ref = np.fft.fft(x, axis=0)[O.bitrev(L)] / np.sqrt(N)
+    assert np.max(np.abs(M @ x - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
+def test_green_tt_matches_oracle_definition():
+    L, k0 = 3, 5.5
+    G = P.green_tt(L, k0, 1e-12)
+    lifted = [G[0]] + T.diag_lift(G[1:])
+    Gref = O.green_momentum(L, k0)
+    # contract the operator on unit fields and compare with the dense symbol
+    dense = T.full_operator(lifted)
+    N = 2 ** L
+    diag = np.einsum("aibi->abi", dense.reshape(3, N ** 3, 3, N ** 3))
+    assert np.max(np.abs(diag.reshape(3, 3, N, N, N) - Gref)) < 1e-11
+
+
+def test_material_tt_bits_and_z_invariance():
+    L = 4
+    sec = I.cylinders_section(L, seed=3, count=2, r_min=2, r_max=3, k_in=5.0)
+    k3 = np.broadcast_to(sec[:, :, None], (16, 16, 16))
+    a = T.full(P.material_tt_z_invariant(sec, 1.0, 1e-12)).reshape(16, 16, 16)
+    b = T.full(P.material_tt(k3, 1.0, 1e-12)).reshape(16, 16, 16)
+    assert np.allclose(a, k3 - 1.0, atol=1e-11) and np.allclose(b, k3 - 1.0, atol=1e-11)
