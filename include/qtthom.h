@@ -132,6 +132,31 @@ qt_status tt_round(qt_ctx ctx, qt_tt* x, const qt_round_opts* opts, double* err_
 /* out[b] = sum_i conj(a_i) b_i for every instance (device [B][2] doubles). */
 qt_status tt_dot(qt_ctx ctx, const qt_tt* a, const qt_tt* b, double* out);
 
+/* ---- product-aware rounding ---------------------------------------------- */
+
+/* Rounds x = A y (TT x TTO contraction, Sec. 2.1; a Hadamard product is the
+ * diagonal case) into `out` WITHOUT forming the rank-(r_A r_y) cores of x:
+ * randomize-then-orthogonalize with a Gaussian train Omega (Al Daas et al.,
+ * SIAM J. Sci. Comput. 2023), contracting A and y separately.
+ *  omega: single train of sketch cores (its capacities are the sketch ranks
+ *         l_k); NULL draws Philox4x32-10 Gaussians from opts->seed with
+ *         l_k = min(natural rank, r_A r_y capacity, max_rank + oversample).
+ *  opts->mode QT_ROUND_SKETCH: then a right-to-left truncated-SVD sweep with
+ *         the remaining budget eps^2||x||^2 - (||x||^2 - ||x~||^2) split over
+ *         the n-1 bonds (capped by max_rank);
+ *         QT_ROUND_LEARNED: keep the sketch ranks (fixed-rank rounding).
+ *  xnorm2: device [B] exact ||x||^2 (e.g. from tt_sandwich).
+ *  err_out: device [B] relative error sqrt(sketch^2 + truncation^2)/||x||.
+ *  fail_out: device [B] int, 1 when the sketch error alone exceeds eps*||x||.
+ * A must be square (p_out = p_in = y's modes). out->cap >= sketch ranks. */
+qt_status tt_sketch_round(qt_ctx ctx, const qt_mpo* A, const qt_tt* y, const qt_tt* omega,
+                          const qt_round_opts* opts, const double* xnorm2, qt_tt* out,
+                          double* err_out, int32_t* fail_out);
+
+/* out[b] = scale * Re <y_b, Q y_b> for an operator train Q (used with
+ * Q = A^H A to get ||A y||^2 exactly without forming A y). */
+qt_status tt_sandwich(qt_ctx ctx, const qt_mpo* Q, const qt_tt* y, double scale, double* out);
+
 /* ---- Algorithm 2 ------------------------------------------------------------ */
 
 /* Operands of one cell problem on a 2^L-per-axis grid: core 0 is the
@@ -139,6 +164,9 @@ qt_status tt_dot(qt_ctx ctx, const qt_tt* a, const qt_tt* b, double* out);
 typedef struct {
   int32_t L;
   qt_tt kp;                 /* k' = k - k0, all-ones control core                */
+  qt_mpo Kp;                /* the same k' as a diagonal operator (sketch modes) */
+  qt_mpo K2;                /* (k')^2 as a diagonal operator: ||k' e||^2 = <e, K2 e> */
+  double k0;                /* reference conductivity: ||G t||^2 = <t, G t>/k0   */
   qt_mpo S;                 /* SFFT operator (Q_L per axis, identity on core 0)  */
   qt_mpo Sinv;              /* its adjoint                                       */
   qt_mpo G;                 /* Green operator, momentum convention, diag spatial */

@@ -5,6 +5,7 @@
 
 #include "kernels.h"
 #include "round.h"
+#include "sketch.h"
 
 namespace qt {
 
@@ -314,6 +315,210 @@ static qt_status setup_iteration(qt_ctx ctx, const qt_operands* ops, qt_tt* e,
   return QT_OK;
 }
 
+
+// ----------------------------------------------------------- sketch mode
+// tau = R(Kp y), tau^ = R(S tau), eps^ = R(G tau^), t4 = R(S^H eps^) with the
+// product-aware rounding R; then e' = SVD-round(E - t4) and the residual.
+struct SketchPlan {
+  std::vector<int32_t> modes, ce;
+  std::vector<int32_t> ell1, ell2, ell3, ell4;
+  std::vector<int32_t> c1r, c2r, c3r, c4r, c5, c5r, c6;
+  TTLayout l1, l2, l3, l4, l5, l6;
+  size_t bytesA = 0, bytesB = 0, ws = 0;
+};
+
+static std::vector<int32_t> capmin(const std::vector<int32_t>& c, int rmax) {
+  std::vector<int32_t> r(c);
+  if (rmax > 0)
+    for (size_t k = 1; k + 1 < r.size(); ++k) r[k] = std::min(r[k], rmax);
+  return r;
+}
+
+static SketchPlan plan_sketch(const qt_operands* ops, const qt_tt* e, const qt_round_opts& ro) {
+  SketchPlan P;
+  const int n = e->n, B = e->batch, rmax = ro.max_rank, os = ro.oversample;
+  P.modes.assign(e->modes, e->modes + n);
+  P.ce.assign(e->cap, e->cap + n + 1);
+  std::vector<int32_t> nat = natural_caps(P.modes);
+  qt_tt y = *e;
+  P.ell1 = sketch_ranks(&ops->Kp, &y, rmax, os);
+  P.c1r = capmin(P.ell1, rmax);
+  y.cap = P.c1r.data();
+  P.ell2 = sketch_ranks(&ops->S, &y, rmax, os);
+  P.c2r = capmin(P.ell2, rmax);
+  y.cap = P.c2r.data();
+  P.ell3 = sketch_ranks(&ops->G, &y, rmax, os);
+  P.c3r = capmin(P.ell3, rmax);
+  y.cap = P.c3r.data();
+  P.ell4 = sketch_ranks(&ops->Sinv, &y, rmax, os);
+  P.c4r = capmin(P.ell4, rmax);
+  P.c5.resize(n + 1);
+  P.c6.resize(n + 1);
+  P.c5r.resize(n + 1);
+  for (int k = 0; k <= n; ++k) {
+    P.c5[k] = (k == 0 || k == n) ? 1 : ops->E.cap[k] + P.c4r[k];
+    P.c5r[k] = std::min(P.c5[k], std::min(nat[k], rmax > 0 ? rmax : P.c5[k]));
+    P.c6[k] = (k == 0 || k == n) ? 1 : P.c5r[k] + P.ce[k];
+  }
+  P.l1 = make_layout(P.modes, P.ell1);
+  P.l2 = make_layout(P.modes, P.ell2);
+  P.l3 = make_layout(P.modes, P.ell3);
+  P.l4 = make_layout(P.modes, P.ell4);
+  P.l5 = make_layout(P.modes, P.c5);
+  P.l6 = make_layout(P.modes, P.c6);
+  P.bytesA = sizeof(cplx) * B * std::max({P.l1.stride, P.l3.stride, P.l5.stride});
+  P.bytesB = sizeof(cplx) * B * std::max({P.l2.stride, P.l4.stride, P.l6.stride});
+  const int lmax = rmax > 0 ? rmax : (1 << 30);
+  size_t ws = 0;
+  qt_tt yv = *e, ov;
+  ov = P.l1.view(nullptr, nullptr, B);
+  ws = std::max(ws, sround_ws_layout(&ops->Kp, &yv, &ov, P.ell1, lmax).bytes);
+  yv.cap = P.c1r.data();
+  ov = P.l2.view(nullptr, nullptr, B);
+  ws = std::max(ws, sround_ws_layout(&ops->S, &yv, &ov, P.ell2, lmax).bytes);
+  yv.cap = P.c2r.data();
+  ov = P.l3.view(nullptr, nullptr, B);
+  ws = std::max(ws, sround_ws_layout(&ops->G, &yv, &ov, P.ell3, lmax).bytes);
+  ws = std::max(ws, sandwich_ws_layout(&ops->G, &yv).bytes);
+  yv.cap = P.c3r.data();
+  ov = P.l4.view(nullptr, nullptr, B);
+  ws = std::max(ws, sround_ws_layout(&ops->Sinv, &yv, &ov, P.ell4, lmax).bytes);
+  yv = *e;
+  ws = std::max(ws, sandwich_ws_layout(&ops->K2, &yv).bytes);
+  ws = std::max(ws, round_bytes(P.l5, B, rmax));
+  ws = std::max(ws, round_bytes(P.l6, B, rmax));
+  P.ws = ws;
+  return P;
+}
+
+static qt_tt view_caps(const qt_tt& t, const std::vector<int32_t>& caps) {
+  qt_tt v = t;
+  v.cap = caps.data();
+  return v;
+}
+
+static qt_status iterate_once_sketch(qt_ctx ctx, const qt_operands* ops, qt_tt* e,
+                                     const SketchPlan& P, const qt_round_opts& ro, char* bufA,
+                                     char* bufB, int32_t* rA, int32_t* rB, double* dnorm,
+                                     const double* dinv, double* xn2, double* res_out,
+                                     uint64_t iter_id) {
+  const int B = e->batch, n = e->n, rs = n + 1;
+  hipStream_t st = ctx->stream;
+  const size_t mark = ctx->ws_top;
+  qt_round_opts so = ro;
+  if (so.mode == QT_ROUND_SVD) so.mode = QT_ROUND_SKETCH;
+  // tau = R(k' e)
+  QT_TRY(sandwich_impl(ctx, &ops->K2, e, 1.0, xn2));
+  ctx->ws_top = mark;
+  qt_tt t1 = P.l1.view(bufA, rA, B);
+  QT_TRY(sround_impl(ctx, &ops->Kp, e, nullptr, nullptr, P.ell1, &so, xn2, &t1, nullptr, nullptr,
+                     iter_id * 4 + 0, nullptr, 0, 0));
+  ctx->ws_top = mark;
+  qt_tt t1r = view_caps(t1, P.c1r);
+  // tau^ = R(S tau);  ||S tau|| = ||tau|| = ||core 0|| (right-orthogonal train)
+  sumsq(st, B, dconst(1), dref(t1r.ranks + 1, rs, t1r.modes[0]), (const cplx*)t1r.data,
+        t1r.inst_stride, xn2, 1.0);
+  qt_tt t2 = P.l2.view(bufB, rB, B);
+  QT_TRY(sround_impl(ctx, &ops->S, &t1r, nullptr, nullptr, P.ell2, &so, xn2, &t2, nullptr, nullptr,
+                     iter_id * 4 + 1, nullptr, 0, 0));
+  ctx->ws_top = mark;
+  qt_tt t2r = view_caps(t2, P.c2r);
+  // eps^ = R(G tau^);  ||G t||^2 = <t, G t>/k0
+  QT_TRY(sandwich_impl(ctx, &ops->G, &t2r, 1.0 / ops->k0, xn2));
+  ctx->ws_top = mark;
+  qt_tt t3 = P.l3.view(bufA, rA, B);
+  QT_TRY(sround_impl(ctx, &ops->G, &t2r, nullptr, nullptr, P.ell3, &so, xn2, &t3, nullptr, nullptr,
+                     iter_id * 4 + 2, nullptr, 0, 0));
+  ctx->ws_top = mark;
+  qt_tt t3r = view_caps(t3, P.c3r);
+  // t4 = R(S^H eps^)
+  sumsq(st, B, dconst(1), dref(t3r.ranks + 1, rs, t3r.modes[0]), (const cplx*)t3r.data,
+        t3r.inst_stride, xn2, 1.0);
+  qt_tt t4 = P.l4.view(bufB, rB, B);
+  QT_TRY(sround_impl(ctx, &ops->Sinv, &t3r, nullptr, nullptr, P.ell4, &so, xn2, &t4, nullptr,
+                     nullptr, iter_id * 4 + 3, nullptr, 0, 0));
+  ctx->ws_top = mark;
+  qt_tt t4r = view_caps(t4, P.c4r);
+  // e' = round(E - t4)
+  qt_tt t5 = P.l5.view(bufA, rA, B);
+  QT_TRY(add_impl(ctx, 1.0, 0.0, &ops->E, -1.0, 0.0, &t4r, &t5));
+  qt_round_opts po = ro;
+  po.mode = QT_ROUND_SVD;
+  QT_TRY(round_impl(ctx, &t5, &po, nullptr, nullptr, false, nullptr, 0, 0));
+  ctx->ws_top = mark;
+  qt_tt t5r = view_caps(t5, P.c5r);
+  qt_tt t6 = P.l6.view(bufB, rB, B);
+  QT_TRY(add_impl(ctx, 1.0, 0.0, &t5r, -1.0, 0.0, e, &t6));
+  QT_TRY(round_impl(ctx, &t6, &po, nullptr, dnorm, true, nullptr, 0, 0));
+  ctx->ws_top = mark;
+  if (res_out) {
+    k_residual<<<(B + 127) / 128, 128, 0, st>>>(B, dnorm, dinv, res_out);
+    QT_HIP(hipGetLastError());
+  }
+  QT_TRY(tt_copy(ctx, &t5r, e));
+  return QT_OK;
+}
+
+// One solver set-up shared by ls_iterate and homogenize (both modes).
+struct Solver {
+  bool sketch = false;
+  IterPlan P;
+  SketchPlan SP;
+  char* bufA = nullptr;
+  char* bufB = nullptr;
+  int32_t* rA = nullptr;
+  int32_t* rB = nullptr;
+  double* dnorm = nullptr;
+  double* dinv = nullptr;
+  double* xn2 = nullptr;
+};
+
+static qt_status solver_setup(qt_ctx ctx, const qt_operands* ops, qt_tt* e,
+                              const qt_solve_opts* opts, Solver& S, size_t extra) {
+  const int B = e->batch, n = e->n;
+  const int rmax = opts->round.max_rank;
+  S.sketch = opts->round.mode != QT_ROUND_SVD;
+  size_t bytesA, bytesB, ws;
+  if (S.sketch) {
+    QT_CHECK(opts->round.mode == QT_ROUND_SKETCH, QT_EINVAL,
+             "solver: learned rounding runs through the predictor path");
+    QT_CHECK(ops->Kp.n == n && ops->K2.n == n && ops->k0 > 0.0, QT_EINVAL,
+             "solver: sketch mode needs Kp, K2 and k0 operands");
+    S.SP = plan_sketch(ops, e, opts->round);
+    bytesA = S.SP.bytesA; bytesB = S.SP.bytesB; ws = S.SP.ws;
+  } else {
+    S.P = plan_iteration(ops, e, rmax);
+    bytesA = S.P.bytesA; bytesB = S.P.bytesB; ws = iteration_bytes(S.P, B, rmax) - S.P.bytesA - S.P.bytesB;
+  }
+  ctx->ws_top = 0;
+  QT_TRY(ws_reserve(ctx, bytesA + bytesB + ws + extra + sizeof(int32_t) * B * (n + 1) * 2 +
+                             sizeof(double) * B * 3 + 8 * 256));
+  S.bufA = (char*)ws_take(ctx, bytesA);
+  S.bufB = (char*)ws_take(ctx, bytesB);
+  S.rA = (int32_t*)ws_take(ctx, sizeof(int32_t) * B * (n + 1));
+  S.rB = (int32_t*)ws_take(ctx, sizeof(int32_t) * B * (n + 1));
+  S.dnorm = (double*)ws_take(ctx, sizeof(double) * B);
+  S.dinv = (double*)ws_take(ctx, sizeof(double) * B);
+  S.xn2 = (double*)ws_take(ctx, sizeof(double) * B);
+  QT_CHECK(S.bufA && S.bufB && S.rA && S.rB && S.dnorm && S.dinv && S.xn2, QT_ENOMEM,
+           "iteration workspace");
+  std::vector<double> inv(B);
+  const double N3 = std::ldexp(1.0, 3 * ops->L);
+  for (int b = 0; b < B; ++b) inv[b] = 1.0 / (ops->E_norm[b] * std::sqrt(N3));
+  QT_HIP(hipMemcpy(S.dinv, inv.data(), sizeof(double) * B, hipMemcpyHostToDevice));
+  return QT_OK;
+}
+
+static qt_status solver_step(qt_ctx ctx, const qt_operands* ops, qt_tt* e, const Solver& S,
+                             const qt_round_opts& ro, double* res_out) {
+  if (S.sketch) {
+    uint64_t id = ctx->sketch_counter++;
+    return iterate_once_sketch(ctx, ops, e, S.SP, ro, S.bufA, S.bufB, S.rA, S.rB, S.dnorm, S.dinv,
+                               S.xn2, res_out, id);
+  }
+  return iterate_once(ctx, ops, e, S.P, ro, S.bufA, S.bufB, S.rA, S.rB, S.dnorm, S.dinv, res_out);
+}
+
 }  // namespace qt
 
 using namespace qt;
@@ -372,13 +577,12 @@ qt_status ls_iterate(qt_ctx ctx, const qt_operands* ops, qt_tt* e, const qt_solv
   QT_CHECK(ctx && ops && e && opts, QT_EINVAL, "ls_iterate: null argument");
   QT_TRY(validate_ops(ops, e));
   QT_CHECK(n_iter >= 0, QT_EINVAL, "ls_iterate: n_iter < 0");
-  QT_CHECK(opts->round.mode == QT_ROUND_SVD, QT_EINVAL, "ls_iterate: rounding mode not available");
   QT_TRY(validate_field_cap(e, opts->round.max_rank));
-  IterSetup S;
-  QT_TRY(setup_iteration(ctx, ops, e, opts, S, 0));
+  Solver S;
+  QT_TRY(solver_setup(ctx, ops, e, opts, S, 0));
   for (int it = 0; it < n_iter; ++it) {
-    QT_TRY(iterate_once(ctx, ops, e, S.P, opts->round, S.bufA, S.bufB, S.rA, S.rB, S.dnorm, S.dinv,
-                        residual_out ? residual_out + (int64_t)it * e->batch : nullptr));
+    QT_TRY(solver_step(ctx, ops, e, S, opts->round,
+                       residual_out ? residual_out + (int64_t)it * e->batch : nullptr));
   }
   return QT_OK;
 }
@@ -393,10 +597,9 @@ qt_status homogenize(qt_ctx ctx, const qt_operands* ops, const qt_tt* k_sel, qt_
     QT_CHECK(k_sel[c].batch == 1 && k_sel[c].n == e->n, QT_EINVAL, "homogenize: k_sel shape");
   }
   QT_CHECK(opts->max_iter >= 1, QT_EINVAL, "homogenize: max_iter < 1");
-  QT_CHECK(opts->round.mode == QT_ROUND_SVD, QT_EINVAL, "homogenize: rounding mode not available");
   QT_TRY(validate_field_cap(e, opts->round.max_rank));
   const int B = e->batch;
-  IterSetup S;
+  Solver S;
   size_t dot_need = 4096 + sizeof(double) * 4 * B;
   {
     int64_t env = 1, tcap = 1;
@@ -405,7 +608,7 @@ qt_status homogenize(qt_ctx ctx, const qt_operands* ops, const qt_tt* k_sel, qt_
       tcap = std::max<int64_t>(tcap, (int64_t)k_sel[0].cap[k] * e->modes[k] * e->cap[k + 1]);
     dot_need += sizeof(cplx) * B * (2 * env + tcap) + 1024;
   }
-  QT_TRY(setup_iteration(ctx, ops, e, opts, S, dot_need));
+  QT_TRY(solver_setup(ctx, ops, e, opts, S, dot_need));
   double* dres = (double*)ws_take(ctx, sizeof(double) * B);
   QT_CHECK(dres, QT_ENOMEM, "homogenize: workspace");
   QT_TRY(tt_copy(ctx, &ops->E, e));
@@ -415,8 +618,7 @@ qt_status homogenize(qt_ctx ctx, const qt_operands* ops, const qt_tt* k_sel, qt_
   int it = 0;
   bool all = false;
   for (it = 1; it <= opts->max_iter && !all; ++it) {
-    QT_TRY(iterate_once(ctx, ops, e, S.P, opts->round, S.bufA, S.bufB, S.rA, S.rB, S.dnorm, S.dinv,
-                        dres));
+    QT_TRY(solver_step(ctx, ops, e, S, opts->round, dres));
     QT_HIP(hipMemcpyAsync(hres.data(), dres, sizeof(double) * B, hipMemcpyDeviceToHost, ctx->stream));
     QT_TRY(check_status(ctx));
     all = true;

@@ -38,16 +38,46 @@ __device__ inline void cfma(cplx& c, cplx a, cplx b) {
   c.y = fma(a.y, b.x, c.y);
 }
 
-// A dimension read from device memory: value = mul * p[b * stride] (or cst if p == null).
+// A size read from device memory: value = mul * p[b * stride] + cst
+// (cst alone when p is null).  b is the instance index of a batch.
 struct Dim {
   const int32_t* p;
   int32_t stride;
   int32_t mul;
   int32_t cst;
 };
-__device__ inline int dimv(const Dim& d, int b) { return d.p ? d.mul * d.p[(int64_t)b * d.stride] : d.cst; }
+__device__ inline int dimv(const Dim& d, int b) {
+  return (d.p ? d.mul * d.p[(int64_t)b * d.stride] : 0) + d.cst;
+}
 inline Dim dconst(int v) { return Dim{nullptr, 0, 0, v}; }
 inline Dim dref(const int32_t* p, int stride, int mul = 1) { return Dim{p, stride, mul, 0}; }
+
+// 64-bit strides that may depend on one device rank: value = mul * p[b*stride] + cst.
+struct Str {
+  const int32_t* p;
+  int32_t stride;
+  int64_t mul;
+  int64_t cst;
+};
+__device__ inline int64_t strv(const Str& s, int b) {
+  return (s.p ? s.mul * (int64_t)s.p[(int64_t)b * s.stride] : 0) + s.cst;
+}
+inline Str sconst(int64_t v) { return Str{nullptr, 0, 0, v}; }
+inline Str sref(const int32_t* p, int stride, int64_t mul = 1, int64_t cst = 0) {
+  return Str{p, stride, mul, cst};
+}
+
+// A strided matrix operand: element (r, c) of batch item (b1, b2) of instance b at
+// base + b*inst + b1*s1 + b2*s2 + r*rs + c*cs.
+struct Mat {
+  cplx* base;
+  int64_t inst;
+  Str off, s1, s2, rs, cs;
+};
+inline Mat mat(const cplx* base, int64_t inst, Str rs, Str cs, Str s1 = Str{nullptr, 0, 0, 0},
+               Str s2 = Str{nullptr, 0, 0, 0}, Str off = Str{nullptr, 0, 0, 0}) {
+  return Mat{const_cast<cplx*>(base), inst, off, s1, s2, rs, cs};
+}
 
 // Wave-level reductions (wave64).
 __device__ inline double wave_sum(double v) {
@@ -101,6 +131,7 @@ struct qt_ctx_s {
   size_t ws_top = 0;
   int32_t* status = nullptr;  // device status word
   int jacobi_default = 30;
+  uint64_t sketch_counter = 0;  // distinct Gaussian streams across iterations
 };
 
 namespace qt {

@@ -15,6 +15,15 @@ void gemm(hipStream_t st, int batch, Dim M, Dim N, Dim K, int Mcap, int Ncap, bo
           const cplx* A, int64_t sA, bool conjB, const cplx* B, int64_t sB, cplx* C, int64_t sC,
           cplx alpha, bool accumulate);
 
+// General strided batched GEMM: for every instance b and batch item (b1, b2)
+// with b1 < nb1, b2 < nb2:  C = alpha * op(A) op(B) (+ C when accumulate),
+// op = identity or conjugate (the transpose is expressed through strides).
+// A is M x K, B is K x N, C is M x N, each addressed through its Mat strides.
+// Batch items with b1 >= lim1 (a device size) are skipped.
+void gemm_ex(hipStream_t st, int batch, int nb1, int nb2, Dim M, Dim N, Dim K, int Mcap, int Ncap,
+             Mat A, bool conjA, Mat B, bool conjB, Mat C, cplx alpha, bool accumulate,
+             Dim lim1 = Dim{nullptr, 0, 0, 1 << 30});
+
 // Householder QR of the packed m x n matrix A (one workgroup per instance):
 // A = Q R with Q (m x s) and R (s x n) packed, s = min(m, n) written to s_out.
 // W is an m x n scratch matrix per instance (stride sW), tau a scratch vector.

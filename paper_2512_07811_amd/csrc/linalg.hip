@@ -233,7 +233,12 @@ void qr(hipStream_t st, int batch, Dim m, Dim n, const cplx* A, int64_t sA, cplx
 //   c = 1/sqrt(1 + t^2), s = c t;  the same J accumulates into V.
 // Pairs follow a round-robin (circle) schedule: every round is a set of
 // disjoint pairs, one per wave at a time.
-constexpr double JAC_TOL = 1e-15;
+// Convergence: rotate only while |gamma| > 2 mb eps sqrt(alpha beta) (the
+// rounding bound of a length-mb dot product), and never between columns whose
+// norms are below 1e-17 ||B||_F (they carry no significant digits; rotating
+// them can cycle on underflowed values).
+constexpr double JAC_EPS = 2.0 * 2.220446049250313e-16;
+constexpr double JAC_NEGL = 1e-34;
 constexpr int SVD_MAXNB = 1024;
 
 __global__ __launch_bounds__(256) void k_svd_trunc(
@@ -263,6 +268,16 @@ __global__ __launch_bounds__(256) void k_svd_trunc(
   }
   __syncthreads();
   const int nbp = (nb + 1) & ~1;
+  const double jtol = JAC_EPS * (double)mb;
+  __shared__ double red_f[16];
+  double fro = 0.0;
+  for (int64_t e = tid; e < (int64_t)mb * nb; e += blockDim.x) fro += cabs2(Bw[e]);
+  fro = wave_sum(fro);
+  if (lane == 0) red_f[wv] = fro;
+  __syncthreads();
+  fro = 0.0;
+  for (int i = 0; i < nw; ++i) fro += red_f[i];
+  const double negl = JAC_NEGL * fro;
   int sweep = 0;
   bool converged = (nb < 2);
   for (; sweep < max_sweeps && !converged; ++sweep) {
@@ -287,7 +302,8 @@ __global__ __launch_bounds__(256) void k_svd_trunc(
         }
         al = wave_sum(al); be = wave_sum(be); ga = wave_sum(ga);
         double g = sqrt(cabs2(ga));
-        if (g == 0.0 || !(g > JAC_TOL * sqrt(al * be))) continue;
+        if (al <= negl || be <= negl) continue;
+        if (g == 0.0 || !(g > jtol * sqrt(al * be))) continue;
         double zeta = (be - al) / (2.0 * g);
         double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
         double c = 1.0 / sqrt(1.0 + t * t), s = c * t;

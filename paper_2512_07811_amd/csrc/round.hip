@@ -8,6 +8,7 @@
 // fixed launch sequence with no host synchronisation.
 #include "kernels.h"
 #include "round.h"
+#include "sketch.h"
 
 namespace qt {
 
@@ -102,22 +103,40 @@ qt_status round_impl(qt_ctx ctx, qt_tt* x, const qt_round_opts* o, double* err_o
     return QT_OK;
   }
   // ---- right truncation sweep
+  SweepBufs buf{scratch, Bsv, Vb, Cb, w.slot, w.vv, w.carry};
+  QT_TRY(right_sweep_impl(ctx, x, rkl, scratch, w.slot, buf, delta, disc2, lmax_cap, sweeps, svlog,
+                          svstride_bond, svstride_inst));
+  finalize_err(st, B, disc2, norm, err_out, norm_out);
+  QT_HIP(hipGetLastError());
+  return QT_OK;
+}
+
+qt_status right_sweep_impl(qt_ctx ctx, qt_tt* x, const int32_t* rkl, const cplx* center,
+                           int64_t cstride, const SweepBufs& buf, const double* delta,
+                           double* disc2, int lmax_cap, int sweeps, double* svlog, int64_t svb,
+                           int64_t svi) {
+  const int n = x->n, B = x->batch, rs = n + 1;
+  hipStream_t st = ctx->stream;
+  cplx* X = (cplx*)x->data;
+  const int64_t sX = x->inst_stride;
+  int32_t* rk = x->ranks;
+  const cplx one = make_double2(1.0, 0.0);
   for (int k = n - 1; k >= 1; --k) {
     const int p = x->modes[k];
     const int lmax = std::min(lmax_cap, x->cap[k]);
-    svd_trunc(st, B, dref(rkl + k, rs), dref(rk + k + 1, rs, p), scratch, w.slot, Bsv, w.slot, Vb,
-              w.vv, X + x->offsets[k], sX, Cb, w.carry, rk + k, rs, delta, disc2, lmax, sweeps,
-              ctx->status, svlog ? svlog + k * svstride_bond : nullptr, svstride_inst,
-              (int)w.max_nb);
+    const cplx* in = (k == n - 1) ? center : buf.scratch;
+    const int64_t sin = (k == n - 1) ? cstride : buf.slot;
+    svd_trunc(st, B, dref(rkl + k, rs), dref(rk + k + 1, rs, p), in, sin, buf.Bsv, buf.slot,
+              buf.V, buf.vv, X + x->offsets[k], sX, buf.C, buf.carry, rk + k, rs, delta, disc2,
+              lmax, sweeps, ctx->status, svlog ? svlog + k * svb : nullptr, svi, 0);
     const int pp = x->modes[k - 1];
     // scratch (r'_{k-1} p x l_k) = core_{k-1} (r'_{k-1} p x r'_k) * carry (r'_k x l_k)
     gemm(st, B, dref(rkl + k - 1, rs, pp), dref(rk + k, rs), dref(rkl + k, rs),
-         x->cap[k - 1] * pp, x->cap[k], false, X + x->offsets[k - 1], sX, false, Cb, w.carry,
-         scratch, w.slot, one, false);
+         x->cap[k - 1] * pp, x->cap[k], false, X + x->offsets[k - 1], sX, false, buf.C, buf.carry,
+         buf.scratch, buf.slot, one, false);
   }
-  copy(st, B, dconst(x->modes[0]), dref(rk + 1, rs), (int64_t)x->modes[0] * x->cap[1], scratch,
-       w.slot, X + x->offsets[0], sX);
-  finalize_err(st, B, disc2, norm, err_out, norm_out);
+  copy(st, B, dconst(x->modes[0]), dref(rk + 1, rs), (int64_t)x->modes[0] * x->cap[1],
+       buf.scratch, buf.slot, X + x->offsets[0], sX);
   QT_HIP(hipGetLastError());
   return QT_OK;
 }

@@ -222,9 +222,13 @@ def build_problem(kvox=None, k0=None, L=None, section=None, op_eps=1e-10, sfft_e
         L = int(round(math.log2(section.shape[0])))
     kp = with_component_core(sp_kp, np.ones(3))
     ksel = [with_component_core(sp_k, np.eye(3)[c]) for c in range(3)]
+    # (k')^2 for the exact norm ||k' e||^2 = <e, diag((k')^2) e>
+    sp_k2 = compress(elementwise(sp_kp, sp_kp), op_eps * 1e-2)
+    k2 = with_component_core(sp_k2, np.ones(3))
     S, Sinv = sfft_3d(L, sfft_eps)
     G = green_tt(L, k0, op_eps)
-    return {"L": L, "kp": kp, "k_sel": ksel, "S": S, "Sinv": Sinv, "G": G}
+    return {"L": L, "k0": float(k0), "kp": kp, "k2": k2, "k_sel": ksel, "S": S, "Sinv": Sinv,
+            "G": G}
 
 
 def upload(prob, loads, max_rank, device=0):
@@ -233,15 +237,17 @@ def upload(prob, loads, max_rank, device=0):
     L = prob["L"]
     B = len(loads)
     kp = qtt.DeviceTT.from_cores(prob["kp"], device=device)
+    n = 3 * L + 1
+    Kp = qtt.DeviceMPO.from_cores(prob["kp"], [1] * n, device=device)
+    K2 = qtt.DeviceMPO.from_cores(prob["k2"], [1] * n, device=device)
     S = qtt.DeviceMPO.from_cores(prob["S"], device=device)
     Sinv = qtt.DeviceMPO.from_cores(prob["Sinv"], device=device)
-    n = 3 * L + 1
     G = qtt.DeviceMPO.from_cores(prob["G"], [0] + [1] * (n - 1), device=device)
     E = qtt.DeviceTT.from_cores([mean_field(np.asarray(Ej, dtype=float), L) for Ej in loads],
                                 device=device)
     ksel = [qtt.DeviceTT.from_cores(c, device=device) for c in prob["k_sel"]]
     E_norm = np.array([np.linalg.norm(Ej) for Ej in loads], dtype=np.float64)
-    ops = qtt.DeviceOperands(L, kp, S, Sinv, G, E, E_norm, ksel)
+    ops = qtt.DeviceOperands(L, kp, Kp, K2, prob["k0"], S, Sinv, G, E, E_norm, ksel)
     modes, cap = qtt.field_capacity(L, max_rank)
     e = qtt.DeviceTT.empty(modes, cap, B, device)
     return ops, e

@@ -22,7 +22,8 @@ ROUND_SVD, ROUND_SKETCH, ROUND_LEARNED = 0, 1, 2
 PREC_F64, PREC_F32 = 0, 1
 
 EXPORTS = ["qt_ctx_create", "qt_ctx_destroy", "qt_last_error", "qt_ctx_sync", "tt_hadamard",
-           "tt_mpo_apply", "tt_add", "tt_round", "tt_dot", "ls_iterate", "homogenize"]
+           "tt_mpo_apply", "tt_add", "tt_round", "tt_dot", "tt_sketch_round", "tt_sandwich",
+           "ls_iterate", "homogenize"]
 
 
 class QtError(RuntimeError):
@@ -51,8 +52,9 @@ class RoundOpts(C.Structure):
 
 
 class Operands(C.Structure):
-    _fields_ = [("L", C.c_int32), ("kp", TTDesc), ("S", MPODesc), ("Sinv", MPODesc),
-                ("G", MPODesc), ("E", TTDesc), ("E_norm", C.POINTER(C.c_double))]
+    _fields_ = [("L", C.c_int32), ("kp", TTDesc), ("Kp", MPODesc), ("K2", MPODesc),
+                ("k0", C.c_double), ("S", MPODesc), ("Sinv", MPODesc), ("G", MPODesc),
+                ("E", TTDesc), ("E_norm", C.POINTER(C.c_double))]
 
 
 class SolveOpts(C.Structure):
@@ -82,6 +84,9 @@ def load_library(path: str = LIB_PATH):
                            C.POINTER(TTDesc)]
     lib.tt_round.argtypes = [vp, C.POINTER(TTDesc), C.POINTER(RoundOpts), vp, vp]
     lib.tt_dot.argtypes = [vp, C.POINTER(TTDesc), C.POINTER(TTDesc), vp]
+    lib.tt_sketch_round.argtypes = [vp, C.POINTER(MPODesc), C.POINTER(TTDesc), C.POINTER(TTDesc),
+                                    C.POINTER(RoundOpts), vp, C.POINTER(TTDesc), vp, vp]
+    lib.tt_sandwich.argtypes = [vp, C.POINTER(MPODesc), C.POINTER(TTDesc), dbl, vp]
     lib.ls_iterate.argtypes = [vp, C.POINTER(Operands), C.POINTER(TTDesc), C.POINTER(SolveOpts),
                                i32, vp]
     lib.homogenize.argtypes = [vp, C.POINTER(Operands), C.POINTER(TTDesc), C.POINTER(TTDesc),
@@ -334,10 +339,37 @@ def tt_dot(ctx: Context, a: DeviceTT, b: DeviceTT):
     return torch.view_as_complex(out.view(b.batch, 2))
 
 
+def tt_sandwich(ctx: Context, Q: DeviceMPO, y: DeviceTT, scale: float = 1.0):
+    """scale * Re <y, Q y> per instance (device float64 tensor [batch])."""
+    torch = _torch()
+    out = torch.zeros(y.batch, dtype=torch.float64, device=y.data.device)
+    _check(ctx.lib.tt_sandwich(ctx.h, C.byref(Q.desc()), C.byref(y.desc()), scale,
+                               C.c_void_p(out.data_ptr())))
+    return out
+
+
+def tt_sketch_round(ctx: Context, A: DeviceMPO, y: DeviceTT, xnorm2, out: DeviceTT,
+                    omega: DeviceTT = None, eps: float = 0.0, max_rank: int = 0,
+                    mode: int = ROUND_SKETCH, oversample: int = 8, seed: int = 1):
+    """Product-aware rounding of A y into out; returns (err, fail) device tensors [batch]."""
+    torch = _torch()
+    err = torch.zeros(y.batch, dtype=torch.float64, device=y.data.device)
+    fail = torch.zeros(y.batch, dtype=torch.int32, device=y.data.device)
+    o = round_opts(eps, max_rank, mode, 0, PREC_F64, oversample, seed)
+    om = C.byref(omega.desc()) if omega is not None else None
+    _check(ctx.lib.tt_sketch_round(ctx.h, C.byref(A.desc()), C.byref(y.desc()), om, C.byref(o),
+                                   C.c_void_p(xnorm2.data_ptr()), C.byref(out.desc()),
+                                   C.c_void_p(err.data_ptr()), C.c_void_p(fail.data_ptr())))
+    return err, fail
+
+
 @dataclass
 class DeviceOperands:
     L: int
     kp: DeviceTT
+    Kp: DeviceMPO
+    K2: DeviceMPO
+    k0: float
     S: DeviceMPO
     Sinv: DeviceMPO
     G: DeviceMPO
@@ -347,8 +379,9 @@ class DeviceOperands:
     _struct: Operands = field(default=None, repr=False)
 
     def struct(self) -> Operands:
-        s = Operands(self.L, self.kp.desc(), self.S.desc(), self.Sinv.desc(), self.G.desc(),
-                     self.E.desc(), self.E_norm.ctypes.data_as(C.POINTER(C.c_double)))
+        s = Operands(self.L, self.kp.desc(), self.Kp.desc(), self.K2.desc(), self.k0,
+                     self.S.desc(), self.Sinv.desc(), self.G.desc(), self.E.desc(),
+                     self.E_norm.ctypes.data_as(C.POINTER(C.c_double)))
         self._struct = s
         return s
 
