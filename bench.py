@@ -1,0 +1,132 @@
+"""Benchmark: Lippmann-Schwinger iterations per second on one MI355X.
+
+A step is one basic-scheme iteration of Algorithm 2 (Hadamard with k', SFFT,
+Green multiply, inverse SFFT and mean field, each followed by rounding, and the
+FP64 residual) on one batch of fields, entirely in the HIP library.
+
+Default workload: 256^3 periodic cell (L = 8, 24 spatial QTT cores plus the
+component core), matrix k = 1 with a centred spherical inclusion of volume
+fraction 0.2 and k = 100, reference k0 = 50.5, load E = e_x, truncation
+tolerance 1e-6, field rank cap 64, product-aware randomized rounding.
+
+Prints one JSON line (see the keys below).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+CONFIGS = {
+    "sphere256": dict(L=8, geom="sphere", frac=0.2, k_in=100.0, k_out=1.0, k0=50.5, eps=1e-6,
+                      rmax=64, loads=[[1.0, 0.0, 0.0]]),
+    "laminate32": dict(L=5, geom="laminate", k0=5.5, eps=1e-10, rmax=64,
+                       loads=[[1.0, 0.0, 0.0], [0.0, 1.0, 0.0]]),
+    "sphere32": dict(L=5, geom="sphere", frac=0.2, k_in=100.0, k_out=1.0, k0=50.5, eps=1e-6,
+                     rmax=16, loads=[[1.0, 0.0, 0.0]]),
+}
+
+
+def voxels(cfg):
+    from paper_2512_07811_amd import inputs as I
+    if cfg["geom"] == "sphere":
+        return I.sphere(cfg["L"], cfg["frac"], cfg["k_in"], cfg["k_out"])
+    if cfg["geom"] == "laminate":
+        return I.laminate(cfg["L"])
+    raise ValueError(cfg["geom"])
+
+
+def cpu_baseline(cfg, kvox, budget_s=20.0):
+    """Dense Moulinec-Suquet oracle iterations on the host (bounded sample)."""
+    import numpy as np
+
+    from oracle import ms
+    E = cfg["loads"][0]
+    d = 3
+    e = np.broadcast_to(np.asarray(E, dtype=float).reshape((d, 1, 1, 1)), (d,) + kvox.shape).copy()
+    t0 = time.perf_counter()
+    its = 0
+    while True:
+        e = ms.ms_step(e, kvox, cfg["k0"], E)
+        its += 1
+        if time.perf_counter() - t0 > budget_s or its >= 50:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": its / dt, "unit": "LS iters/s", "cores": 1, "kind": "oracle",
+            "sample": f"{its} dense Moulinec-Suquet iterations (Algorithm 1, numpy pocketfft, "
+                      f"one thread) on the same {kvox.shape[0]}^3 microstructure and load; "
+                      f"the naive TT oracle cannot form this workload's product ranks"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="sphere256", choices=sorted(CONFIGS))
+    ap.add_argument("--mode", default="sketch", choices=["sketch", "svd"])
+    ap.add_argument("--oversample", type=int, default=8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; the multi-GPU layout is described "
+                                   "in DESIGN.md and not launched", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2512_07811_amd import operands as P
+    from paper_2512_07811_amd import qtt
+
+    cfg = CONFIGS[args.config]
+    kvox = voxels(cfg)
+    t0 = time.perf_counter()
+    prob = P.build_problem(kvox=kvox, k0=cfg["k0"])
+    t_setup = time.perf_counter() - t0
+    print(f"[bench] setup {t_setup:.1f}s  k' max rank {max(c.shape[0] for c in prob['kp'])}  "
+          f"G max rank {max(c.shape[0] for c in prob['G'])}", file=sys.stderr, flush=True)
+    ctx = qtt.Context(0)
+    ops, e = P.upload(prob, cfg["loads"], cfg["rmax"])
+    mode = qtt.ROUND_SKETCH if args.mode == "sketch" else qtt.ROUND_SVD
+    opts = qtt.solve_opts(cfg["eps"], cfg["rmax"], mode=mode, oversample=args.oversample, seed=17)
+    e = qtt.DeviceTT.from_cores([P.mean_field(np.asarray(E), ops.L) for E in cfg["loads"]], e.cap)
+    if args.warmup:
+        qtt.ls_iterate(ctx, ops, e, opts, args.warmup)
+    ctx.sync()
+    torch.cuda.synchronize()
+    print(f"[bench] warmup done, ranks {e.rank_array()[0].tolist()}", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    res = qtt.ls_iterate(ctx, ops, e, opts, args.steps)
+    ctx.sync()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    B = len(cfg["loads"])
+    value = args.steps * B / dt
+    print(f"[bench] {args.steps} steps in {dt:.3f}s; residuals {res.cpu().numpy()[:, 0].tolist()}",
+          file=sys.stderr, flush=True)
+    out = {
+        "metric": "LS iters/s", "value": value, "unit": "LS iters/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1000.0 * dt / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c128",
+        "data": "synthetic",
+        "config": {"workload": args.config, "L": cfg["L"], "grid": f"{2 ** cfg['L']}^3",
+                   "rounding": args.mode, "eps": cfg["eps"], "max_rank": cfg["rmax"],
+                   "batch": B, "parallelism": "single GPU"},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, kvox, args.cpu_budget)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -215,15 +215,17 @@ def build_problem(kvox=None, k0=None, L=None, section=None, op_eps=1e-10, sfft_e
     if kvox is not None:
         sp_k = material_tt(kvox, 0.0, op_eps)
         sp_kp = material_tt(kvox, k0, op_eps)
+        sp_k2 = material_tt((np.asarray(kvox, dtype=np.float64) - k0) ** 2, 0.0, op_eps * 1e-2)
         L = int(round(math.log2(kvox.shape[0])))
     else:
         sp_k = material_tt_z_invariant(section, 0.0, op_eps)
         sp_kp = material_tt_z_invariant(section, k0, op_eps)
+        sp_k2 = material_tt_z_invariant((np.asarray(section, dtype=np.float64) - k0) ** 2, 0.0,
+                                        op_eps * 1e-2)
         L = int(round(math.log2(section.shape[0])))
     kp = with_component_core(sp_kp, np.ones(3))
     ksel = [with_component_core(sp_k, np.eye(3)[c]) for c in range(3)]
     # (k')^2 for the exact norm ||k' e||^2 = <e, diag((k')^2) e>
-    sp_k2 = compress(elementwise(sp_kp, sp_kp), op_eps * 1e-2)
     k2 = with_component_core(sp_k2, np.ones(3))
     S, Sinv = sfft_3d(L, sfft_eps)
     G = green_tt(L, k0, op_eps)
