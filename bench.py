@@ -72,7 +72,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="sphere256", choices=sorted(CONFIGS))
     ap.add_argument("--mode", default="sketch", choices=["sketch", "svd"])
-    ap.add_argument("--oversample", type=int, default=8)
+    ap.add_argument("--oversample", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     args = ap.parse_args()

@@ -90,6 +90,29 @@ __device__ inline cplx wave_sum(cplx v) {
   return v;
 }
 
+// Sum over the 16 lanes of a DPP row (all lanes of the row receive the sum):
+// quad_perm [1,0,3,2] and [2,3,0,1] add within quads, row_ror:4 and :8 across them.
+__device__ inline double row16_sum(double v) {
+#define QT_DPP_STEP(ctrl)                                                           \
+  {                                                                                 \
+    int lo = __double2loint(v), hi = __double2hiint(v);                             \
+    int l2 = __builtin_amdgcn_update_dpp(0, lo, ctrl, 0xF, 0xF, false);             \
+    int h2 = __builtin_amdgcn_update_dpp(0, hi, ctrl, 0xF, 0xF, false);             \
+    v += __hiloint2double(h2, l2);                                                  \
+  }
+  QT_DPP_STEP(0xB1)
+  QT_DPP_STEP(0x4E)
+  QT_DPP_STEP(0x124)
+  QT_DPP_STEP(0x128)
+#undef QT_DPP_STEP
+  return v;
+}
+__device__ inline cplx row16_sum(cplx v) {
+  v.x = row16_sum(v.x);
+  v.y = row16_sum(v.y);
+  return v;
+}
+
 // Error reporting ---------------------------------------------------------
 void set_error(const std::string& msg);
 std::string hip_msg(hipError_t e, const char* what);

@@ -31,6 +31,21 @@ void qr(hipStream_t st, int batch, Dim m, Dim n, const cplx* A, int64_t sA, cplx
         double* tau, int64_t sTau, cplx* Q, int64_t sQ, cplx* R, int64_t sR, int32_t* s_out,
         int s_stride);
 
+// Register-resident variant for m <= 256, n <= 96 (returns false when the
+// capacities do not fit); qr_auto picks it when possible.
+// orient = true factors B = A when m >= n and B = A^H otherwise (mcap/ncap
+// must then bound max(m, n) and min(m, n)).
+bool qr_reg(hipStream_t st, int batch, int mcap, int ncap, Dim m, Dim n, const cplx* A, int64_t sA,
+            cplx* U, int64_t sU, double* tau, int64_t sTau, cplx* Q, int64_t sQ, cplx* R,
+            int64_t sR, int32_t* s_out, int s_stride, bool orient = false);
+// Memory-resident QR (LDS when the matrix fits, else the global scratch W).
+void qr_mem(hipStream_t st, int batch, int mcap, int ncap, Dim m, Dim n, const cplx* A,
+            int64_t sA, cplx* W, int64_t sW, double* tau, int64_t sTau, cplx* Q, int64_t sQ,
+            cplx* R, int64_t sR, int32_t* s_out, int s_stride, bool orient = false);
+void qr_auto(hipStream_t st, int batch, int mcap, int ncap, Dim m, Dim n, const cplx* A,
+             int64_t sA, cplx* W, int64_t sW, double* tau, int64_t sTau, cplx* Q, int64_t sQ,
+             cplx* R, int64_t sR, int32_t* s_out, int s_stride);
+
 // Truncated SVD of the packed m x c matrix A by one-sided (Hestenes) Jacobi:
 // keeps the smallest l >= 1 whose discarded tail does not exceed delta[b],
 // l <= lmax; writes V^dagger[:l] (l x c) to core, U Sigma[:, :l] (m x l) to
@@ -42,6 +57,16 @@ void svd_trunc(hipStream_t st, int batch, Dim m, Dim c, const cplx* A, int64_t s
                int64_t sCarry, int32_t* l_out, int l_stride, const double* delta, double* disc2,
                int lmax, int max_sweeps, int32_t* status, double* svlog, int64_t svstride,
                int nbcap);
+
+// Fast path of svd_trunc for min(m, c) <= 68 and max(m, c) <= 256 (register
+// QR + LDS Jacobi); returns false when the capacities do not fit.  Scratch:
+// Qw, Uw (max x min, stride sQ), Rw, RVw (min^2, stride sR), tau, sig (stride sT).
+bool svd_trunc_fast(hipStream_t st, int batch, int mcap, int ccap, Dim m, Dim c, const cplx* A,
+                    int64_t sA, cplx* Qw, cplx* Uw, int64_t sQ, cplx* Rw, cplx* RVw, int64_t sR,
+                    double* tau, double* sig, int64_t sT, cplx* core, int64_t sCore, cplx* carry,
+                    int64_t sCarry, int32_t* l_out, int l_stride, const double* delta,
+                    double* disc2, int lmax, int max_sweeps, int32_t* status, double* svlog,
+                    int64_t svstride);
 
 // Frobenius norm of a packed rows x cols matrix per instance; also sets
 // delta[b] = eps * norm / sqrt(nb_bonds) (0 when nb_bonds == 0) and disc2[b] = 0.

@@ -129,7 +129,7 @@ __device__ inline double block_sum(double v, double* red) {
 // -------------------------------------------------------------------- QR
 // Householder reflector H = I - tau u u^H with u_0 = 1, H x = beta e_1,
 // beta = -e^{i arg x_0} ||x||, tau = 1 + |x_0|/||x|| (tau = 0 for x = 0).
-__global__ __launch_bounds__(256) void k_qr(Dim Md, Dim Nd, const cplx* __restrict__ A, int64_t sA,
+__global__ __launch_bounds__(1024) void k_qr(Dim Md, Dim Nd, const cplx* __restrict__ A, int64_t sA,
                                             cplx* __restrict__ W, int64_t sW,
                                             double* __restrict__ tau, int64_t sTau,
                                             cplx* __restrict__ Q, int64_t sQ, cplx* __restrict__ R,
@@ -222,7 +222,15 @@ __global__ __launch_bounds__(256) void k_qr(Dim Md, Dim Nd, const cplx* __restri
 void qr(hipStream_t st, int batch, Dim m, Dim n, const cplx* A, int64_t sA, cplx* W, int64_t sW,
         double* tau, int64_t sTau, cplx* Q, int64_t sQ, cplx* R, int64_t sR, int32_t* s_out,
         int s_stride) {
-  k_qr<<<batch, 256, 0, st>>>(m, n, A, sA, W, sW, tau, sTau, Q, sQ, R, sR, s_out, s_stride);
+  k_qr<<<batch, 1024, 0, st>>>(m, n, A, sA, W, sW, tau, sTau, Q, sQ, R, sR, s_out, s_stride);
+}
+
+void qr_auto(hipStream_t st, int batch, int mcap, int ncap, Dim m, Dim n, const cplx* A,
+             int64_t sA, cplx* W, int64_t sW, double* tau, int64_t sTau, cplx* Q, int64_t sQ,
+             cplx* R, int64_t sR, int32_t* s_out, int s_stride) {
+  if (qr_reg(st, batch, mcap, ncap, m, n, A, sA, W, sW, tau, sTau, Q, sQ, R, sR, s_out, s_stride))
+    return;
+  qr_mem(st, batch, mcap, ncap, m, n, A, sA, W, sW, tau, sTau, Q, sQ, R, sR, s_out, s_stride);
 }
 
 // ------------------------------------------------------------ Jacobi SVD

@@ -8,6 +8,7 @@ namespace qt {
 struct RoundWs {
   int64_t slot = 1, rr = 1, vv = 1, carry = 1, tau = 1, max_nb = 0;
   size_t bytes = 0;
+  size_t sweep_bytes = 0;   // extra for the fast SVD (reflectors, R V, tau, sigma)
 };
 RoundWs round_ws_layout(const qt_tt* x, int lmax_cap);
 

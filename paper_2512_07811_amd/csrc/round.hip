@@ -36,8 +36,10 @@ RoundWs round_ws_layout(const qt_tt* x, int lmax_cap) {
   }
   w.slot = slot; w.rr = rr; w.vv = vv; w.carry = carry; w.tau = tau;
   const int B = x->batch;
+  w.max_nb = std::max<int64_t>(w.max_nb, 1);
+  w.sweep_bytes = sizeof(cplx) * B * (slot + vv) + sizeof(double) * B * 2 * w.max_nb + 4 * 256;
   w.bytes = sizeof(cplx) * B * (3 * slot + rr + vv + carry) + sizeof(double) * B * (tau + 4) +
-            sizeof(int32_t) * B * (n + 1) + 16 * 256;
+            sizeof(int32_t) * B * (n + 1) + 16 * 256 + w.sweep_bytes;
   return w;
 }
 
@@ -82,8 +84,8 @@ qt_status round_impl(qt_ctx ctx, qt_tt* x, const qt_round_opts* o, double* err_o
     const int p = x->modes[k];
     const cplx* in = (k == 0) ? X + x->offsets[0] : scratch;
     const int64_t sin = (k == 0) ? sX : w.slot;
-    qr(st, B, dref(rkl + k, rs, p), dref(rk + k + 1, rs), in, sin, Wq, w.slot, tau, w.tau,
-       X + x->offsets[k], sX, Rb, w.rr, rkl + k + 1, rs);
+    qr_auto(st, B, x->cap[k] * p, x->cap[k + 1], dref(rkl + k, rs, p), dref(rk + k + 1, rs), in,
+            sin, Wq, w.slot, tau, w.tau, X + x->offsets[k], sX, Rb, w.rr, rkl + k + 1, rs);
     const int p1 = x->modes[k + 1];
     // scratch (s x p1 r_{k+2}) = R (s x r_{k+1}) * core_{k+1} (r_{k+1} x p1 r_{k+2})
     gemm(st, B, dref(rkl + k + 1, rs), dref(rk + k + 2, rs, p1), dref(rk + k + 1, rs),
@@ -104,10 +106,21 @@ qt_status round_impl(qt_ctx ctx, qt_tt* x, const qt_round_opts* o, double* err_o
   }
   // ---- right truncation sweep
   SweepBufs buf{scratch, Bsv, Vb, Cb, w.slot, w.vv, w.carry};
+  QT_TRY(take_sweep_extra(ctx, B, w, buf));
   QT_TRY(right_sweep_impl(ctx, x, rkl, scratch, w.slot, buf, delta, disc2, lmax_cap, sweeps, svlog,
                           svstride_bond, svstride_inst));
   finalize_err(st, B, disc2, norm, err_out, norm_out);
   QT_HIP(hipGetLastError());
+  return QT_OK;
+}
+
+qt_status take_sweep_extra(qt_ctx ctx, int B, const RoundWs& w, SweepBufs& buf) {
+  buf.U = (cplx*)ws_take(ctx, sizeof(cplx) * B * w.slot);
+  buf.RV = (cplx*)ws_take(ctx, sizeof(cplx) * B * w.vv);
+  buf.tau = (double*)ws_take(ctx, sizeof(double) * B * w.max_nb);
+  buf.sig = (double*)ws_take(ctx, sizeof(double) * B * w.max_nb);
+  buf.nbmax = w.max_nb;
+  QT_CHECK(buf.U && buf.RV && buf.tau && buf.sig, QT_ENOMEM, "rounding: sweep workspace too small");
   return QT_OK;
 }
 
@@ -126,9 +139,15 @@ qt_status right_sweep_impl(qt_ctx ctx, qt_tt* x, const int32_t* rkl, const cplx*
     const int lmax = std::min(lmax_cap, x->cap[k]);
     const cplx* in = (k == n - 1) ? center : buf.scratch;
     const int64_t sin = (k == n - 1) ? cstride : buf.slot;
-    svd_trunc(st, B, dref(rkl + k, rs), dref(rk + k + 1, rs, p), in, sin, buf.Bsv, buf.slot,
-              buf.V, buf.vv, X + x->offsets[k], sX, buf.C, buf.carry, rk + k, rs, delta, disc2,
-              lmax, sweeps, ctx->status, svlog ? svlog + k * svb : nullptr, svi, 0);
+    const int mcap = x->cap[k], ccap = p * std::min(x->cap[k + 1], lmax_cap);
+    double* svk = svlog ? svlog + k * svb : nullptr;
+    if (!svd_trunc_fast(st, B, mcap, ccap, dref(rkl + k, rs), dref(rk + k + 1, rs, p), in, sin,
+                        buf.Bsv, buf.U, buf.slot, buf.V, buf.RV, buf.vv, buf.tau, buf.sig,
+                        buf.nbmax, X + x->offsets[k], sX, buf.C, buf.carry, rk + k, rs, delta,
+                        disc2, lmax, sweeps, ctx->status, svk, svi))
+      svd_trunc(st, B, dref(rkl + k, rs), dref(rk + k + 1, rs, p), in, sin, buf.Bsv, buf.slot,
+                buf.V, buf.vv, X + x->offsets[k], sX, buf.C, buf.carry, rk + k, rs, delta, disc2,
+                lmax, sweeps, ctx->status, svk, svi, 0);
     const int pp = x->modes[k - 1];
     // scratch (r'_{k-1} p x l_k) = core_{k-1} (r'_{k-1} p x r'_k) * carry (r'_k x l_k)
     gemm(st, B, dref(rkl + k - 1, rs, pp), dref(rk + k, rs), dref(rkl + k, rs),

@@ -41,7 +41,13 @@ struct SweepBufs {
   cplx* V;
   cplx* C;
   int64_t slot, vv, carry;
+  cplx* U;     // reflectors (slot)
+  cplx* RV;    // kept columns of R V (vv)
+  double* tau; // nb entries
+  double* sig; // nb entries
+  int64_t nbmax;
 };
+qt_status take_sweep_extra(qt_ctx ctx, int B, const RoundWs& w, SweepBufs& buf);
 qt_status right_sweep_impl(qt_ctx ctx, qt_tt* x, const int32_t* rkl, const cplx* center,
                            int64_t cstride, const SweepBufs& buf, const double* delta,
                            double* disc2, int lmax_cap, int sweeps, double* svlog, int64_t svb,

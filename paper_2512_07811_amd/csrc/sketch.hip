@@ -240,8 +240,8 @@ qt_status sketch_impl(qt_ctx ctx, const qt_mpo* A, const qt_tt* y, const cplx* o
             mat(Wall + w.Woff[k + 1], iW, sc(lk1), sc(1)), false, mat(Yb, iY, sc(lk1), sc(1)),
             one, false);
     // Q_k = qr(Y_k) -> out core k, new rank s' -> ro[k+1]
-    qr(st, B, dref(ro + k, rs, p), dconst(lk1), Yb, iY, Wq, iY, tau, w.tau, Od + out->offsets[k],
-       out->inst_stride, Rb, w.R, ro + k + 1, rs);
+    qr_auto(st, B, lk * p, lk1, dref(ro + k, rs, p), dconst(lk1), Yb, iY, Wq, iY, tau, w.tau,
+            Od + out->offsets[k], out->inst_stride, Rb, w.R, ro + k + 1, rs);
     // M_k = Q_k^H Z   (s' x R_{k+1})
     gemm_ex(st, B, 1, 1, dref(ro + k + 1, rs), dref(ry + k + 1, rs, rd1), dref(ro + k, rs, p), lk1,
             rd1 * y->cap[k + 1],

@@ -61,7 +61,8 @@ SRoundWs sround_ws_layout(const qt_mpo* A, const qt_tt* y, const qt_tt* out,
   w.om_tot = std::max<int64_t>(o, 1);
   const int B = y->batch;
   w.sweep = rw;
-  w.bytes = sk.bytes + sizeof(cplx) * (w.om_tot + (int64_t)B * (2 * rw.slot + rw.vv + rw.carry)) +
+  w.bytes = sk.bytes + rw.sweep_bytes +
+            sizeof(cplx) * (w.om_tot + (int64_t)B * (2 * rw.slot + rw.vv + rw.carry)) +
             sizeof(double) * B * 6 + sizeof(int32_t) * B * (y->n + 2) * 2 + 16 * 256;
   return w;
 }
@@ -101,6 +102,7 @@ qt_status sround_impl(qt_ctx ctx, const qt_mpo* A, const qt_tt* y, const cplx* o
     QT_HIP(hipMemcpyAsync(rkl, out->ranks, sizeof(int32_t) * B * (n + 1), hipMemcpyDeviceToDevice,
                           st));
     SweepBufs buf{scratch, Bsv, V, Cb, w.sweep.slot, w.sweep.vv, w.sweep.carry};
+    QT_TRY(take_sweep_extra(ctx, B, w.sweep, buf));
     const int sweeps = o->jacobi_max_sweeps > 0 ? o->jacobi_max_sweeps : ctx->jacobi_default;
     QT_TRY(right_sweep_impl(ctx, out, rkl, (const cplx*)out->data + out->offsets[n - 1],
                             out->inst_stride, buf, delta, disc2, lmax_cap, sweeps, svlog, svb, svi));

@@ -1,0 +1,224 @@
+// Truncated SVD for the right-to-left sweep, small sizes (min(m, c) <= 68):
+//   1. B = A (m >= c) or A^H (m < c); B = Q R by the register-resident QR;
+//   2. one-sided (Hestenes) Jacobi on the square R with R and V in LDS
+//      (R V = U_R Sigma), 16 waves, round-robin pairs, one barrier per round;
+//   3. truncation (smallest l whose discarded tail <= delta, l <= lmax);
+//   4. outputs: for A = Q R:   core = V^H[:l],  carry = Q (R V)[:, :l];
+//               for A^H = Q R: core = (Q (R V)[:, r] / sigma_r)^H,
+//                              carry = V[:, :l] Sigma[:l].
+// Rotation: gamma = b_p^H b_q = |gamma| e^{i phi}, zeta = (beta - alpha)/(2|gamma|),
+// t = sign(zeta)/(|zeta| + sqrt(1 + zeta^2)), c = 1/sqrt(1 + t^2), s = c t,
+// [b_p, b_q] <- [b_p, b_q] [[c, s e^{i phi}], [-s e^{-i phi}, c]].
+#include "kernels.h"
+
+namespace qt {
+
+constexpr int SL_NB = 68;            // LDS holds two SL_NB x SL_NB complex matrices
+constexpr double SL_EPS = 2.0 * 2.220446049250313e-16;
+constexpr double SL_NEGL = 1e-34;
+
+__global__ __launch_bounds__(1024) void k_jacobi_lds(
+    Dim Md, Dim Cd, const cplx* __restrict__ Rin, int64_t sR, cplx* __restrict__ RVp, int64_t sRV,
+    double* __restrict__ sigp, int64_t sSig, cplx* __restrict__ core, int64_t sCore,
+    cplx* __restrict__ carry, int64_t sCarry, int32_t* l_out, int l_stride,
+    const double* __restrict__ delta, double* __restrict__ disc2, int lmax, int max_sweeps,
+    int32_t* status, double* svlog, int64_t svstride) {
+  __shared__ cplx Rs[SL_NB * SL_NB];
+  __shared__ cplx Vs[SL_NB * SL_NB];
+  __shared__ double sig[SL_NB];
+  __shared__ int perm[SL_NB];
+  __shared__ double red[16];
+  __shared__ int sh_rot, sh_l;
+  const int b = blockIdx.x;
+  const int m = dimv(Md, b), nc = dimv(Cd, b);
+  const bool tall = m >= nc;
+  const int nb = tall ? nc : m;
+  Rin += b * sR; RVp += b * sRV; sigp += b * sSig; core += b * sCore; carry += b * sCarry;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
+  for (int e = tid; e < nb * nb; e += blockDim.x) {
+    const int i = e / nb, c = e % nb;       // R row-major (nb x nb)
+    Rs[c * nb + i] = Rin[e];
+    Vs[c * nb + i] = make_double2(i == c ? 1.0 : 0.0, 0.0);
+  }
+  double fro = 0.0;
+  for (int e = tid; e < nb * nb; e += blockDim.x) fro += cabs2(Rin[e]);
+  fro = wave_sum(fro);
+  if (lane == 0) red[wv] = fro;
+  __syncthreads();
+  fro = 0.0;
+  for (int i = 0; i < nw; ++i) fro += red[i];
+  const double negl = SL_NEGL * fro;
+  const double jtol = SL_EPS * (double)nb;
+  const int nbp = (nb + 1) & ~1;
+  const int g = tid & 15, grp = tid >> 4, ngrp = blockDim.x >> 4;
+  bool converged = nb < 2;
+  // each 16-lane row group owns one pair per round; sums reduce over the group by DPP
+  for (int sweep = 0; sweep < max_sweeps && !converged; ++sweep) {
+    if (tid == 0) sh_rot = 0;
+    __syncthreads();
+    for (int r = 0; r < nbp - 1; ++r) {
+      for (int pi0 = 0; pi0 < nbp / 2; pi0 += ngrp) {
+        const int pi = pi0 + grp;
+        int p = 0, q = 0;
+        bool valid = pi < nbp / 2;
+        if (valid) {
+          if (pi == 0) { p = nbp - 1; q = r; }
+          else { p = (r + pi) % (nbp - 1); q = (r - pi + nbp - 1) % (nbp - 1); }
+          if (p >= nb || q >= nb) valid = false;
+          if (p > q) { int t = p; p = q; q = t; }
+        }
+        cplx* bp = Rs + p * nb;
+        cplx* bq = Rs + q * nb;
+        double al = 0.0, be = 0.0;
+        cplx ga = make_double2(0.0, 0.0);
+        if (valid) {
+          for (int i = g; i < nb; i += 16) {
+            cplx x = bp[i], y = bq[i];
+            al += cabs2(x);
+            be += cabs2(y);
+            cfma(ga, cconj(x), y);
+          }
+        }
+        al = row16_sum(al); be = row16_sum(be); ga = row16_sum(ga);
+        const double gabs = sqrt(cabs2(ga));
+        const bool rot = valid && al > negl && be > negl && gabs > 0.0 && gabs > jtol * sqrt(al * be);
+        if (rot) {
+          const double zeta = (be - al) / (2.0 * gabs);
+          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+          const cplx e = make_double2(ga.x / gabs, ga.y / gabs);
+          const cplx se = cscale(e, s), sec = cscale(cconj(e), s);
+          for (int i = g; i < nb; i += 16) {
+            cplx x = bp[i], y = bq[i];
+            bp[i] = csub(cscale(x, c), cmul(sec, y));
+            bq[i] = cadd(cmul(se, x), cscale(y, c));
+          }
+          cplx* vp = Vs + p * nb;
+          cplx* vq = Vs + q * nb;
+          for (int i = g; i < nb; i += 16) {
+            cplx x = vp[i], y = vq[i];
+            vp[i] = csub(cscale(x, c), cmul(sec, y));
+            vq[i] = cadd(cmul(se, x), cscale(y, c));
+          }
+          if (g == 0) sh_rot = 1;
+        }
+      }
+      __syncthreads();
+    }
+    converged = (sh_rot == 0);
+    __syncthreads();
+  }
+  if (!converged && tid == 0) atomicOr(status, (int32_t)ST_JACOBI_CAP);
+  for (int c = wv; c < nb; c += nw) {
+    double a = 0.0;
+    for (int i = lane; i < nb; i += 64) a += cabs2(Rs[c * nb + i]);
+    a = wave_sum(a);
+    if (lane == 0) sig[c] = sqrt(a);
+  }
+  __syncthreads();
+  for (int c = tid; c < nb; c += blockDim.x) {
+    const double v = sig[c];
+    int pos = 0;
+    for (int d = 0; d < nb; ++d) pos += (sig[d] > v) || (sig[d] == v && d < c);
+    perm[pos] = c;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const double dl = delta[b];
+    double tail2 = 0.0;
+    int l = nb;
+    for (int j = nb - 1; j >= 0; --j) {
+      const double sj = sig[perm[j]];
+      if (sqrt(tail2 + sj * sj) <= dl) { tail2 += sj * sj; l = j; }
+      else break;
+    }
+    if (l < 1) l = 1;
+    if (l > lmax) l = lmax;
+    if (l > nb) l = nb;
+    double d2 = 0.0;
+    bool finite = true;
+    for (int j = 0; j < nb; ++j) {
+      const double sj = sig[perm[j]];
+      if (!isfinite(sj)) finite = false;
+      if (j >= l) d2 += sj * sj;
+    }
+    if (!finite) atomicOr(status, (int32_t)ST_NONFINITE);
+    disc2[b] += d2;
+    sh_l = l;
+    if (l_out) l_out[(int64_t)b * l_stride] = l;
+  }
+  __syncthreads();
+  const int l = sh_l;
+  if (svlog)
+    for (int j = tid; j < nb; j += blockDim.x) svlog[b * svstride + j] = sig[perm[j]];
+  // (R V)[:, perm[:l]] column-major and sorted sigma for the finalizer
+  for (int e = tid; e < l * nb; e += blockDim.x) {
+    const int r = e / nb, i = e % nb;
+    RVp[e] = Rs[perm[r] * nb + i];
+  }
+  for (int r = tid; r < l; r += blockDim.x) sigp[r] = sig[perm[r]];
+  if (tall) {
+    // core = V^H[:l]  (l x nc), nc = nb
+    for (int e = tid; e < l * nb; e += blockDim.x) {
+      const int r = e / nb, c = e % nb;
+      core[e] = cconj(Vs[perm[r] * nb + c]);
+    }
+  } else {
+    // carry = V[:, perm[:l]] Sigma  (m x l), m = nb
+    for (int e = tid; e < nb * l; e += blockDim.x) {
+      const int i = e / l, r = e % l;
+      carry[e] = cscale(Vs[perm[r] * nb + i], sig[perm[r]]);
+    }
+  }
+}
+
+// Applies Q (mb x nb, row-major) to the kept columns of R V.
+__global__ __launch_bounds__(1024) void k_svd_finalize(Dim Md, Dim Cd, const cplx* __restrict__ Q,
+                                                       int64_t sQ, const cplx* __restrict__ RVp,
+                                                       int64_t sRV, const double* __restrict__ sigp,
+                                                       int64_t sSig, const int32_t* l_in,
+                                                       int l_stride, cplx* __restrict__ core,
+                                                       int64_t sCore, cplx* __restrict__ carry,
+                                                       int64_t sCarry) {
+  const int b = blockIdx.x;
+  const int m = dimv(Md, b), nc = dimv(Cd, b);
+  const bool tall = m >= nc;
+  const int mb = tall ? m : nc, nb = tall ? nc : m;
+  const int l = l_in[(int64_t)b * l_stride];
+  Q += b * sQ; RVp += b * sRV; sigp += b * sSig; core += b * sCore; carry += b * sCarry;
+  for (int e = threadIdx.x; e < mb * l; e += blockDim.x) {
+    const int i = e / l, r = e % l;
+    cplx acc = make_double2(0.0, 0.0);
+    const cplx* qi = Q + (int64_t)i * nb;
+    const cplx* rv = RVp + (int64_t)r * nb;
+    for (int c = 0; c < nb; ++c) cfma(acc, qi[c], rv[c]);
+    if (tall) {
+      carry[(int64_t)i * l + r] = acc;                     // carry (m x l)
+    } else {
+      const double sv = sigp[r];
+      cplx v = sv > 0.0 ? cscale(cconj(acc), 1.0 / sv) : make_double2(i == r ? 1.0 : 0.0, 0.0);
+      core[(int64_t)r * nc + i] = v;                       // core (l x nc), row r
+    }
+  }
+}
+
+bool svd_trunc_fast(hipStream_t st, int batch, int mcap, int ccap, Dim m, Dim c, const cplx* A,
+                    int64_t sA, cplx* Qw, cplx* Uw, int64_t sQ, cplx* Rw, cplx* RVw, int64_t sR,
+                    double* tau, double* sig, int64_t sT, cplx* core, int64_t sCore, cplx* carry,
+                    int64_t sCarry, int32_t* l_out, int l_stride, const double* delta,
+                    double* disc2, int lmax, int max_sweeps, int32_t* status, double* svlog,
+                    int64_t svstride) {
+  const int mbcap = std::max(mcap, ccap), nbcap = std::min(mcap, ccap);
+  if (nbcap > SL_NB) return false;
+  if (!qr_reg(st, batch, mbcap, nbcap, m, c, A, sA, Uw, sQ, tau, sT, Qw, sQ, Rw, sR, nullptr, 0,
+              true))
+    qr_mem(st, batch, mbcap, nbcap, m, c, A, sA, Uw, sQ, tau, sT, Qw, sQ, Rw, sR, nullptr, 0, true);
+  k_jacobi_lds<<<batch, 1024, 0, st>>>(m, c, Rw, sR, RVw, sR, sig, sT, core, sCore, carry, sCarry,
+                                       l_out, l_stride, delta, disc2, lmax, max_sweeps, status,
+                                       svlog, svstride);
+  k_svd_finalize<<<batch, 1024, 0, st>>>(m, c, Qw, sQ, RVw, sR, sig, sT, l_out, l_stride, core,
+                                         sCore, carry, sCarry);
+  return true;
+}
+
+}  // namespace qt
