@@ -104,11 +104,27 @@ def main():
     ctx.sync()
     torch.cuda.synchronize()
     print(f"[bench] warmup done, ranks {e.rank_array()[0].tolist()}", file=sys.stderr, flush=True)
+    ctx.counters(reset=True)
+    ctx.profile(ctx.PROF_GEMM | ctx.PROF_QR | ctx.PROF_SVD)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     res = qtt.ls_iterate(ctx, ops, e, opts, args.steps)
     ctx.sync()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    kernel_ms, kernel_launches = ctx.profile_read()
+    ctx.profile(0)
+    cnt = ctx.counters()
+    # per-class split: time the classes one at a time over one more step each
+    split = {}
+    for name, cls in (("gemm", ctx.PROF_GEMM), ("qr", ctx.PROF_QR), ("svd", ctx.PROF_SVD)):
+        ctx.profile(cls)
+        qtt.ls_iterate(ctx, ops, e, opts, 1)
+        split[name] = ctx.profile_read()
+    ctx.profile(0)
+    cnt1 = ctx.counters(reset=True)
+    gemm_flops_step = (cnt1["gemm_flops"] - cnt["gemm_flops"])
+    gemm_bytes_step = (cnt1["gemm_bytes"] - cnt["gemm_bytes"])
     B = len(cfg["loads"])
     value = args.steps * B / dt
     print(f"[bench] {args.steps} steps in {dt:.3f}s; residuals {res.cpu().numpy()[:, 0].tolist()}",
@@ -122,6 +138,25 @@ def main():
                    "rounding": args.mode, "eps": cfg["eps"], "max_rank": cfg["rmax"],
                    "batch": B, "parallelism": "single GPU"},
     }
+    dom = max(split, key=lambda k: split[k][0])
+    g_ms, g_n = split["gemm"]
+    # the structured contractions are the flop-carrying kernels (complex FP64 FMA);
+    # the QR and SVD kernels are latency-bound and reported by their time share
+    achieved = gemm_flops_step / (g_ms * 1e-3) / 1e12 if g_ms > 0 else None
+    out["roofline"] = {
+        "kernel": "structured GEMM (k_gemm_ex)", "bound": "alu", "achieved": achieved,
+        "peak": 78.6, "unit": "TFLOP/s",
+        "frac": (achieved / 78.6) if achieved else None, "traffic": None,
+        "flops_per_step": gemm_flops_step, "bytes_per_step": gemm_bytes_step,
+        "kernel_ms_per_step": {k: v[0] for k, v in split.items()},
+        "launches_per_step": {k: v[1] for k, v in split.items()},
+        "dominant_class": dom,
+    }
+    out["counters"] = {"svd_calls_per_step": cnt["svd_calls"] / args.steps,
+                       "jacobi_sweeps_per_svd": (cnt["svd_sweeps"] / cnt["svd_calls"]
+                                                 if cnt["svd_calls"] else None),
+                       "sketch_over_budget": cnt["sketch_over_budget"],
+                       "timed_kernel_ms": kernel_ms, "timed_launches": kernel_launches}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, kvox, args.cpu_budget)
     ctx.close()

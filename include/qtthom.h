@@ -101,6 +101,23 @@ const char* qt_last_error(void);
 /* Block until every call issued on the context's stream has finished. */
 qt_status qt_ctx_sync(qt_ctx ctx);
 
+/* Device event counters since creation (or the last reset), int64 each:
+ *  [0] truncated SVDs, [1] Jacobi sweeps they used, [2] sketch roundings whose
+ *  error exceeded the budget, [3] learned roundings that fell back to SVD
+ *  rounding, [4] structured-GEMM flops, [5] structured-GEMM bytes.
+ *  Synchronizes the stream. */
+qt_status qt_ctx_counters(qt_ctx ctx, int64_t* out, int32_t n, int32_t reset);
+
+/* Live timing of kernel classes (bit mask: 1 structured GEMMs, 2 QR
+ * factorizations, 4 truncated SVDs; 0 disables): the library records HIP
+ * events on its stream around every launch of those classes.
+ * qt_ctx_profile_read returns the summed event time and the number of timed
+ * launches since the last read, then clears them.  Counters [4] and [5] of
+ * qt_ctx_counters hold the algorithmic flops and bytes of the structured
+ * GEMMs (8 flops per complex multiply-add; A, B, C touched once). */
+qt_status qt_ctx_profile(qt_ctx ctx, int32_t classes);
+qt_status qt_ctx_profile_read(qt_ctx ctx, double* total_ms, int64_t* launches);
+
 /* ---- TT algebra (Sec. 2.1) --------------------------------------------- */
 
 /* out = a (Hadamard) b: C_k(i) = A_k(i) (Kronecker) B_k(i); exact, ranks

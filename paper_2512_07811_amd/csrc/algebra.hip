@@ -241,15 +241,18 @@ qt_status add_impl(qt_ctx ctx, double are, double aim, const qt_tt* x, double br
 }  // namespace qt
 
 extern "C" qt_status tt_hadamard(qt_ctx ctx, const qt_tt* a, const qt_tt* b, qt_tt* out) {
+  qt::enter(ctx);
   if (ctx) ctx->ws_top = 0;
   return qt::hadamard_impl(ctx, a, b, out);
 }
 extern "C" qt_status tt_mpo_apply(qt_ctx ctx, const qt_mpo* A, const qt_tt* x, qt_tt* out) {
+  qt::enter(ctx);
   if (ctx) ctx->ws_top = 0;
   return qt::mpo_impl(ctx, A, x, out);
 }
 extern "C" qt_status tt_add(qt_ctx ctx, double are, double aim, const qt_tt* x, double bre,
                             double bim, const qt_tt* y, qt_tt* out) {
+  qt::enter(ctx);
   if (ctx) ctx->ws_top = 0;
   return qt::add_impl(ctx, are, aim, x, bre, bim, y, out);
 }
@@ -295,6 +298,7 @@ qt_status dot_impl(qt_ctx ctx, const qt_tt* a, const qt_tt* b, double* out, bool
 }  // namespace qt
 
 extern "C" qt_status tt_dot(qt_ctx ctx, const qt_tt* a, const qt_tt* b, double* out) {
+  qt::enter(ctx);
   QT_CHECK(ctx && a && b && out, QT_EINVAL, "tt_dot: null argument");
   QT_TRY(tt_validate(a, "a"));
   QT_TRY(tt_validate(b, "b"));

@@ -10,6 +10,34 @@
 namespace qt {
 
 static thread_local std::string g_last_error;
+thread_local ProfSink* g_prof = nullptr;
+thread_local unsigned long long* g_counters = nullptr;
+
+void ProfSink::begin() {
+  if (used + 2 > ev.size()) {
+    for (int i = 0; i < 64; ++i) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return;
+      ev.push_back(e);
+    }
+  }
+  hipEventRecord(ev[used], stream);
+}
+
+void ProfSink::end() {
+  if (used + 2 > ev.size()) return;
+  hipEventRecord(ev[used + 1], stream);
+  used += 2;
+}
+
+// Every public entry point binds the context's profiling sink and counters
+// for the kernels it launches on this thread.
+void enter(qt_ctx ctx) {
+  if (!ctx) return;
+  ctx->prof.stream = ctx->stream;
+  g_prof = ctx->prof.cls ? &ctx->prof : nullptr;
+  g_counters = ctx->counters;
+}
 
 void set_error(const std::string& msg) { g_last_error = msg; }
 
@@ -541,6 +569,8 @@ qt_status qt_ctx_create(int device, void* stream, size_t ws_bytes, qt_ctx* out) 
     return QT_ENOMEM;
   }
   e = hipMemset(c->status, 0, sizeof(int32_t));
+  if (e == hipSuccess) e = hipMalloc((void**)&c->counters, sizeof(unsigned long long) * CNT_N);
+  if (e == hipSuccess) e = hipMemset(c->counters, 0, sizeof(unsigned long long) * CNT_N);
   if (e != hipSuccess) {
     hipFree(c->status);
     delete c;
@@ -564,7 +594,42 @@ void qt_ctx_destroy(qt_ctx ctx) {
   hipStreamSynchronize(ctx->stream);
   if (ctx->ws) hipFree(ctx->ws);
   if (ctx->status) hipFree(ctx->status);
+  if (ctx->counters) hipFree(ctx->counters);
+  for (hipEvent_t e : ctx->prof.ev) hipEventDestroy(e);
   delete ctx;
+}
+
+qt_status qt_ctx_profile(qt_ctx ctx, int32_t classes) {
+  QT_CHECK(ctx, QT_EINVAL, "qt_ctx_profile: null ctx");
+  QT_HIP(hipStreamSynchronize(ctx->stream));
+  ctx->prof.cls = classes;
+  ctx->prof.used = 0;
+  return QT_OK;
+}
+
+qt_status qt_ctx_profile_read(qt_ctx ctx, double* total_ms, int64_t* launches) {
+  QT_CHECK(ctx && total_ms && launches, QT_EINVAL, "qt_ctx_profile_read: bad argument");
+  QT_HIP(hipStreamSynchronize(ctx->stream));
+  double t = 0.0;
+  for (size_t i = 0; i + 1 < ctx->prof.used; i += 2) {
+    float ms = 0.f;
+    QT_HIP(hipEventElapsedTime(&ms, ctx->prof.ev[i], ctx->prof.ev[i + 1]));
+    t += ms;
+  }
+  *total_ms = t;
+  *launches = (int64_t)(ctx->prof.used / 2);
+  ctx->prof.used = 0;
+  return QT_OK;
+}
+
+qt_status qt_ctx_counters(qt_ctx ctx, int64_t* out, int32_t n, int32_t reset) {
+  QT_CHECK(ctx && out && n >= 0, QT_EINVAL, "qt_ctx_counters: bad argument");
+  unsigned long long h[CNT_N] = {0};
+  QT_HIP(hipMemcpyAsync(h, ctx->counters, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+  QT_HIP(hipStreamSynchronize(ctx->stream));
+  for (int i = 0; i < n && i < CNT_N; ++i) out[i] = (int64_t)h[i];
+  if (reset) QT_HIP(hipMemsetAsync(ctx->counters, 0, sizeof(h), ctx->stream));
+  return QT_OK;
 }
 
 qt_status qt_ctx_sync(qt_ctx ctx) {
@@ -575,6 +640,7 @@ qt_status qt_ctx_sync(qt_ctx ctx) {
 qt_status ls_iterate(qt_ctx ctx, const qt_operands* ops, qt_tt* e, const qt_solve_opts* opts,
                      int32_t n_iter, double* residual_out) {
   QT_CHECK(ctx && ops && e && opts, QT_EINVAL, "ls_iterate: null argument");
+  enter(ctx);
   QT_TRY(validate_ops(ops, e));
   QT_CHECK(n_iter >= 0, QT_EINVAL, "ls_iterate: n_iter < 0");
   QT_TRY(validate_field_cap(e, opts->round.max_rank));
@@ -591,6 +657,7 @@ qt_status homogenize(qt_ctx ctx, const qt_operands* ops, const qt_tt* k_sel, qt_
                      const qt_solve_opts* opts, double* A_eff, int32_t* iters,
                      double* residuals) {
   QT_CHECK(ctx && ops && k_sel && e && opts && A_eff && iters, QT_EINVAL, "homogenize: null argument");
+  enter(ctx);
   QT_TRY(validate_ops(ops, e));
   for (int c = 0; c < 3; ++c) {
     QT_TRY(tt_validate(&k_sel[c], "k_sel"));

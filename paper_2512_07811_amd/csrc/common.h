@@ -143,6 +143,26 @@ std::string hip_msg(hipError_t e, const char* what);
 // Device status word bits (written by kernels, read by the host on sync).
 enum : int32_t { ST_JACOBI_CAP = 1, ST_NONFINITE = 2 };
 
+// Device event counters (int64, indices below), read with qt_ctx_counters.
+enum : int32_t { CNT_SVD_CALLS = 0, CNT_SVD_SWEEPS = 1, CNT_SKETCH_FAIL = 2, CNT_FALLBACK = 3,
+                 CNT_GEMM_FLOPS = 4, CNT_GEMM_BYTES = 5, CNT_N = 8 };
+
+// Kernel classes that can be timed with events (qt_ctx_profile).
+enum : int32_t { PROF_GEMM = 1, PROF_QR = 2, PROF_SVD = 4 };
+
+// Live timing of one kernel class: event pairs recorded around its launches.
+struct ProfSink {
+  int cls = 0;
+  hipStream_t stream = nullptr;
+  std::vector<hipEvent_t> ev;   // start/stop pairs
+  size_t used = 0;
+  void begin();                 // record a start event (grows the pool)
+  void end();                   // record the matching stop event
+};
+extern thread_local ProfSink* g_prof;
+inline bool prof_on(int cls) { return g_prof && (g_prof->cls & cls); }
+extern thread_local unsigned long long* g_counters;
+
 }  // namespace qt
 
 // Context: device, stream and a growable workspace arena.
@@ -153,6 +173,8 @@ struct qt_ctx_s {
   size_t ws_size = 0;
   size_t ws_top = 0;
   int32_t* status = nullptr;  // device status word
+  unsigned long long* counters = nullptr;  // device [CNT_N] event counters
+  qt::ProfSink prof;
   int jacobi_default = 30;
   uint64_t sketch_counter = 0;  // distinct Gaussian streams across iterations
 };

@@ -10,7 +10,8 @@ constexpr int XT_M = 64, XT_N = 64, XT_K = 16;
 template <bool CA, bool CB>
 __global__ __launch_bounds__(256) void k_gemm_ex(int nb1, int nb2, int ntn, Dim Md, Dim Nd,
                                                  Dim Kd, Mat A, Mat B, Mat C, cplx alpha,
-                                                 int accumulate, Dim lim1) {
+                                                 int accumulate, Dim lim1,
+                                                 unsigned long long* counters) {
   const int nbt = nb1 * nb2;
   const int tn = blockIdx.x % ntn;
   const int z = blockIdx.x / ntn;
@@ -20,6 +21,13 @@ __global__ __launch_bounds__(256) void k_gemm_ex(int nb1, int nb2, int ntn, Dim 
   const int M = dimv(Md, b), N = dimv(Nd, b), K = dimv(Kd, b);
   const int m0 = blockIdx.y * XT_M, n0 = tn * XT_N;
   if (m0 >= M || n0 >= N || b1 >= dimv(lim1, b)) return;
+  if (counters && m0 == 0 && n0 == 0 && threadIdx.x == 0 && K > 0) {
+    // algorithmic work of this product: 8 real flops per complex MAC and the
+    // compulsory traffic of reading A, B and writing C once
+    atomicAdd(counters + CNT_GEMM_FLOPS, 8ull * M * N * K);
+    atomicAdd(counters + CNT_GEMM_BYTES, 16ull * ((unsigned long long)M * K + (unsigned long long)K * N +
+                                                  (unsigned long long)M * N));
+  }
   const cplx* Ab = A.base + b * A.inst + strv(A.off, b) + b1 * strv(A.s1, b) + b2 * strv(A.s2, b);
   const cplx* Bb = B.base + b * B.inst + strv(B.off, b) + b1 * strv(B.s1, b) + b2 * strv(B.s2, b);
   cplx* Cb = C.base + b * C.inst + strv(C.off, b) + b1 * strv(C.s1, b) + b2 * strv(C.s2, b);
@@ -104,14 +112,18 @@ void gemm_ex(hipStream_t st, int batch, int nb1, int nb2, Dim M, Dim N, Dim K, i
   const int64_t gx = (int64_t)ntn * batch * nb1 * nb2;
   dim3 grid((unsigned)gx, (Mcap + XT_M - 1) / XT_M, 1);
   const int acc = accumulate ? 1 : 0;
+  unsigned long long* cnt = g_counters;
+  const bool prof = prof_on(PROF_GEMM);
+  if (prof) g_prof->begin();
   if (!conjA && !conjB)
-    k_gemm_ex<false, false><<<grid, 256, 0, st>>>(nb1, nb2, ntn, M, N, K, A, B, C, alpha, acc, lim1);
+    k_gemm_ex<false, false><<<grid, 256, 0, st>>>(nb1, nb2, ntn, M, N, K, A, B, C, alpha, acc, lim1, cnt);
   else if (conjA && !conjB)
-    k_gemm_ex<true, false><<<grid, 256, 0, st>>>(nb1, nb2, ntn, M, N, K, A, B, C, alpha, acc, lim1);
+    k_gemm_ex<true, false><<<grid, 256, 0, st>>>(nb1, nb2, ntn, M, N, K, A, B, C, alpha, acc, lim1, cnt);
   else if (!conjA && conjB)
-    k_gemm_ex<false, true><<<grid, 256, 0, st>>>(nb1, nb2, ntn, M, N, K, A, B, C, alpha, acc, lim1);
+    k_gemm_ex<false, true><<<grid, 256, 0, st>>>(nb1, nb2, ntn, M, N, K, A, B, C, alpha, acc, lim1, cnt);
   else
-    k_gemm_ex<true, true><<<grid, 256, 0, st>>>(nb1, nb2, ntn, M, N, K, A, B, C, alpha, acc, lim1);
+    k_gemm_ex<true, true><<<grid, 256, 0, st>>>(nb1, nb2, ntn, M, N, K, A, B, C, alpha, acc, lim1, cnt);
+  if (prof) g_prof->end();
 }
 
 }  // namespace qt

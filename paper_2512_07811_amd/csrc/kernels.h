@@ -5,6 +5,8 @@
 
 namespace qt {
 
+void enter(qt_ctx ctx);
+
 // C_b = alpha * op(A_b) op(B_b) (+ C_b when accumulate), complex double,
 // row-major packed matrices whose sizes M, N, K are read from device memory.
 //   A stored M x K (conjA = false) or K x M (conjA = true, A^dagger used)
@@ -66,7 +68,7 @@ bool svd_trunc_fast(hipStream_t st, int batch, int mcap, int ccap, Dim m, Dim c,
                     double* tau, double* sig, int64_t sT, cplx* core, int64_t sCore, cplx* carry,
                     int64_t sCarry, int32_t* l_out, int l_stride, const double* delta,
                     double* disc2, int lmax, int max_sweeps, int32_t* status, double* svlog,
-                    int64_t svstride);
+                    int64_t svstride, unsigned long long* counters);
 
 // Frobenius norm of a packed rows x cols matrix per instance; also sets
 // delta[b] = eps * norm / sqrt(nb_bonds) (0 when nb_bonds == 0) and disc2[b] = 0.

@@ -228,9 +228,11 @@ void qr(hipStream_t st, int batch, Dim m, Dim n, const cplx* A, int64_t sA, cplx
 void qr_auto(hipStream_t st, int batch, int mcap, int ncap, Dim m, Dim n, const cplx* A,
              int64_t sA, cplx* W, int64_t sW, double* tau, int64_t sTau, cplx* Q, int64_t sQ,
              cplx* R, int64_t sR, int32_t* s_out, int s_stride) {
-  if (qr_reg(st, batch, mcap, ncap, m, n, A, sA, W, sW, tau, sTau, Q, sQ, R, sR, s_out, s_stride))
-    return;
-  qr_mem(st, batch, mcap, ncap, m, n, A, sA, W, sW, tau, sTau, Q, sQ, R, sR, s_out, s_stride);
+  const bool prof = prof_on(PROF_QR);
+  if (prof) g_prof->begin();
+  if (!qr_reg(st, batch, mcap, ncap, m, n, A, sA, W, sW, tau, sTau, Q, sQ, R, sR, s_out, s_stride))
+    qr_mem(st, batch, mcap, ncap, m, n, A, sA, W, sW, tau, sTau, Q, sQ, R, sR, s_out, s_stride);
+  if (prof) g_prof->end();
 }
 
 // ------------------------------------------------------------ Jacobi SVD

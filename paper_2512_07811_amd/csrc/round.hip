@@ -141,13 +141,16 @@ qt_status right_sweep_impl(qt_ctx ctx, qt_tt* x, const int32_t* rkl, const cplx*
     const int64_t sin = (k == n - 1) ? cstride : buf.slot;
     const int mcap = x->cap[k], ccap = p * std::min(x->cap[k + 1], lmax_cap);
     double* svk = svlog ? svlog + k * svb : nullptr;
+    const bool prof = prof_on(PROF_SVD);
+    if (prof) g_prof->begin();
     if (!svd_trunc_fast(st, B, mcap, ccap, dref(rkl + k, rs), dref(rk + k + 1, rs, p), in, sin,
                         buf.Bsv, buf.U, buf.slot, buf.V, buf.RV, buf.vv, buf.tau, buf.sig,
                         buf.nbmax, X + x->offsets[k], sX, buf.C, buf.carry, rk + k, rs, delta,
-                        disc2, lmax, sweeps, ctx->status, svk, svi))
+                        disc2, lmax, sweeps, ctx->status, svk, svi, ctx->counters))
       svd_trunc(st, B, dref(rkl + k, rs), dref(rk + k + 1, rs, p), in, sin, buf.Bsv, buf.slot,
                 buf.V, buf.vv, X + x->offsets[k], sX, buf.C, buf.carry, rk + k, rs, delta, disc2,
                 lmax, sweeps, ctx->status, svk, svi, 0);
+    if (prof) g_prof->end();
     const int pp = x->modes[k - 1];
     // scratch (r'_{k-1} p x l_k) = core_{k-1} (r'_{k-1} p x r'_k) * carry (r'_k x l_k)
     gemm(st, B, dref(rkl + k - 1, rs, pp), dref(rk + k, rs), dref(rkl + k, rs),
@@ -164,6 +167,7 @@ qt_status right_sweep_impl(qt_ctx ctx, qt_tt* x, const int32_t* rkl, const cplx*
 
 extern "C" qt_status tt_round(qt_ctx ctx, qt_tt* x, const qt_round_opts* opts, double* err_out,
                               double* norm_out) {
+  qt::enter(ctx);
   QT_CHECK(ctx && x && opts, QT_EINVAL, "tt_round: null argument");
   QT_TRY(qt::tt_validate(x, "x"));
   QT_CHECK(opts->eps >= 0.0, QT_EINVAL, "tt_round: eps < 0");

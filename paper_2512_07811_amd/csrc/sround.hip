@@ -13,7 +13,8 @@ namespace qt {
 
 // delta[b] = sqrt(max(eps^2 ||x||^2 - e_s^2, 0)/(n-1)); e_s^2 = max(||x||^2 - ||x~||^2, 0)
 __global__ void k_budget(int batch, int nbonds, double eps, const double* xn2, const double* yn2,
-                         double* delta, double* disc2, double* es2, int32_t* fail) {
+                         double* delta, double* disc2, double* es2, int32_t* fail,
+                         unsigned long long* counters) {
   int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= batch) return;
   double e2 = fmax(xn2[b] - yn2[b], 0.0);
@@ -22,6 +23,7 @@ __global__ void k_budget(int batch, int nbonds, double eps, const double* xn2, c
   disc2[b] = 0.0;
   es2[b] = e2;
   if (fail) fail[b] = bud < 0.0 ? 1 : 0;
+  if (bud < 0.0 && counters) atomicAdd(counters + CNT_SKETCH_FAIL, 1ull);
 }
 
 __global__ void k_sketch_err(int batch, const double* xn2, const double* es2, const double* disc2,
@@ -92,7 +94,8 @@ qt_status sround_impl(qt_ctx ctx, const qt_mpo* A, const qt_tt* y, const cplx* o
   int32_t* rkl = (int32_t*)ws_take(ctx, sizeof(int32_t) * B * (n + 1));
   QT_CHECK(yn2 && delta && disc2 && es2 && rkl, QT_ENOMEM, "sketch rounding: workspace too small");
   QT_TRY(sketch_impl(ctx, A, y, omega, *om_off, ell, out, yn2));
-  k_budget<<<(B + 127) / 128, 128, 0, st>>>(B, n - 1, o->eps, xn2, yn2, delta, disc2, es2, fail);
+  k_budget<<<(B + 127) / 128, 128, 0, st>>>(B, n - 1, o->eps, xn2, yn2, delta, disc2, es2, fail,
+                                            ctx->counters);
   if (o->mode == QT_ROUND_SKETCH && n > 1) {
     cplx* scratch = (cplx*)ws_take(ctx, sizeof(cplx) * B * w.sweep.slot);
     cplx* Bsv = (cplx*)ws_take(ctx, sizeof(cplx) * B * w.sweep.slot);
@@ -132,6 +135,7 @@ extern "C" qt_status tt_sketch_round(qt_ctx ctx, const qt_mpo* A, const qt_tt* y
                                      const qt_tt* omega, const qt_round_opts* opts,
                                      const double* xnorm2, qt_tt* out, double* err_out,
                                      int32_t* fail_out) {
+  qt::enter(ctx);
   QT_CHECK(ctx && A && y && opts && xnorm2 && out, QT_EINVAL, "tt_sketch_round: null argument");
   QT_TRY(tt_validate(y, "y"));
   QT_TRY(tt_validate(out, "out"));
@@ -163,6 +167,7 @@ extern "C" qt_status tt_sketch_round(qt_ctx ctx, const qt_mpo* A, const qt_tt* y
 
 extern "C" qt_status tt_sandwich(qt_ctx ctx, const qt_mpo* Q, const qt_tt* y, double scale,
                                  double* out) {
+  qt::enter(ctx);
   QT_CHECK(ctx && Q && y && out, QT_EINVAL, "tt_sandwich: null argument");
   QT_TRY(tt_validate(y, "y"));
   QT_TRY(validate_mpo(Q, y));

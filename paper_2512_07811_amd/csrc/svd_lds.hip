@@ -22,7 +22,7 @@ __global__ __launch_bounds__(1024) void k_jacobi_lds(
     double* __restrict__ sigp, int64_t sSig, cplx* __restrict__ core, int64_t sCore,
     cplx* __restrict__ carry, int64_t sCarry, int32_t* l_out, int l_stride,
     const double* __restrict__ delta, double* __restrict__ disc2, int lmax, int max_sweeps,
-    int32_t* status, double* svlog, int64_t svstride) {
+    int32_t* status, double* svlog, int64_t svstride, unsigned long long* counters) {
   __shared__ cplx Rs[SL_NB * SL_NB];
   __shared__ cplx Vs[SL_NB * SL_NB];
   __shared__ double sig[SL_NB];
@@ -52,8 +52,10 @@ __global__ __launch_bounds__(1024) void k_jacobi_lds(
   const int nbp = (nb + 1) & ~1;
   const int g = tid & 15, grp = tid >> 4, ngrp = blockDim.x >> 4;
   bool converged = nb < 2;
+  int sweeps_done = 0;
   // each 16-lane row group owns one pair per round; sums reduce over the group by DPP
   for (int sweep = 0; sweep < max_sweeps && !converged; ++sweep) {
+    ++sweeps_done;
     if (tid == 0) sh_rot = 0;
     __syncthreads();
     for (int r = 0; r < nbp - 1; ++r) {
@@ -109,6 +111,10 @@ __global__ __launch_bounds__(1024) void k_jacobi_lds(
     __syncthreads();
   }
   if (!converged && tid == 0) atomicOr(status, (int32_t)ST_JACOBI_CAP);
+  if (tid == 0 && counters) {
+    atomicAdd(counters + CNT_SVD_CALLS, 1ull);
+    atomicAdd(counters + CNT_SVD_SWEEPS, (unsigned long long)sweeps_done);
+  }
   for (int c = wv; c < nb; c += nw) {
     double a = 0.0;
     for (int i = lane; i < nb; i += 64) a += cabs2(Rs[c * nb + i]);
@@ -207,7 +213,7 @@ bool svd_trunc_fast(hipStream_t st, int batch, int mcap, int ccap, Dim m, Dim c,
                     double* tau, double* sig, int64_t sT, cplx* core, int64_t sCore, cplx* carry,
                     int64_t sCarry, int32_t* l_out, int l_stride, const double* delta,
                     double* disc2, int lmax, int max_sweeps, int32_t* status, double* svlog,
-                    int64_t svstride) {
+                    int64_t svstride, unsigned long long* counters) {
   const int mbcap = std::max(mcap, ccap), nbcap = std::min(mcap, ccap);
   if (nbcap > SL_NB) return false;
   if (!qr_reg(st, batch, mbcap, nbcap, m, c, A, sA, Uw, sQ, tau, sT, Qw, sQ, Rw, sR, nullptr, 0,
@@ -215,7 +221,7 @@ bool svd_trunc_fast(hipStream_t st, int batch, int mcap, int ccap, Dim m, Dim c,
     qr_mem(st, batch, mbcap, nbcap, m, c, A, sA, Uw, sQ, tau, sT, Qw, sQ, Rw, sR, nullptr, 0, true);
   k_jacobi_lds<<<batch, 1024, 0, st>>>(m, c, Rw, sR, RVw, sR, sig, sT, core, sCore, carry, sCarry,
                                        l_out, l_stride, delta, disc2, lmax, max_sweeps, status,
-                                       svlog, svstride);
+                                       svlog, svstride, counters);
   k_svd_finalize<<<batch, 1024, 0, st>>>(m, c, Qw, sQ, RVw, sR, sig, sT, l_out, l_stride, core,
                                          sCore, carry, sCarry);
   return true;

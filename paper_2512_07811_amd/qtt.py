@@ -21,7 +21,8 @@ QT_OK, QT_NOT_CONVERGED = 0, 1
 ROUND_SVD, ROUND_SKETCH, ROUND_LEARNED = 0, 1, 2
 PREC_F64, PREC_F32 = 0, 1
 
-EXPORTS = ["qt_ctx_create", "qt_ctx_destroy", "qt_last_error", "qt_ctx_sync", "tt_hadamard",
+EXPORTS = ["qt_ctx_create", "qt_ctx_destroy", "qt_last_error", "qt_ctx_sync",
+           "qt_ctx_counters", "qt_ctx_profile", "qt_ctx_profile_read", "tt_hadamard",
            "tt_mpo_apply", "tt_add", "tt_round", "tt_dot", "tt_sketch_round", "tt_sandwich",
            "ls_iterate", "homogenize"]
 
@@ -78,6 +79,9 @@ def load_library(path: str = LIB_PATH):
     lib.qt_ctx_destroy.restype = None
     lib.qt_last_error.restype = C.c_char_p
     lib.qt_ctx_sync.argtypes = [vp]
+    lib.qt_ctx_counters.argtypes = [vp, C.POINTER(C.c_int64), i32, i32]
+    lib.qt_ctx_profile.argtypes = [vp, i32]
+    lib.qt_ctx_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     lib.tt_hadamard.argtypes = [vp, C.POINTER(TTDesc), C.POINTER(TTDesc), C.POINTER(TTDesc)]
     lib.tt_mpo_apply.argtypes = [vp, C.POINTER(MPODesc), C.POINTER(TTDesc), C.POINTER(TTDesc)]
     lib.tt_add.argtypes = [vp, dbl, dbl, C.POINTER(TTDesc), dbl, dbl, C.POINTER(TTDesc),
@@ -155,6 +159,26 @@ class Context:
 
     def sync(self):
         _check(self.lib.qt_ctx_sync(self.h))
+
+    def counters(self, reset: bool = False) -> dict:
+        """Device event counters (see qt_ctx_counters in include/qtthom.h)."""
+        out = (C.c_int64 * 8)()
+        _check(self.lib.qt_ctx_counters(self.h, out, 8, 1 if reset else 0))
+        return {"svd_calls": out[0], "svd_sweeps": out[1], "sketch_over_budget": out[2],
+                "learned_fallbacks": out[3], "gemm_flops": out[4], "gemm_bytes": out[5]}
+
+    PROF_GEMM, PROF_QR, PROF_SVD = 1, 2, 4
+
+    def profile(self, classes: int):
+        """Start live event timing of kernel classes (bit mask; 0 stops)."""
+        _check(self.lib.qt_ctx_profile(self.h, classes))
+
+    def profile_read(self):
+        """(summed kernel time in ms, number of timed launches) since the last read."""
+        ms = C.c_double()
+        n = C.c_int64()
+        _check(self.lib.qt_ctx_profile_read(self.h, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
 
 
 def natural_caps(modes):
