@@ -104,7 +104,8 @@ qt_status qt_ctx_sync(qt_ctx ctx);
 /* Device event counters since creation (or the last reset), int64 each:
  *  [0] truncated SVDs, [1] Jacobi sweeps they used, [2] sketch roundings whose
  *  error exceeded the budget, [3] learned roundings that fell back to SVD
- *  rounding, [4] structured-GEMM flops, [5] structured-GEMM bytes.
+ *  rounding, [4] structured-GEMM flops, [5] structured-GEMM bytes,
+ *  [6] learned (fixed predicted rank) roundings attempted.
  *  Synchronizes the stream. */
 qt_status qt_ctx_counters(qt_ctx ctx, int64_t* out, int32_t n, int32_t reset);
 
@@ -214,6 +215,74 @@ qt_status ls_iterate(qt_ctx ctx, const qt_operands* ops, qt_tt* e, const qt_solv
 qt_status homogenize(qt_ctx ctx, const qt_operands* ops, const qt_tt* k_sel, qt_tt* e,
                      const qt_solve_opts* opts, double* A_eff, int32_t* iters,
                      double* residuals);
+
+/* ---------------------------------------------------------------------------
+ * Learned-rank rounding (rank predictor).  The method's fixed-rank truncation
+ * (Sec. 3, truncated SVD at a given rank) and its coarse-grained rank classes
+ * r_c = c * r_0 (Sec. 5.1) are combined with a small FP32 MLP that predicts
+ * each bond's rank from the previous iteration's sketched spectrum, so that the
+ * product-aware rounding can skip its SVD truncation sweep.  The exact
+ * a-posteriori error decides: above accept * max(eps, e_s), where e_s is the
+ * error of the last SVD-truncated rounding of the same step (e_s > eps only
+ * where the rank cap binds), the step is redone with the SVD-truncated sketch
+ * rounding (fallback, counted).  With accept <= 1 every rounding is as
+ * accurate as the SVD truncation would be (to the drift of e_s between its
+ * refreshes, which happen at every fallback).
+ * ------------------------------------------------------------------------- */
+
+/* Number of floats in the MLP parameter vector for n_in inputs and n_cls
+ * classes (three hidden tanh layers of 64; W row-major [in][out], then bias,
+ * for each of the four layers). */
+int32_t qt_mlp_num_params(int32_t n_in, int32_t n_cls);
+
+/* One full-batch training step of the MLP on the context's stream.
+ * params, adam_m, adam_v: device [num_params] floats (in/out; Adam moments,
+ *   zero-initialised by the caller; may be NULL when lr <= 0).
+ * step: Adam step number (>= 1, for bias correction).
+ * X: device [n][n_in] features; labels: device [n] classes in [0, n_cls).
+ * Loss = mean over samples of cross-entropy + beta * sum_c p_c w(c, y), with
+ *   w(c, y) = (c - y)/n_cls above the label and gamma below it.
+ * lr <= 0: no update (gradient evaluation only).
+ * loss_out: device float (may be NULL); grad_out: device [num_params] floats
+ *   holding the mean gradient (may be NULL).
+ * Errors: QT_EINVAL for NULL inputs or n_in > 32, n_cls outside [2, 32]. */
+qt_status qt_mlp_train_step(qt_ctx ctx, float* params, float* adam_m, float* adam_v,
+                            int32_t step, const float* X, const int32_t* labels, int32_t n,
+                            int32_t n_in, int32_t n_cls, float lr, float beta, float gamma,
+                            float* loss_out, float* grad_out);
+
+/* MLP inference on device features X [n][n_in].  logits: device [n][n_cls]
+ * (may be NULL).  ranks: device [n] (may be NULL): rank 8 (c + 1) of the
+ * smallest class c whose cumulative softmax probability reaches quantile,
+ * clipped to rank_cap[i] when rank_cap (device [n]) is given. */
+qt_status qt_mlp_infer(qt_ctx ctx, const float* params, const float* X, int32_t n,
+                       int32_t n_in, int32_t n_cls, float quantile, float* logits,
+                       int32_t* ranks, const int32_t* rank_cap);
+
+/* Rank log (training data): while enabled (capacity > 0), every SVD-truncated
+ * product-aware rounding inside ls_iterate appends, per bond, the features of
+ * the previous iteration's same step and the class min(ceil(r / 8), n_cls) - 1
+ * of the rank r it kept.  capacity == 0 disables and frees the log. */
+qt_status qt_ranklog_enable(qt_ctx ctx, int32_t capacity, int32_t n_cls);
+
+/* Number of logged samples (*count, host) and a copy of the first
+ * min(count, max_count) of them into caller-owned device buffers
+ * features [max_count][24] and labels [max_count] (stream-ordered; may be
+ * NULL when max_count == 0).  Errors: QT_EINVAL when the log is not enabled. */
+qt_status qt_ranklog_get(qt_ctx ctx, float* features, int32_t* labels, int32_t max_count,
+                         int32_t* count);
+
+/* Installs the predictor for QT_ROUND_LEARNED (params: device, borrowed; must
+ * stay valid while used).  quantile in (0, 1]: class choice (see qt_mlp_infer);
+ * accept_factor in (0, 2]: a learned rounding is kept iff its relative error
+ * is at most accept_factor * max(eps, e_s) (<= 0: 1).  Errors: QT_EINVAL for
+ * other values, n_cls outside [2, 32] or quantile outside (0, 1]. */
+qt_status qt_set_predictor(qt_ctx ctx, const float* params, int32_t n_cls, float quantile,
+                           float accept_factor);
+
+/* Forgets the previous-iteration features and reference errors (call before
+ * iterating a new field from its start). */
+qt_status qt_learn_reset(qt_ctx ctx);
 
 #ifdef __cplusplus
 }

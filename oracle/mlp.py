@@ -3,8 +3,8 @@
 A plain fully connected network with three hidden layers of 64 tanh units,
 written out in float64 so that finite differences can pin its gradients.  It
 maps per-bond features to a distribution over rank classes (class c means
-rank 16*(c+1), the coarse rank lattice r_c = n*r_0 with r_0 = 16 of Sec. 5.1
-of Hauck, Kabel, Gauger, arXiv 2512.07811).
+rank 8*(c+1): the coarse rank lattice r_c = n*r_0 of Sec. 5.1 of Hauck, Kabel,
+Gauger, arXiv 2512.07811, taken here with r_0 = 8 instead of the paper's 16).
 
 Loss per sample (reading: under-prediction costs a fallback, over-prediction
 only extra work, so the loss is biased upward):

@@ -6,6 +6,7 @@
 #include "kernels.h"
 #include "round.h"
 #include "sketch.h"
+#include "learned.h"
 
 namespace qt {
 
@@ -307,7 +308,19 @@ static qt_status check_status(qt_ctx ctx) {
   if (st) {
     QT_HIP(hipMemsetAsync(ctx->status, 0, sizeof(int32_t), ctx->stream));
     if (st & ST_NONFINITE) { set_error("non-finite values in a rounding"); return QT_ENUMERIC; }
-    if (st & ST_JACOBI_CAP) { set_error("Jacobi SVD reached its sweep cap"); return QT_ENUMERIC; }
+    if (st & ST_JACOBI_CAP) {
+      double d[QT_DIAG_N];
+      QT_HIP(hipMemcpyAsync(d, status_diag(ctx->status), sizeof(d), hipMemcpyDeviceToHost,
+                            ctx->stream));
+      QT_HIP(hipStreamSynchronize(ctx->stream));
+      char msg[256];
+      snprintf(msg, sizeof(msg),
+               "Jacobi SVD reached its sweep cap (order %d, ||R||_F^2 %.3e, worst off-diagonal "
+               "%.3e x tol, smallest rotated column %.3e of ||R||_F^2, %d sweeps)",
+               (int)d[0], d[1], d[2], d[3], (int)d[4]);
+      set_error(msg);
+      return QT_ENUMERIC;
+    }
   }
   return QT_OK;
 }
@@ -425,48 +438,148 @@ static qt_tt view_caps(const qt_tt& t, const std::vector<int32_t>& caps) {
   return v;
 }
 
+// One product-aware rounding step s of the iteration.  Learned path: fixed
+// ranks predicted by the MLP from the previous iteration's features; accepted
+// when the exact a-posteriori error sqrt(||x||^2 - ||x~||^2)/||x|| is at most
+// accept * max(eps, e_s), e_s = the error of the last SVD-truncated rounding
+// of this step (above eps only where the rank cap binds), otherwise redone
+// with the SVD-truncated sketch (fallback).
+static qt_status round_step(qt_ctx ctx, int step, const qt_mpo* A, const qt_tt* y,
+                            const std::vector<int32_t>& ell_plan, const qt_round_opts& base,
+                            const double* xn2, qt_tt* out, double* err_dev, uint64_t iter_id,
+                            bool learned, bool logging, bool* left_orth) {
+  const int n = y->n;
+  LearnCtx* L = ctx->learn;
+  const bool track = L && (learned || logging);
+  double* rd = track ? L->rdiag + (int64_t)step * (n + 1) * RD_MAX : nullptr;
+  const size_t mark = ctx->ws_top;
+  qt_round_opts so = base;
+  so.mode = QT_ROUND_SKETCH;
+  std::vector<int32_t> ell = ell_plan;
+  const bool use_learned = learned && L->have_prev && L->params && !L->pred_ell[step].empty();
+  bool sketch_mode = true;
+  if (use_learned) {
+    for (size_t k = 1; k + 1 < ell.size(); ++k) ell[k] = std::min(ell[k], L->pred_ell[step][k]);
+    so.mode = QT_ROUND_LEARNED;
+    sketch_mode = false;
+  }
+  QT_TRY(sround_impl(ctx, A, y, nullptr, nullptr, ell, &so, xn2, out, err_dev, nullptr,
+                     iter_id * 4 + step, nullptr, 0, 0, rd));
+  ctx->ws_top = mark;
+  if (use_learned) {
+    double err = 0.0;
+    QT_HIP(hipMemcpyAsync(&err, err_dev, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    QT_HIP(hipStreamSynchronize(ctx->stream));
+    ++L->learned_roundings;
+    const double ref = std::max(base.eps, L->ref_err[step]);
+    if (!(err <= (double)L->accept * ref)) {
+      ++L->fallbacks;
+      ell = ell_plan;
+      so.mode = QT_ROUND_SKETCH;
+      sketch_mode = true;
+      QT_TRY(sround_impl(ctx, A, y, nullptr, nullptr, ell, &so, xn2, out, err_dev, nullptr,
+                         iter_id * 4 + step + (1ull << 40), nullptr, 0, 0, rd));
+      ctx->ws_top = mark;
+    }
+  }
+  // a kept fixed-rank rounding is left-orthogonal with its weight in the last
+  // core; the SVD-truncated one is right-orthogonal with its weight in core 0
+  *left_orth = !sketch_mode;
+  if (track) learn_features(ctx, step, ell, xn2, base.eps, base.max_rank);
+  if (sketch_mode && logging) learn_log(ctx, step, out->ranks);
+  if (sketch_mode && learned) {
+    double err = 0.0;
+    QT_HIP(hipMemcpyAsync(&err, err_dev, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    QT_HIP(hipStreamSynchronize(ctx->stream));
+    L->ref_err[step] = err;
+  }
+  QT_HIP(hipGetLastError());
+  return QT_OK;
+}
+
+// After an iteration: the features just written become "previous"; the
+// learned path predicts the next iteration's ranks with the MLP.
+static qt_status learn_advance(qt_ctx ctx, bool learned, const std::vector<int32_t>* ells[4]) {
+  LearnCtx* L = ctx->learn;
+  if (!L) return QT_OK;
+  const int n = L->n;
+  const int cur = L->cur;
+  L->cur = 1 - cur;
+  L->have_prev = true;
+  if (!learned || !L->params) return QT_OK;
+  // caps = plan sketch ranks per (step, bond); features of bond k at row k-1
+  std::vector<int32_t> caps(4 * QT_MAX_CORES, 1);
+  for (int s = 0; s < 4; ++s)
+    for (int k = 1; k < n; ++k) caps[s * QT_MAX_CORES + k - 1] = (*ells[s])[k];
+  int32_t* dcap = L->pred_at(1, 0);
+  int32_t* dpred = L->pred_at(0, 0);
+  QT_HIP(hipMemcpyAsync(dcap, caps.data(), sizeof(int32_t) * caps.size(), hipMemcpyHostToDevice,
+                        ctx->stream));
+  QT_TRY(qt_mlp_infer(ctx, L->params, L->feat_at(cur, 0), 4 * QT_MAX_CORES, QT_RANK_FEATURES,
+                      L->pred_cls, L->quantile, nullptr, dpred, dcap));
+  std::vector<int32_t> pr(4 * QT_MAX_CORES);
+  QT_HIP(hipMemcpyAsync(pr.data(), dpred, sizeof(int32_t) * pr.size(), hipMemcpyDeviceToHost,
+                        ctx->stream));
+  QT_HIP(hipStreamSynchronize(ctx->stream));
+  for (int s = 0; s < 4; ++s) {
+    L->pred_ell[s].assign(n + 1, 1);
+    for (int k = 1; k < n; ++k) L->pred_ell[s][k] = pr[s * QT_MAX_CORES + k - 1];
+  }
+  return QT_OK;
+}
+
+// ||t||^2 of an orthogonalized train: the squared norm of its weight core.
+static void weight_norm2(hipStream_t st, const qt_tt& t, bool left_orth, double* out) {
+  const int n = t.n, rs = n + 1;
+  if (left_orth)
+    sumsq(st, t.batch, dref(t.ranks + n - 1, rs, t.modes[n - 1]), dconst(1),
+          (const cplx*)t.data + t.offsets[n - 1], t.inst_stride, out, 1.0);
+  else
+    sumsq(st, t.batch, dconst(1), dref(t.ranks + 1, rs, t.modes[0]), (const cplx*)t.data,
+          t.inst_stride, out, 1.0);
+}
+
 static qt_status iterate_once_sketch(qt_ctx ctx, const qt_operands* ops, qt_tt* e,
                                      const SketchPlan& P, const qt_round_opts& ro, char* bufA,
                                      char* bufB, int32_t* rA, int32_t* rB, double* dnorm,
-                                     const double* dinv, double* xn2, double* res_out,
-                                     uint64_t iter_id) {
+                                     const double* dinv, double* xn2, double* err_dev,
+                                     double* res_out, uint64_t iter_id, bool learned,
+                                     bool logging) {
   const int B = e->batch, n = e->n, rs = n + 1;
   hipStream_t st = ctx->stream;
   const size_t mark = ctx->ws_top;
-  qt_round_opts so = ro;
-  if (so.mode == QT_ROUND_SVD) so.mode = QT_ROUND_SKETCH;
+  if (learned || logging) QT_TRY(learn_ensure(ctx, n));
+  bool lo = false;
   // tau = R(k' e)
   QT_TRY(sandwich_impl(ctx, &ops->K2, e, 1.0, xn2));
   ctx->ws_top = mark;
   qt_tt t1 = P.l1.view(bufA, rA, B);
-  QT_TRY(sround_impl(ctx, &ops->Kp, e, nullptr, nullptr, P.ell1, &so, xn2, &t1, nullptr, nullptr,
-                     iter_id * 4 + 0, nullptr, 0, 0));
-  ctx->ws_top = mark;
+  QT_TRY(round_step(ctx, 0, &ops->Kp, e, P.ell1, ro, xn2, &t1, err_dev, iter_id, learned, logging,
+                    &lo));
   qt_tt t1r = view_caps(t1, P.c1r);
-  // tau^ = R(S tau);  ||S tau|| = ||tau|| = ||core 0|| (right-orthogonal train)
-  sumsq(st, B, dconst(1), dref(t1r.ranks + 1, rs, t1r.modes[0]), (const cplx*)t1r.data,
-        t1r.inst_stride, xn2, 1.0);
+  // tau^ = R(S tau);  ||S tau|| = ||tau|| (S unitary)
+  weight_norm2(st, t1r, lo, xn2);
   qt_tt t2 = P.l2.view(bufB, rB, B);
-  QT_TRY(sround_impl(ctx, &ops->S, &t1r, nullptr, nullptr, P.ell2, &so, xn2, &t2, nullptr, nullptr,
-                     iter_id * 4 + 1, nullptr, 0, 0));
-  ctx->ws_top = mark;
+  QT_TRY(round_step(ctx, 1, &ops->S, &t1r, P.ell2, ro, xn2, &t2, err_dev, iter_id, learned, logging,
+                    &lo));
   qt_tt t2r = view_caps(t2, P.c2r);
   // eps^ = R(G tau^);  ||G t||^2 = <t, G t>/k0
   QT_TRY(sandwich_impl(ctx, &ops->G, &t2r, 1.0 / ops->k0, xn2));
   ctx->ws_top = mark;
   qt_tt t3 = P.l3.view(bufA, rA, B);
-  QT_TRY(sround_impl(ctx, &ops->G, &t2r, nullptr, nullptr, P.ell3, &so, xn2, &t3, nullptr, nullptr,
-                     iter_id * 4 + 2, nullptr, 0, 0));
-  ctx->ws_top = mark;
+  QT_TRY(round_step(ctx, 2, &ops->G, &t2r, P.ell3, ro, xn2, &t3, err_dev, iter_id, learned, logging,
+                    &lo));
   qt_tt t3r = view_caps(t3, P.c3r);
   // t4 = R(S^H eps^)
-  sumsq(st, B, dconst(1), dref(t3r.ranks + 1, rs, t3r.modes[0]), (const cplx*)t3r.data,
-        t3r.inst_stride, xn2, 1.0);
+  weight_norm2(st, t3r, lo, xn2);
   qt_tt t4 = P.l4.view(bufB, rB, B);
-  QT_TRY(sround_impl(ctx, &ops->Sinv, &t3r, nullptr, nullptr, P.ell4, &so, xn2, &t4, nullptr,
-                     nullptr, iter_id * 4 + 3, nullptr, 0, 0));
-  ctx->ws_top = mark;
+  QT_TRY(round_step(ctx, 3, &ops->Sinv, &t3r, P.ell4, ro, xn2, &t4, err_dev, iter_id, learned,
+                    logging, &lo));
   qt_tt t4r = view_caps(t4, P.c4r);
+  if (learned || logging) {
+    const std::vector<int32_t>* ells[4] = {&P.ell1, &P.ell2, &P.ell3, &P.ell4};
+    QT_TRY(learn_advance(ctx, learned, ells));
+  }
   // e' = round(E - t4)
   qt_tt t5 = P.l5.view(bufA, rA, B);
   QT_TRY(add_impl(ctx, 1.0, 0.0, &ops->E, -1.0, 0.0, &t4r, &t5));
@@ -499,6 +612,9 @@ struct Solver {
   double* dnorm = nullptr;
   double* dinv = nullptr;
   double* xn2 = nullptr;
+  double* err = nullptr;
+  bool learned = false;
+  bool logging = false;
 };
 
 static qt_status solver_setup(qt_ctx ctx, const qt_operands* ops, qt_tt* e,
@@ -506,10 +622,15 @@ static qt_status solver_setup(qt_ctx ctx, const qt_operands* ops, qt_tt* e,
   const int B = e->batch, n = e->n;
   const int rmax = opts->round.max_rank;
   S.sketch = opts->round.mode != QT_ROUND_SVD;
+  S.learned = opts->round.mode == QT_ROUND_LEARNED;
+  S.logging = ctx->learn && ctx->learn->log_count && S.sketch;
   size_t bytesA, bytesB, ws;
+  if (S.learned) {
+    QT_CHECK(ctx->learn && ctx->learn->params, QT_EINVAL,
+             "solver: learned rounding needs a predictor (qt_set_predictor)");
+    QT_CHECK(e->batch == 1, QT_EINVAL, "solver: learned rounding runs one field at a time");
+  }
   if (S.sketch) {
-    QT_CHECK(opts->round.mode == QT_ROUND_SKETCH, QT_EINVAL,
-             "solver: learned rounding runs through the predictor path");
     QT_CHECK(ops->Kp.n == n && ops->K2.n == n && ops->k0 > 0.0, QT_EINVAL,
              "solver: sketch mode needs Kp, K2 and k0 operands");
     S.SP = plan_sketch(ops, e, opts->round);
@@ -520,7 +641,7 @@ static qt_status solver_setup(qt_ctx ctx, const qt_operands* ops, qt_tt* e,
   }
   ctx->ws_top = 0;
   QT_TRY(ws_reserve(ctx, bytesA + bytesB + ws + extra + sizeof(int32_t) * B * (n + 1) * 2 +
-                             sizeof(double) * B * 3 + 8 * 256));
+                             sizeof(double) * B * 4 + 8 * 256));
   S.bufA = (char*)ws_take(ctx, bytesA);
   S.bufB = (char*)ws_take(ctx, bytesB);
   S.rA = (int32_t*)ws_take(ctx, sizeof(int32_t) * B * (n + 1));
@@ -528,7 +649,8 @@ static qt_status solver_setup(qt_ctx ctx, const qt_operands* ops, qt_tt* e,
   S.dnorm = (double*)ws_take(ctx, sizeof(double) * B);
   S.dinv = (double*)ws_take(ctx, sizeof(double) * B);
   S.xn2 = (double*)ws_take(ctx, sizeof(double) * B);
-  QT_CHECK(S.bufA && S.bufB && S.rA && S.rB && S.dnorm && S.dinv && S.xn2, QT_ENOMEM,
+  S.err = (double*)ws_take(ctx, sizeof(double) * B);
+  QT_CHECK(S.bufA && S.bufB && S.rA && S.rB && S.dnorm && S.dinv && S.xn2 && S.err, QT_ENOMEM,
            "iteration workspace");
   std::vector<double> inv(B);
   const double N3 = std::ldexp(1.0, 3 * ops->L);
@@ -542,7 +664,7 @@ static qt_status solver_step(qt_ctx ctx, const qt_operands* ops, qt_tt* e, const
   if (S.sketch) {
     uint64_t id = ctx->sketch_counter++;
     return iterate_once_sketch(ctx, ops, e, S.SP, ro, S.bufA, S.bufB, S.rA, S.rB, S.dnorm, S.dinv,
-                               S.xn2, res_out, id);
+                               S.xn2, S.err, res_out, id, S.learned, S.logging);
   }
   return iterate_once(ctx, ops, e, S.P, ro, S.bufA, S.bufB, S.rA, S.rB, S.dnorm, S.dinv, res_out);
 }
@@ -562,13 +684,13 @@ qt_status qt_ctx_create(int device, void* stream, size_t ws_bytes, qt_ctx* out) 
   qt_ctx c = new qt_ctx_s();
   c->device = device;
   c->stream = (hipStream_t)stream;
-  hipError_t e = hipMalloc((void**)&c->status, sizeof(int32_t));
+  hipError_t e = hipMalloc((void**)&c->status, QT_STATUS_BYTES);
   if (e != hipSuccess) {
     delete c;
     set_error(hip_msg(e, "hipMalloc(status)"));
     return QT_ENOMEM;
   }
-  e = hipMemset(c->status, 0, sizeof(int32_t));
+  e = hipMemset(c->status, 0, QT_STATUS_BYTES);
   if (e == hipSuccess) e = hipMalloc((void**)&c->counters, sizeof(unsigned long long) * CNT_N);
   if (e == hipSuccess) e = hipMemset(c->counters, 0, sizeof(unsigned long long) * CNT_N);
   if (e != hipSuccess) {
@@ -596,6 +718,7 @@ void qt_ctx_destroy(qt_ctx ctx) {
   if (ctx->status) hipFree(ctx->status);
   if (ctx->counters) hipFree(ctx->counters);
   for (hipEvent_t e : ctx->prof.ev) hipEventDestroy(e);
+  qt_learn_free(ctx);
   delete ctx;
 }
 
@@ -628,6 +751,9 @@ qt_status qt_ctx_counters(qt_ctx ctx, int64_t* out, int32_t n, int32_t reset) {
   QT_HIP(hipMemcpyAsync(h, ctx->counters, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
   QT_HIP(hipStreamSynchronize(ctx->stream));
   for (int i = 0; i < n && i < CNT_N; ++i) out[i] = (int64_t)h[i];
+  if (ctx->learn && n > CNT_FALLBACK) out[CNT_FALLBACK] += ctx->learn->fallbacks;
+  if (ctx->learn && n > 6) out[6] += ctx->learn->learned_roundings;
+  if (reset && ctx->learn) { ctx->learn->fallbacks = 0; ctx->learn->learned_roundings = 0; }
   if (reset) QT_HIP(hipMemsetAsync(ctx->counters, 0, sizeof(h), ctx->stream));
   return QT_OK;
 }
@@ -679,6 +805,7 @@ qt_status homogenize(qt_ctx ctx, const qt_operands* ops, const qt_tt* k_sel, qt_
   double* dres = (double*)ws_take(ctx, sizeof(double) * B);
   QT_CHECK(dres, QT_ENOMEM, "homogenize: workspace");
   QT_TRY(tt_copy(ctx, &ops->E, e));
+  QT_TRY(qt_learn_reset(ctx));   // a new field: no previous-iteration features
   std::vector<double> hres(B);
   std::vector<int> done(B, 0);
   for (int b = 0; b < B; ++b) iters[b] = opts->max_iter;

@@ -90,8 +90,14 @@ __device__ inline cplx wave_sum(cplx v) {
   return v;
 }
 
-// Sum over the 16 lanes of a DPP row (all lanes of the row receive the sum):
-// quad_perm [1,0,3,2] and [2,3,0,1] add within quads, row_ror:4 and :8 across them.
+// Sum over the 16 lanes of a DPP row; every lane of the row receives the same
+// bits.  quad_perm [1,0,3,2] and [2,3,0,1] add within quads (lane i adds lane
+// i^1, then i^2), row_half_mirror pairs quad 0 with 1 and 2 with 3, row_mirror
+// pairs quad 0 with 3 and 1 with 2.  Each step adds two values that the partner
+// lane adds in the other order, so by commutativity all 16 lanes round alike.
+// (A rotate-based tree would associate differently per quad; lanes would then
+// disagree in the last bit, which lets the sign of a cancelling difference,
+// such as beta - alpha of a Jacobi pair with equal norms, differ between lanes.)
 __device__ inline double row16_sum(double v) {
 #define QT_DPP_STEP(ctrl)                                                           \
   {                                                                                 \
@@ -102,8 +108,8 @@ __device__ inline double row16_sum(double v) {
   }
   QT_DPP_STEP(0xB1)
   QT_DPP_STEP(0x4E)
-  QT_DPP_STEP(0x124)
-  QT_DPP_STEP(0x128)
+  QT_DPP_STEP(0x141)
+  QT_DPP_STEP(0x140)
 #undef QT_DPP_STEP
   return v;
 }
@@ -142,6 +148,15 @@ std::string hip_msg(hipError_t e, const char* what);
 
 // Device status word bits (written by kernels, read by the host on sync).
 enum : int32_t { ST_JACOBI_CAP = 1, ST_NONFINITE = 2 };
+// The status word is followed (at byte 16) by QT_DIAG_N doubles of diagnostics
+// written by the first kernel that raises ST_JACOBI_CAP: matrix order, squared
+// Frobenius norm, largest |b_p^H b_q| / (||b_p|| ||b_q|| tol) of the last sweep,
+// smallest rotated column norm^2 / Frobenius^2 of the last sweep, sweeps.
+constexpr int QT_DIAG_N = 5;
+constexpr size_t QT_STATUS_BYTES = 16 + 8 * QT_DIAG_N;
+__host__ __device__ inline double* status_diag(int32_t* status) {
+  return (double*)((char*)status + 16);
+}
 
 // Device event counters (int64, indices below), read with qt_ctx_counters.
 enum : int32_t { CNT_SVD_CALLS = 0, CNT_SVD_SWEEPS = 1, CNT_SKETCH_FAIL = 2, CNT_FALLBACK = 3,
@@ -163,6 +178,7 @@ extern thread_local ProfSink* g_prof;
 inline bool prof_on(int cls) { return g_prof && (g_prof->cls & cls); }
 extern thread_local unsigned long long* g_counters;
 
+struct LearnCtx;
 }  // namespace qt
 
 // Context: device, stream and a growable workspace arena.
@@ -175,6 +191,7 @@ struct qt_ctx_s {
   int32_t* status = nullptr;  // device status word
   unsigned long long* counters = nullptr;  // device [CNT_N] event counters
   qt::ProfSink prof;
+  qt::LearnCtx* learn = nullptr;   // learned-rank state (created on demand)
   int jacobi_default = 30;
   uint64_t sketch_counter = 0;  // distinct Gaussian streams across iterations
 };

@@ -338,7 +338,15 @@ __global__ __launch_bounds__(256) void k_svd_trunc(
     converged = (sh_rot == 0);
     __syncthreads();
   }
-  if (!converged && tid == 0) atomicOr(status, (int32_t)ST_JACOBI_CAP);
+  if (!converged && tid == 0) {
+    const int32_t old = atomicOr(status, (int32_t)ST_JACOBI_CAP);
+    if (!(old & ST_JACOBI_CAP)) {
+      double* d = status_diag(status);
+      d[0] = nb;
+      d[1] = d[2] = d[3] = -1.0;   // not tracked by this variant
+      d[4] = max_sweeps;
+    }
+  }
   // singular values
   for (int c = wv; c < nb; c += nw) {
     double a = 0.0;

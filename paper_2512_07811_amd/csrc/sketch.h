@@ -16,9 +16,12 @@ SketchWs sketch_ws_layout(const qt_mpo* A, const qt_tt* y, const std::vector<int
 // Randomize-then-orthogonalize of x = A (*) y with sketch cores omega (slot k at
 // om_off[k], shape (ell[k], p_k, ell[k+1]), shared by all instances).  out gets
 // left-orthogonal cores 0..n-2 and the centre in core n-1; ynorm2[b] = ||x~||^2.
+// rdiag (optional): [n+1][RD_MAX] sorted |R_jj| of the QR of Y_k written at
+// bond k+1 (instance 0), the input of the rank-predictor features.
+constexpr int RD_MAX = 128;
 qt_status sketch_impl(qt_ctx ctx, const qt_mpo* A, const qt_tt* y, const cplx* omega,
                       const std::vector<int64_t>& om_off, const std::vector<int32_t>& ell,
-                      qt_tt* out, double* ynorm2);
+                      qt_tt* out, double* ynorm2, double* rdiag = nullptr);
 
 struct SandwichWs {
   int64_t E = 1, F = 1, G = 1;
@@ -70,6 +73,6 @@ qt_status sround_impl(qt_ctx ctx, const qt_mpo* A, const qt_tt* y, const cplx* o
                       const std::vector<int64_t>* om_off_in, const std::vector<int32_t>& ell,
                       const qt_round_opts* o, const double* xn2, qt_tt* out, double* err_out,
                       int32_t* fail, uint64_t stream_id, double* svlog, int64_t svb,
-                      int64_t svi);
+                      int64_t svi, double* rdiag = nullptr);
 
 }  // namespace qt

@@ -129,9 +129,24 @@ SketchWs sketch_ws_layout(const qt_mpo* A, const qt_tt* y, const std::vector<int
   return w;
 }
 
+// |R_jj| of the sketch QR at bond k+1, sorted descending (instance 0)
+__global__ void k_rdiag(const cplx* R, int ldr, const int32_t* s_rank, double* out) {
+  __shared__ double v[RD_MAX];
+  const int s = min(*s_rank, RD_MAX);
+  for (int j = threadIdx.x; j < RD_MAX; j += blockDim.x)
+    v[j] = j < s ? sqrt(cabs2(R[(int64_t)j * ldr + j])) : 0.0;
+  __syncthreads();
+  for (int j = threadIdx.x; j < RD_MAX; j += blockDim.x) {
+    const double x = v[j];
+    int pos = 0;
+    for (int i = 0; i < RD_MAX; ++i) pos += (v[i] > x) || (v[i] == x && i < j);
+    out[pos] = x;
+  }
+}
+
 qt_status sketch_impl(qt_ctx ctx, const qt_mpo* A, const qt_tt* y, const cplx* omega,
                       const std::vector<int64_t>& om_off, const std::vector<int32_t>& ell,
-                      qt_tt* out, double* ynorm2) {
+                      qt_tt* out, double* ynorm2, double* rdiag) {
   const int n = y->n, B = y->batch;
   hipStream_t st = ctx->stream;
   SketchWs w = sketch_ws_layout(A, y, ell);
@@ -242,6 +257,7 @@ qt_status sketch_impl(qt_ctx ctx, const qt_mpo* A, const qt_tt* y, const cplx* o
     // Q_k = qr(Y_k) -> out core k, new rank s' -> ro[k+1]
     qr_auto(st, B, lk * p, lk1, dref(ro + k, rs, p), dconst(lk1), Yb, iY, Wq, iY, tau, w.tau,
             Od + out->offsets[k], out->inst_stride, Rb, w.R, ro + k + 1, rs);
+    if (rdiag) k_rdiag<<<1, 128, 0, st>>>(Rb, lk1, ro + k + 1, rdiag + (int64_t)(k + 1) * RD_MAX);
     // M_k = Q_k^H Z   (s' x R_{k+1})
     gemm_ex(st, B, 1, 1, dref(ro + k + 1, rs), dref(ry + k + 1, rs, rd1), dref(ro + k, rs, p), lk1,
             rd1 * y->cap[k + 1],

@@ -73,7 +73,7 @@ qt_status sround_impl(qt_ctx ctx, const qt_mpo* A, const qt_tt* y, const cplx* o
                       const std::vector<int64_t>* om_off_in, const std::vector<int32_t>& ell,
                       const qt_round_opts* o, const double* xn2, qt_tt* out, double* err_out,
                       int32_t* fail, uint64_t stream_id, double* svlog, int64_t svb,
-                      int64_t svi) {
+                      int64_t svi, double* rdiag) {
   const int n = y->n, B = y->batch;
   hipStream_t st = ctx->stream;
   const int lmax_cap = o->max_rank > 0 ? o->max_rank : (1 << 30);
@@ -93,7 +93,7 @@ qt_status sround_impl(qt_ctx ctx, const qt_mpo* A, const qt_tt* y, const cplx* o
   double* es2 = (double*)ws_take(ctx, sizeof(double) * B);
   int32_t* rkl = (int32_t*)ws_take(ctx, sizeof(int32_t) * B * (n + 1));
   QT_CHECK(yn2 && delta && disc2 && es2 && rkl, QT_ENOMEM, "sketch rounding: workspace too small");
-  QT_TRY(sketch_impl(ctx, A, y, omega, *om_off, ell, out, yn2));
+  QT_TRY(sketch_impl(ctx, A, y, omega, *om_off, ell, out, yn2, rdiag));
   k_budget<<<(B + 127) / 128, 128, 0, st>>>(B, n - 1, o->eps, xn2, yn2, delta, disc2, es2, fail,
                                             ctx->counters);
   if (o->mode == QT_ROUND_SKETCH && n > 1) {

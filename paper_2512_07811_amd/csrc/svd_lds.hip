@@ -29,6 +29,7 @@ __global__ __launch_bounds__(1024) void k_jacobi_lds(
   __shared__ int perm[SL_NB];
   __shared__ double red[16];
   __shared__ int sh_rot, sh_l;
+  __shared__ unsigned long long sh_worst, sh_small;   // bit patterns of positive doubles
   const int b = blockIdx.x;
   const int m = dimv(Md, b), nc = dimv(Cd, b);
   const bool tall = m >= nc;
@@ -56,7 +57,11 @@ __global__ __launch_bounds__(1024) void k_jacobi_lds(
   // each 16-lane row group owns one pair per round; sums reduce over the group by DPP
   for (int sweep = 0; sweep < max_sweeps && !converged; ++sweep) {
     ++sweeps_done;
-    if (tid == 0) sh_rot = 0;
+    if (tid == 0) {
+      sh_rot = 0;
+      sh_worst = 0ull;
+      sh_small = (unsigned long long)__double_as_longlong(1.0);
+    }
     __syncthreads();
     for (int r = 0; r < nbp - 1; ++r) {
       for (int pi0 = 0; pi0 < nbp / 2; pi0 += ngrp) {
@@ -102,7 +107,12 @@ __global__ __launch_bounds__(1024) void k_jacobi_lds(
             vp[i] = csub(cscale(x, c), cmul(sec, y));
             vq[i] = cadd(cmul(se, x), cscale(y, c));
           }
-          if (g == 0) sh_rot = 1;
+          if (g == 0) {
+            sh_rot = 1;
+            atomicMax(&sh_worst, (unsigned long long)__double_as_longlong(
+                                     gabs / (jtol * sqrt(al * be))));
+            atomicMin(&sh_small, (unsigned long long)__double_as_longlong(fmin(al, be) / fro));
+          }
         }
       }
       __syncthreads();
@@ -110,7 +120,17 @@ __global__ __launch_bounds__(1024) void k_jacobi_lds(
     converged = (sh_rot == 0);
     __syncthreads();
   }
-  if (!converged && tid == 0) atomicOr(status, (int32_t)ST_JACOBI_CAP);
+  if (!converged && tid == 0) {
+    const int32_t old = atomicOr(status, (int32_t)ST_JACOBI_CAP);
+    if (!(old & ST_JACOBI_CAP)) {
+      double* d = status_diag(status);
+      d[0] = nb;
+      d[1] = fro;
+      d[2] = __longlong_as_double((long long)sh_worst);
+      d[3] = __longlong_as_double((long long)sh_small);
+      d[4] = sweeps_done;
+    }
+  }
   if (tid == 0 && counters) {
     atomicAdd(counters + CNT_SVD_CALLS, 1ull);
     atomicAdd(counters + CNT_SVD_SWEEPS, (unsigned long long)sweeps_done);

@@ -161,3 +161,16 @@ def graded_tt(modes, ranks, decay: float, seed: int, is_complex: bool = True):
         w = decay ** np.arange(ranks[k + 1])
         cores.append(c * w[None, None, :] / math.sqrt(ranks[k] * p))
     return cores
+
+
+def mlp_init(n_in: int, n_cls: int, seed: int, hidden: int = 64, layers: int = 3):
+    """Initial MLP weights: W_i ~ N(0, 1/fan_in) of shape (fan_in, fan_out), b_i = 0.
+
+    Returned as the list [W0, b0, W1, b1, ...] in float64."""
+    g = rng(seed)
+    dims = [n_in] + [hidden] * layers + [n_cls]
+    out = []
+    for i in range(len(dims) - 1):
+        out.append(g.standard_normal((dims[i], dims[i + 1])) * math.sqrt(1.0 / dims[i]))
+        out.append(np.zeros(dims[i + 1]))
+    return out

@@ -24,7 +24,8 @@ PREC_F64, PREC_F32 = 0, 1
 EXPORTS = ["qt_ctx_create", "qt_ctx_destroy", "qt_last_error", "qt_ctx_sync",
            "qt_ctx_counters", "qt_ctx_profile", "qt_ctx_profile_read", "tt_hadamard",
            "tt_mpo_apply", "tt_add", "tt_round", "tt_dot", "tt_sketch_round", "tt_sandwich",
-           "ls_iterate", "homogenize"]
+           "ls_iterate", "homogenize", "qt_mlp_num_params", "qt_mlp_train_step", "qt_mlp_infer",
+           "qt_ranklog_enable", "qt_ranklog_get", "qt_set_predictor", "qt_learn_reset"]
 
 
 class QtError(RuntimeError):
@@ -96,6 +97,15 @@ def load_library(path: str = LIB_PATH):
     lib.homogenize.argtypes = [vp, C.POINTER(Operands), C.POINTER(TTDesc), C.POINTER(TTDesc),
                                C.POINTER(SolveOpts), C.POINTER(C.c_double), C.POINTER(C.c_int32),
                                C.POINTER(C.c_double)]
+    lib.qt_mlp_num_params.argtypes = [i32, i32]
+    f32 = C.c_float
+    lib.qt_mlp_train_step.argtypes = [vp, vp, vp, vp, i32, vp, vp, i32, i32, i32, f32, f32, f32,
+                                      vp, vp]
+    lib.qt_mlp_infer.argtypes = [vp, vp, vp, i32, i32, i32, f32, vp, vp, vp]
+    lib.qt_ranklog_enable.argtypes = [vp, i32, i32]
+    lib.qt_ranklog_get.argtypes = [vp, vp, vp, i32, C.POINTER(C.c_int32)]
+    lib.qt_set_predictor.argtypes = [vp, vp, i32, f32, f32]
+    lib.qt_learn_reset.argtypes = [vp]
     for name in EXPORTS:
         if name not in ("qt_ctx_destroy", "qt_last_error"):
             getattr(lib, name).restype = C.c_int32
@@ -165,7 +175,8 @@ class Context:
         out = (C.c_int64 * 8)()
         _check(self.lib.qt_ctx_counters(self.h, out, 8, 1 if reset else 0))
         return {"svd_calls": out[0], "svd_sweeps": out[1], "sketch_over_budget": out[2],
-                "learned_fallbacks": out[3], "gemm_flops": out[4], "gemm_bytes": out[5]}
+                "learned_fallbacks": out[3], "gemm_flops": out[4], "gemm_bytes": out[5],
+                "learned_roundings": out[6]}
 
     PROF_GEMM, PROF_QR, PROF_SVD = 1, 2, 4
 
@@ -442,3 +453,65 @@ def homogenize(ctx: Context, ops: DeviceOperands, e: DeviceTT, opts: SolveOpts):
                                   its.ctypes.data_as(C.POINTER(C.c_int32)),
                                   res.ctypes.data_as(C.POINTER(C.c_double))))
     return A, its, res, s
+
+
+# ---------------------------------------------------------------------------
+# Learned-rank rounding: MLP kernels, rank logs and the predictor.
+
+RANK_FEATURES = 24
+
+
+def mlp_num_params(n_in: int, n_cls: int) -> int:
+    return int(load_library().qt_mlp_num_params(n_in, n_cls))
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def mlp_train_step(ctx: Context, params, m, v, step: int, X, labels, n_cls: int, lr: float,
+                   beta: float, gamma: float, loss=None, grad=None):
+    """One full-batch MLP step on device tensors (params/m/v float32, X [n, F] float32,
+    labels [n] int32); loss (float32 [1]) and grad (float32 [P]) are optional outputs."""
+    n, F = X.shape
+    _check(ctx.lib.qt_mlp_train_step(ctx.h, _ptr(params), _ptr(m), _ptr(v), step, _ptr(X),
+                                     _ptr(labels), n, F, n_cls, lr, beta, gamma, _ptr(loss),
+                                     _ptr(grad)))
+
+
+def mlp_infer(ctx: Context, params, X, n_cls: int, quantile: float = 0.9, rank_cap=None):
+    """(logits [n, n_cls] float32, ranks [n] int32) on the device."""
+    torch = _torch()
+    n, F = X.shape
+    logits = torch.empty((n, n_cls), dtype=torch.float32, device=X.device)
+    ranks = torch.empty(n, dtype=torch.int32, device=X.device)
+    _check(ctx.lib.qt_mlp_infer(ctx.h, _ptr(params), _ptr(X), n, F, n_cls, quantile,
+                                _ptr(logits), _ptr(ranks), _ptr(rank_cap)))
+    return logits, ranks
+
+
+def ranklog_enable(ctx: Context, capacity: int, n_cls: int):
+    _check(ctx.lib.qt_ranklog_enable(ctx.h, capacity, n_cls))
+
+
+def ranklog_get(ctx: Context):
+    """The logged (features [count, 24] float32, labels [count] int32) as device tensors."""
+    torch = _torch()
+    cnt = C.c_int32()
+    _check(ctx.lib.qt_ranklog_get(ctx.h, None, None, 0, C.byref(cnt)))
+    n = cnt.value
+    X = torch.empty((n, RANK_FEATURES), dtype=torch.float32, device="cuda")
+    Y = torch.empty(n, dtype=torch.int32, device="cuda")
+    if n:
+        _check(ctx.lib.qt_ranklog_get(ctx.h, _ptr(X), _ptr(Y), n, C.byref(cnt)))
+        ctx.sync()
+    return X, Y
+
+
+def set_predictor(ctx: Context, params, n_cls: int, quantile: float = 0.9,
+                  accept_factor: float = 1.0):
+    _check(ctx.lib.qt_set_predictor(ctx.h, _ptr(params), n_cls, quantile, accept_factor))
+
+
+def learn_reset(ctx: Context):
+    _check(ctx.lib.qt_learn_reset(ctx.h))

@@ -171,3 +171,22 @@ def test_homogenize_boxes_matches_oracle_tt(q, ctx):
     A_ref, its_ref = ls_tt.effective_tensor(oprob, [0], eps=1e-6, tol=1e-9, max_iter=300)
     assert abs(its[0] - its_ref[0]) <= 1
     assert np.max(np.abs(A[0] - A_ref[:, 0])) < 1e-8 * abs(A_ref[0, 0])
+
+
+@pytest.mark.parametrize("mode", ["svd", "sketch"])
+def test_jacobi_converges_on_symmetric_cell(q, ctx, mode):
+    # A centred sphere's fields have bond spectra with (nearly) repeated singular
+    # values from the cube symmetries.  One-sided Jacobi must converge on them:
+    # the rotation of a pair with almost equal norms depends on the sign of a
+    # cancelling difference, which every lane of a pair must evaluate alike.
+    from paper_2512_07811_amd import operands as P
+    kvox = I.sphere(4, 0.2, k_in=10.0, k_out=1.0)
+    prob = P.build_problem(kvox=kvox, k0=5.5)
+    ops, e = P.upload(prob, [[1.0, 0.0, 0.0]], 64)
+    m = q.ROUND_SVD if mode == "svd" else q.ROUND_SKETCH
+    ctx.counters(reset=True)
+    A, its, res, st = q.homogenize(ctx, ops, e, q.solve_opts(1e-8, 64, tol=1e-7, max_iter=4,
+                                                             mode=m, oversample=4, seed=3))
+    cnt = ctx.counters(reset=True)
+    assert cnt["svd_calls"] > 0
+    assert cnt["svd_sweeps"] / cnt["svd_calls"] < 16
