@@ -7,7 +7,11 @@ FP64 residual) on one batch of fields, entirely in the HIP library.
 Default workload: 256^3 periodic cell (L = 8, 24 spatial QTT cores plus the
 component core), matrix k = 1 with a centred spherical inclusion of volume
 fraction 0.2 and k = 100, reference k0 = 50.5, load E = e_x, truncation
-tolerance 1e-6, field rank cap 64, product-aware randomized rounding.
+tolerance 1e-6, field rank cap 64, learned-rank rounding: the rank predictor is
+trained on the device from the rank log of SVD-truncated iterations run before
+the timed window (part of the warm-up), then the timed window runs the learned
+path; the same window is re-run with the SVD-truncated product-aware rounding
+from the same field for the ablation figures.
 
 Prints one JSON line (see the keys below).
 """
@@ -71,7 +75,11 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="sphere256", choices=sorted(CONFIGS))
-    ap.add_argument("--mode", default="sketch", choices=["sketch", "svd"])
+    ap.add_argument("--mode", default="learned", choices=["learned", "sketch", "svd"])
+    ap.add_argument("--log-iters", type=int, default=8,
+                    help="SVD-truncated iterations logged for training the rank predictor")
+    ap.add_argument("--epochs", type=int, default=400)
+    ap.add_argument("--no-ablation", action="store_true")
     ap.add_argument("--oversample", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
@@ -96,14 +104,33 @@ def main():
           f"G max rank {max(c.shape[0] for c in prob['G'])}", file=sys.stderr, flush=True)
     ctx = qtt.Context(0)
     ops, e = P.upload(prob, cfg["loads"], cfg["rmax"])
-    mode = qtt.ROUND_SKETCH if args.mode == "sketch" else qtt.ROUND_SVD
+    mode = {"learned": qtt.ROUND_LEARNED, "sketch": qtt.ROUND_SKETCH, "svd": qtt.ROUND_SVD}[args.mode]
     opts = qtt.solve_opts(cfg["eps"], cfg["rmax"], mode=mode, oversample=args.oversample, seed=17)
+    sk_opts = qtt.solve_opts(cfg["eps"], cfg["rmax"], mode=qtt.ROUND_SKETCH,
+                             oversample=args.oversample, seed=17)
     e = qtt.DeviceTT.from_cores([P.mean_field(np.asarray(E), ops.L) for E in cfg["loads"]], e.cap)
+    train_info = None
+    if args.mode == "learned":
+        from paper_2512_07811_amd import learned
+        t0 = time.perf_counter()
+        qtt.ranklog_enable(ctx, 1 << 20, learned.N_CLS)
+        qtt.ls_iterate(ctx, ops, e, sk_opts, args.log_iters)
+        X, Y = qtt.ranklog_get(ctx)
+        qtt.ranklog_enable(ctx, 0, learned.N_CLS)
+        pred = learned.RankPredictor(ctx, seed=5)
+        hist = pred.train(X, Y, epochs=args.epochs)
+        pred.install()
+        train_info = {"samples": int(X.shape[0]), "epochs": args.epochs,
+                      "loss_first": float(hist[0]), "loss_last": float(hist[-1]),
+                      "log_and_train_s": time.perf_counter() - t0}
+        print(f"[bench] predictor trained on {X.shape[0]} samples, loss {hist[0]:.3f} -> "
+              f"{hist[-1]:.4f}", file=sys.stderr, flush=True)
     if args.warmup:
         qtt.ls_iterate(ctx, ops, e, opts, args.warmup)
     ctx.sync()
     torch.cuda.synchronize()
     print(f"[bench] warmup done, ranks {e.rank_array()[0].tolist()}", file=sys.stderr, flush=True)
+    snap = (e.data.clone(), e.ranks.clone())
     ctx.counters(reset=True)
     ctx.profile(ctx.PROF_GEMM | ctx.PROF_QR | ctx.PROF_SVD)
     torch.cuda.synchronize()
@@ -115,16 +142,39 @@ def main():
     kernel_ms, kernel_launches = ctx.profile_read()
     ctx.profile(0)
     cnt = ctx.counters()
-    # per-class split: time the classes one at a time over one more step each
-    split = {}
+    # per-class split: time the classes one at a time over one more step each,
+    # with that step's own algorithmic GEMM flops and bytes
+    split, step_cnt = {}, {}
     for name, cls in (("gemm", ctx.PROF_GEMM), ("qr", ctx.PROF_QR), ("svd", ctx.PROF_SVD)):
+        c0 = ctx.counters()
         ctx.profile(cls)
         qtt.ls_iterate(ctx, ops, e, opts, 1)
         split[name] = ctx.profile_read()
+        c1 = ctx.counters()
+        step_cnt[name] = {k: c1[k] - c0[k] for k in c1}
     ctx.profile(0)
-    cnt1 = ctx.counters(reset=True)
-    gemm_flops_step = (cnt1["gemm_flops"] - cnt["gemm_flops"])
-    gemm_bytes_step = (cnt1["gemm_bytes"] - cnt["gemm_bytes"])
+    ctx.counters(reset=True)
+    gemm_flops_step = step_cnt["gemm"]["gemm_flops"]
+    gemm_bytes_step = step_cnt["gemm"]["gemm_bytes"]
+    ablation = None
+    if args.mode == "learned" and not args.no_ablation:
+        # the same window from the same field with the SVD-truncated rounding
+        e.data.copy_(snap[0])
+        e.ranks.copy_(snap[1])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        res_sk = qtt.ls_iterate(ctx, ops, e, sk_opts, args.steps)
+        ctx.sync()
+        torch.cuda.synchronize()
+        dt_sk = time.perf_counter() - t1
+        cnt_sk = ctx.counters(reset=True)
+        r_l = res.cpu().numpy()[:, 0]
+        r_s = res_sk.cpu().numpy()[:, 0]
+        ablation = {"sketch_svd_iters_per_s": args.steps * len(cfg["loads"]) / dt_sk,
+                    "speedup_learned_over_sketch_svd": dt_sk / dt,
+                    "gemm_flops_ratio": cnt["gemm_flops"] / max(cnt_sk["gemm_flops"], 1),
+                    "svd_calls_learned": cnt["svd_calls"], "svd_calls_sketch": cnt_sk["svd_calls"],
+                    "max_residual_rel_diff": float(np.max(np.abs(r_l - r_s) / r_s))}
     B = len(cfg["loads"])
     value = args.steps * B / dt
     print(f"[bench] {args.steps} steps in {dt:.3f}s; residuals {res.cpu().numpy()[:, 0].tolist()}",
@@ -136,6 +186,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.config, "L": cfg["L"], "grid": f"{2 ** cfg['L']}^3",
                    "rounding": args.mode, "eps": cfg["eps"], "max_rank": cfg["rmax"],
+                   "oversample": args.oversample,
                    "batch": B, "parallelism": "single GPU"},
     }
     dom = max(split, key=lambda k: split[k][0])
@@ -153,10 +204,16 @@ def main():
         "dominant_class": dom,
     }
     out["counters"] = {"svd_calls_per_step": cnt["svd_calls"] / args.steps,
+                       "learned_roundings": cnt["learned_roundings"],
+                       "learned_fallbacks": cnt["learned_fallbacks"],
                        "jacobi_sweeps_per_svd": (cnt["svd_sweeps"] / cnt["svd_calls"]
                                                  if cnt["svd_calls"] else None),
                        "sketch_over_budget": cnt["sketch_over_budget"],
                        "timed_kernel_ms": kernel_ms, "timed_launches": kernel_launches}
+    if train_info:
+        out["predictor"] = train_info
+    if ablation:
+        out["ablation"] = ablation
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, kvox, args.cpu_budget)
     ctx.close()

@@ -13,6 +13,7 @@ namespace qt {
 static thread_local std::string g_last_error;
 thread_local ProfSink* g_prof = nullptr;
 thread_local unsigned long long* g_counters = nullptr;
+thread_local SplitKBuf g_splitk;
 
 void ProfSink::begin() {
   if (used + 2 > ev.size()) {
@@ -38,6 +39,7 @@ void enter(qt_ctx ctx) {
   ctx->prof.stream = ctx->stream;
   g_prof = ctx->prof.cls ? &ctx->prof : nullptr;
   g_counters = ctx->counters;
+  g_splitk = ctx->splitk;
 }
 
 void set_error(const std::string& msg) { g_last_error = msg; }
@@ -693,10 +695,16 @@ qt_status qt_ctx_create(int device, void* stream, size_t ws_bytes, qt_ctx* out) 
   e = hipMemset(c->status, 0, QT_STATUS_BYTES);
   if (e == hipSuccess) e = hipMalloc((void**)&c->counters, sizeof(unsigned long long) * CNT_N);
   if (e == hipSuccess) e = hipMemset(c->counters, 0, sizeof(unsigned long long) * CNT_N);
+  if (e == hipSuccess) {
+    e = hipMalloc((void**)&c->splitk.p, sizeof(cplx) * QT_SPLITK_ELEMS);
+    if (e == hipSuccess) c->splitk.elems = QT_SPLITK_ELEMS;
+  }
   if (e != hipSuccess) {
     hipFree(c->status);
+    if (c->counters) hipFree(c->counters);
+    if (c->splitk.p) hipFree(c->splitk.p);
     delete c;
-    set_error(hip_msg(e, "hipMemset(status)"));
+    set_error(hip_msg(e, "qt_ctx_create: device allocations"));
     return QT_EHIP;
   }
   if (ws_bytes) {
@@ -717,6 +725,7 @@ void qt_ctx_destroy(qt_ctx ctx) {
   if (ctx->ws) hipFree(ctx->ws);
   if (ctx->status) hipFree(ctx->status);
   if (ctx->counters) hipFree(ctx->counters);
+  if (ctx->splitk.p) hipFree(ctx->splitk.p);
   for (hipEvent_t e : ctx->prof.ev) hipEventDestroy(e);
   qt_learn_free(ctx);
   delete ctx;

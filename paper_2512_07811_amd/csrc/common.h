@@ -177,6 +177,13 @@ struct ProfSink {
 extern thread_local ProfSink* g_prof;
 inline bool prof_on(int cls) { return g_prof && (g_prof->cls & cls); }
 extern thread_local unsigned long long* g_counters;
+// Split-K partial tiles of the structured GEMM (owned by the context).
+struct SplitKBuf {
+  cplx* p = nullptr;
+  int64_t elems = 0;
+};
+extern thread_local SplitKBuf g_splitk;
+constexpr int64_t QT_SPLITK_ELEMS = int64_t(1) << 22;   // 64 MiB of complex doubles
 
 struct LearnCtx;
 }  // namespace qt
@@ -190,6 +197,7 @@ struct qt_ctx_s {
   size_t ws_top = 0;
   int32_t* status = nullptr;  // device status word
   unsigned long long* counters = nullptr;  // device [CNT_N] event counters
+  qt::SplitKBuf splitk;                    // GEMM split-K partials
   qt::ProfSink prof;
   qt::LearnCtx* learn = nullptr;   // learned-rank state (created on demand)
   int jacobi_default = 30;

@@ -1,17 +1,38 @@
 // General strided, batched complex-double GEMM used by the structured
 // (product-aware) contractions.  Every size and stride may depend on device
 // ranks, so the launch grid covers capacities and idle tiles exit at once.
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace qt {
 
 constexpr int XT_M = 64, XT_N = 64, XT_K = 16;
+constexpr int XT_PAD = 16;   // LDS row pitch 80 doubles: 16-lane groups of one read land 32 banks apart
 
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// v_mfma_f64_16x16x4f64 lane layout (gfx950): lane l supplies A[l % 16][l / 16]
+// and B[l / 16][l % 16] of the 16x4 and 4x16 operands; accumulator register r
+// of lane l holds D[4 r + l / 16][l % 16].
+__device__ inline dbl4 mfma16(double a, double b, dbl4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// One 64 x 64 complex output tile per workgroup of 4 waves (2 x 2 waves of
+// 32 x 32, each 2 x 2 MFMA tiles of 16 x 16).  Complex products as four real
+// MFMAs into a real and an imaginary accumulator:
+//   Re += Ar Br + (-Ai) Bi,   Im += Ar Bi + Ai Br.
+// The next K panel is fetched into registers while the current one is in use.
+// Split-K (gridDim.z = splits > 1): workgroup z takes K range
+// [z kper, (z + 1) kper) with kper a multiple of the panel depth and writes its
+// raw partial tile to part[z][item][Mcap][Ncap]; k_splitk_sum finishes.
 template <bool CA, bool CB>
 __global__ __launch_bounds__(256) void k_gemm_ex(int nb1, int nb2, int ntn, Dim Md, Dim Nd,
                                                  Dim Kd, Mat A, Mat B, Mat C, cplx alpha,
                                                  int accumulate, Dim lim1,
-                                                 unsigned long long* counters) {
+                                                 unsigned long long* counters, cplx* part,
+                                                 int Mcap, int Ncap, int64_t items) {
   const int nbt = nb1 * nb2;
   const int tn = blockIdx.x % ntn;
   const int z = blockIdx.x / ntn;
@@ -21,7 +42,14 @@ __global__ __launch_bounds__(256) void k_gemm_ex(int nb1, int nb2, int ntn, Dim 
   const int M = dimv(Md, b), N = dimv(Nd, b), K = dimv(Kd, b);
   const int m0 = blockIdx.y * XT_M, n0 = tn * XT_N;
   if (m0 >= M || n0 >= N || b1 >= dimv(lim1, b)) return;
-  if (counters && m0 == 0 && n0 == 0 && threadIdx.x == 0 && K > 0) {
+  const int splits = gridDim.z, sk = blockIdx.z;
+  int kbeg = 0, kend = K;
+  if (splits > 1) {
+    const int kper = (((K + splits - 1) / splits) + XT_K - 1) / XT_K * XT_K;
+    kbeg = min(K, sk * kper);
+    kend = min(K, kbeg + kper);
+  }
+  if (counters && m0 == 0 && n0 == 0 && sk == 0 && threadIdx.x == 0 && K > 0) {
     // algorithmic work of this product: 8 real flops per complex MAC and the
     // compulsory traffic of reading A, B and writing C once
     atomicAdd(counters + CNT_GEMM_FLOPS, 8ull * M * N * K);
@@ -36,93 +64,166 @@ __global__ __launch_bounds__(256) void k_gemm_ex(int nb1, int nb2, int ntn, Dim 
   const int64_t crs = strv(C.rs, b), ccs = strv(C.cs, b);
   const bool a_kfast = (acs == 1);
   const bool b_nfast = (bcs == 1);
-  __shared__ cplx As[XT_K][XT_M + 1];
-  __shared__ cplx Bs[XT_K][XT_N + 1];
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  cplx acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = make_double2(0.0, 0.0);
+  __shared__ double Ar[XT_K][XT_M + XT_PAD], Ai[XT_K][XT_M + XT_PAD];
+  __shared__ double Br[XT_K][XT_N + XT_PAD], Bi[XT_K][XT_N + XT_PAD];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
 
-  for (int k0 = 0; k0 < K; k0 += XT_K) {
+  // element e of this thread's share of a panel: (row/col, k) inside the tile
+  int am[4], ak[4], bk[4], bn[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int idx = tid + 256 * e;
+    if (a_kfast) { am[e] = idx >> 4; ak[e] = idx & 15; }
+    else { ak[e] = idx >> 6; am[e] = idx & 63; }
+    if (b_nfast) { bk[e] = idx >> 6; bn[e] = idx & 63; }
+    else { bn[e] = idx >> 4; bk[e] = idx & 15; }
+  }
+  cplx ra[4], rb[4];
+  auto fetch = [&](int k0) {
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      int idx = tid + 256 * e;
-      int mm, kk;
-      if (a_kfast) { mm = idx >> 4; kk = idx & 15; }
-      else { kk = idx >> 6; mm = idx & 63; }
-      int gm = m0 + mm, gk = k0 + kk;
+      const int gm = m0 + am[e], gk = k0 + ak[e];
       cplx v = make_double2(0.0, 0.0);
-      if (gm < M && gk < K) {
+      if (gm < M && gk < kend) {
         v = Ab[gm * ars + gk * acs];
         if (CA) v = cconj(v);
       }
-      As[kk][mm] = v;
+      ra[e] = v;
+      const int gk2 = k0 + bk[e], gn = n0 + bn[e];
+      cplx u = make_double2(0.0, 0.0);
+      if (gk2 < kend && gn < N) {
+        u = Bb[gk2 * brs + gn * bcs];
+        if (CB) u = cconj(u);
+      }
+      rb[e] = u;
     }
+  };
+  dbl4 cre[2][2], cim[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      cre[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+      cim[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+    }
+  fetch(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += XT_K) {
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      int idx = tid + 256 * e;
-      int kk, nn;
-      if (b_nfast) { kk = idx >> 6; nn = idx & 63; }
-      else { nn = idx >> 4; kk = idx & 15; }
-      int gk = k0 + kk, gn = n0 + nn;
-      cplx v = make_double2(0.0, 0.0);
-      if (gk < K && gn < N) {
-        v = Bb[gk * brs + gn * bcs];
-        if (CB) v = cconj(v);
+      Ar[ak[e]][am[e]] = ra[e].x;
+      Ai[ak[e]][am[e]] = ra[e].y;
+      Br[bk[e]][bn[e]] = rb[e].x;
+      Bi[bk[e]][bn[e]] = rb[e].y;
+    }
+    __syncthreads();
+    if (k0 + XT_K < kend) fetch(k0 + XT_K);
+#pragma unroll
+    for (int kc = 0; kc < XT_K; kc += 4) {
+      double far[2], fai[2], fbr[2], fbi[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        far[t] = Ar[kc + lk][wm + 16 * t + li];
+        fai[t] = Ai[kc + lk][wm + 16 * t + li];
+        fbr[t] = Br[kc + lk][wn + 16 * t + li];
+        fbi[t] = Bi[kc + lk][wn + 16 * t + li];
       }
-      Bs[kk][nn] = v;
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int kk = 0; kk < XT_K; ++kk) {
-      cplx a[4], bb[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty + 16 * i];
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bb[j] = Bs[kk][tx + 16 * j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) cfma(acc[i][j], a[i], bb[j]);
+        for (int j = 0; j < 2; ++j) {
+          cre[i][j] = mfma16(far[i], fbr[j], cre[i][j]);
+          cre[i][j] = mfma16(-fai[i], fbi[j], cre[i][j]);
+          cim[i][j] = mfma16(far[i], fbi[j], cim[i][j]);
+          cim[i][j] = mfma16(fai[i], fbr[j], cim[i][j]);
+        }
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    int gm = m0 + ty + 16 * i;
-    if (gm >= M) continue;
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      int gn = n0 + tx + 16 * j;
-      if (gn >= N) continue;
-      cplx v = cmul(alpha, acc[i][j]);
-      cplx* o = Cb + gm * crs + gn * ccs;
-      if (accumulate) v = cadd(v, *o);
-      *o = v;
-    }
-  }
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gm = m0 + wm + 16 * i + 4 * r + lk;
+        const int gn = n0 + wn + 16 * j + li;
+        if (gm >= M || gn >= N) continue;
+        if (splits > 1) {
+          if (gm >= Mcap || gn >= Ncap) continue;
+          part[((int64_t)sk * items + z) * Mcap * Ncap + (int64_t)gm * Ncap + gn] =
+              make_double2(cre[i][j][r], cim[i][j][r]);
+          continue;
+        }
+        cplx v = cmul(alpha, make_double2(cre[i][j][r], cim[i][j][r]));
+        cplx* o = Cb + gm * crs + gn * ccs;
+        if (accumulate) v = cadd(v, *o);
+        *o = v;
+      }
+}
+
+// Sums the split-K partials of every output element in split order.
+__global__ void k_splitk_sum(int nb1, int nb2, Dim Md, Dim Nd, Mat C, cplx alpha, int accumulate,
+                             Dim lim1, const cplx* __restrict__ part, int splits, int Mcap,
+                             int Ncap, int64_t items) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t tile = (int64_t)Mcap * Ncap;
+  if (t >= items * tile) return;
+  const int64_t z = t / tile;
+  const int gm = (int)((t % tile) / Ncap), gn = (int)(t % Ncap);
+  const int nbt = nb1 * nb2;
+  const int b = (int)(z / nbt), rem = (int)(z % nbt);
+  const int b1 = rem / nb2, b2 = rem % nb2;
+  if (gm >= dimv(Md, b) || gn >= dimv(Nd, b) || b1 >= dimv(lim1, b)) return;
+  cplx acc = make_double2(0.0, 0.0);
+  for (int s = 0; s < splits; ++s) acc = cadd(acc, part[((int64_t)s * items + z) * tile + (int64_t)gm * Ncap + gn]);
+  cplx* Cb = C.base + b * C.inst + strv(C.off, b) + b1 * strv(C.s1, b) + b2 * strv(C.s2, b);
+  cplx* o = Cb + gm * strv(C.rs, b) + gn * strv(C.cs, b);
+  cplx v = cmul(alpha, acc);
+  if (accumulate) v = cadd(v, *o);
+  *o = v;
 }
 
 void gemm_ex(hipStream_t st, int batch, int nb1, int nb2, Dim M, Dim N, Dim K, int Mcap, int Ncap,
-             Mat A, bool conjA, Mat B, bool conjB, Mat C, cplx alpha, bool accumulate, Dim lim1) {
+             Mat A, bool conjA, Mat B, bool conjB, Mat C, cplx alpha, bool accumulate, Dim lim1,
+             int64_t Kcap) {
   if (Mcap <= 0 || Ncap <= 0 || batch <= 0 || nb1 <= 0 || nb2 <= 0) return;
   const int ntn = (Ncap + XT_N - 1) / XT_N;
-  const int64_t gx = (int64_t)ntn * batch * nb1 * nb2;
-  dim3 grid((unsigned)gx, (Mcap + XT_M - 1) / XT_M, 1);
+  const int mtn = (Mcap + XT_M - 1) / XT_M;
+  const int64_t items = (int64_t)batch * nb1 * nb2;
+  const int64_t gx = (int64_t)ntn * items;
+  // split K when the output has too few tiles to fill the chip and K is long
+  int splits = 1;
+  const int64_t tiles = gx * mtn;
+  if (Kcap >= 1024 && tiles < 256 && g_splitk.p) {
+    splits = (int)std::min<int64_t>({(Kcap + 255) / 256, (512 + tiles - 1) / tiles, 64});
+    const int64_t per = items * Mcap * Ncap;
+    while (splits > 1 && splits * per > g_splitk.elems) --splits;
+  }
+  dim3 grid((unsigned)gx, mtn, splits);
   const int acc = accumulate ? 1 : 0;
   unsigned long long* cnt = g_counters;
+  cplx* part = g_splitk.p;
   const bool prof = prof_on(PROF_GEMM);
   if (prof) g_prof->begin();
   if (!conjA && !conjB)
-    k_gemm_ex<false, false><<<grid, 256, 0, st>>>(nb1, nb2, ntn, M, N, K, A, B, C, alpha, acc, lim1, cnt);
+    k_gemm_ex<false, false><<<grid, 256, 0, st>>>(nb1, nb2, ntn, M, N, K, A, B, C, alpha, acc, lim1,
+                                                  cnt, part, Mcap, Ncap, items);
   else if (conjA && !conjB)
-    k_gemm_ex<true, false><<<grid, 256, 0, st>>>(nb1, nb2, ntn, M, N, K, A, B, C, alpha, acc, lim1, cnt);
+    k_gemm_ex<true, false><<<grid, 256, 0, st>>>(nb1, nb2, ntn, M, N, K, A, B, C, alpha, acc, lim1,
+                                                 cnt, part, Mcap, Ncap, items);
   else if (!conjA && conjB)
-    k_gemm_ex<false, true><<<grid, 256, 0, st>>>(nb1, nb2, ntn, M, N, K, A, B, C, alpha, acc, lim1, cnt);
+    k_gemm_ex<false, true><<<grid, 256, 0, st>>>(nb1, nb2, ntn, M, N, K, A, B, C, alpha, acc, lim1,
+                                                 cnt, part, Mcap, Ncap, items);
   else
-    k_gemm_ex<true, true><<<grid, 256, 0, st>>>(nb1, nb2, ntn, M, N, K, A, B, C, alpha, acc, lim1, cnt);
+    k_gemm_ex<true, true><<<grid, 256, 0, st>>>(nb1, nb2, ntn, M, N, K, A, B, C, alpha, acc, lim1,
+                                                cnt, part, Mcap, Ncap, items);
+  if (splits > 1) {
+    const int64_t total = items * Mcap * Ncap;
+    k_splitk_sum<<<(unsigned)((total + 255) / 256), 256, 0, st>>>(
+        nb1, nb2, M, N, C, alpha, acc, lim1, part, splits, Mcap, Ncap, items);
+  }
   if (prof) g_prof->end();
 }
 

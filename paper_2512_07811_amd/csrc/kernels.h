@@ -22,9 +22,12 @@ void gemm(hipStream_t st, int batch, Dim M, Dim N, Dim K, int Mcap, int Ncap, bo
 // op = identity or conjugate (the transpose is expressed through strides).
 // A is M x K, B is K x N, C is M x N, each addressed through its Mat strides.
 // Batch items with b1 >= lim1 (a device size) are skipped.
+// Kcap (optional, host bound on K): when the output has few tiles and K is
+// long, K is split over workgroups whose partial tiles go to the context's
+// split-K buffer and are summed in a fixed order by a second kernel.
 void gemm_ex(hipStream_t st, int batch, int nb1, int nb2, Dim M, Dim N, Dim K, int Mcap, int Ncap,
              Mat A, bool conjA, Mat B, bool conjB, Mat C, cplx alpha, bool accumulate,
-             Dim lim1 = Dim{nullptr, 0, 0, 1 << 30});
+             Dim lim1 = Dim{nullptr, 0, 0, 1 << 30}, int64_t Kcap = 0);
 
 // Householder QR of the packed m x n matrix A (one workgroup per instance):
 // A = Q R with Q (m x s) and R (s x n) packed, s = min(m, n) written to s_out.

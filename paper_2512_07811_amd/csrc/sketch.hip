@@ -205,7 +205,8 @@ qt_status sketch_impl(qt_ctx ctx, const qt_mpo* A, const qt_tt* y, const cplx* o
     // W_k[(a, b)][g] = sum_K D_k[a][K] T2[K][b][g]
     gemm_ex(st, B, 1, 1, dconst(rd), dref(ry + k, rs, lk), dconst(kd), rd, y->cap[k] * lk,
             mat(Dd + A->offsets[k], 0, sc(kd), sc(1)), false, mat(T2, iT2, sc(t2_a), sc(1)), false,
-            mat(Wall + w.Woff[k], iW, sref(ry + k, rs, lk), sc(1)), one, false);
+            mat(Wall + w.Woff[k], iW, sref(ry + k, rs, lk), sc(1)), one, false,
+            dconst(1 << 30), kd);
   }
   // ---- left pass: M_{-1} = 1, out ranks r_0 = r_n = 1
   k_fill_one<<<(B + 127) / 128, 128, 0, st>>>(B, Mb, iM);
@@ -222,7 +223,7 @@ qt_status sketch_impl(qt_ctx ctx, const qt_mpo* A, const qt_tt* y, const cplx* o
     gemm_ex(st, B, lk, 1, dref(ry + k, rs), dconst(kd), dconst(rd), y->cap[k], kd,
             mat(Mb, iM, sc(1), sref(ry + k, rs, 1), sref(ry + k, rs, rd)), false,
             mat(Dd + A->offsets[k], 0, sc(kd), sc(1)), false, mat(T3, iT3, sc(kd), sc(1), sc(t3_s)),
-            one, false, dref(ro + k, rs));
+            one, false, dref(ro + k, rs), rd);
     // Z[(s, i)][(a', b')] = sum_j sum_b T3[s][b][(i [j] a')] Y_k[b, j, b']
     Mat Zc = mat(Zb, iZ, sref(ry + k + 1, rs, 1), sc(1), sref(ry + k + 1, rs, (int64_t)p * rd1),
                  sref(ry + k + 1, rs, rd1));
@@ -253,7 +254,7 @@ qt_status sketch_impl(qt_ctx ctx, const qt_mpo* A, const qt_tt* y, const cplx* o
     gemm_ex(st, B, 1, 1, dref(ro + k, rs, p), dconst(lk1), dref(ry + k + 1, rs, rd1), lk * p, lk1,
             mat(Zb, iZ, sref(ry + k + 1, rs, rd1), sc(1)), false,
             mat(Wall + w.Woff[k + 1], iW, sc(lk1), sc(1)), false, mat(Yb, iY, sc(lk1), sc(1)),
-            one, false);
+            one, false, dconst(1 << 30), (int64_t)rd1 * y->cap[k + 1]);
     // Q_k = qr(Y_k) -> out core k, new rank s' -> ro[k+1]
     qr_auto(st, B, lk * p, lk1, dref(ro + k, rs, p), dconst(lk1), Yb, iY, Wq, iY, tau, w.tau,
             Od + out->offsets[k], out->inst_stride, Rb, w.R, ro + k + 1, rs);

@@ -107,6 +107,33 @@ def test_fixed_rank_sketch_matches_oracle_rto(q, ctx, kind, ell_max):
             assert np.allclose(T.left_gram(c), np.eye(c.shape[2]), atol=1e-12)
 
 
+def test_fixed_rank_sketch_long_contraction_matches_oracle(q, ctx):
+    # product ranks r_D r_y >= 1024 with narrow sketches: the contraction of the
+    # left-pass carry with W_{k+1} has a long inner dimension and few output
+    # tiles, so it is split over workgroups and summed in a second pass
+    import torch
+    modes = [3] + [2] * 9
+    ry = [1, 3, 6, 12, 24, 32, 24, 16, 8, 4, 1]
+    rd = [1, 2, 4, 8, 40, 40, 40, 8, 4, 2, 1]
+    dcores = I.random_tt(modes, rd, seed=90)
+    Ad = q.DeviceMPO.from_cores(dcores, [1] * len(modes))
+    Ao = T.diag_lift(dcores)
+    y = I.random_tt(modes, ry, seed=91)
+    nat = natural(modes)
+    ells = [1] + [min(nat[k], rd[k] * ry[k], 40) for k in range(1, len(modes))] + [1]
+    om = I.gaussian_sketch(modes, ells, seed=92)
+    Om = q.DeviceTT.from_cores([om], ells)
+    Y = q.DeviceTT.from_cores([y])
+    out = q.DeviceTT.empty(modes, ells, 1)
+    x = T.mpo_apply(Ao, y)
+    xn2 = torch.tensor([np.real(T.dot(x, x))], dtype=torch.float64, device="cuda")
+    err, fail = q.tt_sketch_round(ctx, Ad, Y, xn2, out, omega=Om, eps=1e-3, mode=q.ROUND_LEARNED)
+    got = out.to_cores()[0]
+    ref = SK.rto(x, om)
+    assert T.ranks(got) == T.ranks(ref)
+    assert rel(T.full(got), T.full(ref)) < 1e-11
+
+
 def test_sketch_svd_round_matches_oracle(q, ctx):
     import torch
     modes = [3] + [2] * 8
