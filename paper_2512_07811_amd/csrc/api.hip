@@ -624,6 +624,8 @@ static qt_status solver_setup(qt_ctx ctx, const qt_operands* ops, qt_tt* e,
   const int B = e->batch, n = e->n;
   const int rmax = opts->round.max_rank;
   S.sketch = opts->round.mode != QT_ROUND_SVD;
+  QT_CHECK(opts->round.precision == QT_PREC_F64, QT_EINVAL,
+           "solver: only QT_PREC_F64 contractions are available");
   S.learned = opts->round.mode == QT_ROUND_LEARNED;
   S.logging = ctx->learn && ctx->learn->log_count && S.sketch;
   size_t bytesA, bytesB, ws;

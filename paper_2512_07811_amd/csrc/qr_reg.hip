@@ -6,11 +6,13 @@
 // register slot c / 64; row i lives in lane i % 16 of that group, register row
 // i / 16.  Step j: the group owning column j forms the reflector
 // H = I - tau u u^H (u_j = 1, H x = beta e_1, beta = -e^{i arg x_j} ||x||,
-// tau = 1 + |x_j|/||x||) and publishes u through a double-buffered LDS vector;
+// tau = 1 + |x_j|/||x||) and publishes u in LDS;
 // every group updates its own trailing columns in registers, reducing over its
-// 16 lanes with DPP.  One barrier per column.  Q = H_0..H_{s-1} [I; 0] is then
-// accumulated backwards in the same registers from reflectors kept
-// (column-major) in a global scratch buffer.
+// 16 lanes with DPP.  One barrier per column.  The reflectors stay in LDS
+// (column-major, at most 144 x 64 or 96 x 96 complex = 144 KiB), so that
+// Q = H_0..H_{s-1} [I; 0] is then accumulated backwards in the same registers
+// with no barrier at all: every group owns its columns and the reflectors are
+// read-only by then.  (U is unused scratch kept for the common QR signature.)
 #include "kernels.h"
 
 namespace qt {
@@ -25,6 +27,7 @@ __global__ __launch_bounds__(1024) void k_qr_reg(Dim Md, Dim Nd, const cplx* __r
                                                  cplx* __restrict__ R, int64_t sR, int32_t* s_out,
                                                  int s_stride) {
   constexpr int MAXM = 16 * RPL;
+  constexpr int SMAX = MAXM < QG * CPS ? MAXM : QG * CPS;
   const int b = blockIdx.x;
   const int m0 = dimv(Md, b), n0 = dimv(Nd, b);
   // ORIENT: factor B = A when m0 >= n0, else B = A^H (so B is never wide)
@@ -34,8 +37,8 @@ __global__ __launch_bounds__(1024) void k_qr_reg(Dim Md, Dim Nd, const cplx* __r
   A += b * sA; U += b * sU; tau += b * sTau; Q += b * sQ; R += b * sR;
   const int g = threadIdx.x & 15;          // lane in the row group
   const int grp = threadIdx.x >> 4;        // row group 0..63 (= column residue)
-  __shared__ cplx ush[2][MAXM];
-  __shared__ double tsh[2];
+  __shared__ cplx ul[SMAX * MAXM];     // reflector j in ul[j * MAXM ...]
+  __shared__ double tl[SMAX];
   cplx a[CPS][RPL];
 #pragma unroll
   for (int cs = 0; cs < CPS; ++cs) {
@@ -49,7 +52,6 @@ __global__ __launch_bounds__(1024) void k_qr_reg(Dim Md, Dim Nd, const cplx* __r
     }
   }
   for (int j = 0; j < s; ++j) {
-    const int buf = j & 1;
     if (grp == (j % QG)) {
       const int csj = j / QG;
       cplx col[RPL];
@@ -91,8 +93,7 @@ __global__ __launch_bounds__(1024) void k_qr_reg(Dim Md, Dim Nd, const cplx* __r
         if (i < j || i >= m) u = make_double2(0.0, 0.0);
         else if (i == j) u = make_double2(1.0, 0.0);
         else u = cmul(col[r], iu0);
-        ush[buf][i] = u;
-        if (i < m) U[(int64_t)j * m + i] = u;
+        ul[j * MAXM + i] = u;
         // the owner keeps R's column: beta on the diagonal, zeros below
         cplx keep = (i == j) ? beta : (i > j ? make_double2(0.0, 0.0) : col[r]);
 #pragma unroll
@@ -100,25 +101,25 @@ __global__ __launch_bounds__(1024) void k_qr_reg(Dim Md, Dim Nd, const cplx* __r
           if (cs == csj) a[cs][r] = keep;
       }
       if (g == 0) {
-        tsh[buf] = t;
+        tl[j] = t;
         tau[j] = t;
       }
     }
     __syncthreads();
-    const double t = tsh[buf];
+    const double t = tl[j];
     if (t != 0.0) {
-      // u is re-read from LDS (cheap) instead of held in registers
+      const cplx* uj = ul + j * MAXM;
 #pragma unroll
       for (int cs = 0; cs < CPS; ++cs) {
         const int c = grp + QG * cs;
         const bool act = (c > j) && (c < n);
         cplx w = make_double2(0.0, 0.0);
 #pragma unroll
-        for (int r = 0; r < RPL; ++r) cfma(w, cconj(ush[buf][g + 16 * r]), a[cs][r]);
+        for (int r = 0; r < RPL; ++r) cfma(w, cconj(uj[g + 16 * r]), a[cs][r]);
         w = row16_sum(w);
         const cplx f = act ? cscale(w, -t) : make_double2(0.0, 0.0);
 #pragma unroll
-        for (int r = 0; r < RPL; ++r) cfma(a[cs][r], ush[buf][g + 16 * r], f);
+        for (int r = 0; r < RPL; ++r) cfma(a[cs][r], uj[g + 16 * r], f);
       }
     }
   }
@@ -143,26 +144,22 @@ __global__ __launch_bounds__(1024) void k_qr_reg(Dim Md, Dim Nd, const cplx* __r
       a[cs][r] = make_double2((i == c && c < s) ? 1.0 : 0.0, 0.0);
     }
   }
-  __syncthreads();
+  // the last step's barrier made every reflector visible; no more barriers
   for (int j = s - 1; j >= 0; --j) {
-    const int buf = j & 1;
-    for (int i = threadIdx.x; i < MAXM; i += blockDim.x)
-      ush[buf][i] = (i < m) ? U[(int64_t)j * m + i] : make_double2(0.0, 0.0);
-    if (threadIdx.x == 0) tsh[buf] = tau[j];
-    __syncthreads();
-    const double t = tsh[buf];
+    const double t = tl[j];
     if (t != 0.0) {
+      const cplx* uj = ul + j * MAXM;
 #pragma unroll
       for (int cs = 0; cs < CPS; ++cs) {
         const int c = grp + QG * cs;
         const bool act = (c >= j) && (c < s);
         cplx w = make_double2(0.0, 0.0);
 #pragma unroll
-        for (int r = 0; r < RPL; ++r) cfma(w, cconj(ush[buf][g + 16 * r]), a[cs][r]);
+        for (int r = 0; r < RPL; ++r) cfma(w, cconj(uj[g + 16 * r]), a[cs][r]);
         w = row16_sum(w);
         const cplx f = act ? cscale(w, -t) : make_double2(0.0, 0.0);
 #pragma unroll
-        for (int r = 0; r < RPL; ++r) cfma(a[cs][r], ush[buf][g + 16 * r], f);
+        for (int r = 0; r < RPL; ++r) cfma(a[cs][r], uj[g + 16 * r], f);
       }
     }
   }
@@ -295,30 +292,44 @@ __global__ __launch_bounds__(1024) void k_qr_mem(Dim Md, Dim Nd, const cplx* __r
     const int i = (int)(e / n), c = (int)(e % n);
     R[e] = (c >= i) ? M[(int64_t)c * m + i] : make_double2(0.0, 0.0);
   }
-  // Q (m x s) formed in the output buffer, reflectors read from M
-  for (int64_t e = threadIdx.x; e < (int64_t)m * s; e += blockDim.x) {
-    const int i = (int)(e / s), c = (int)(e % s);
-    Q[e] = make_double2(i == c ? 1.0 : 0.0, 0.0);
-  }
-  __syncthreads();
+  __syncthreads();   // R is read from M before M is overwritten below
+  // Q (m x s) formed in place over the reflectors (backward accumulation):
+  // at step j, H_j is applied to columns j+1..s-1, then column j, whose
+  // reflector is no longer needed, becomes H_j e_j.  The R factor was copied
+  // out above; Q is written out coalesced at the end.
   for (int j = s - 1; j >= 0; --j) {
     const double t = tau[j];
-    if (t == 0.0) continue;
     const cplx* uj = M + (int64_t)j * m;
-    for (int c = j + grp; c < s; c += QG) {
-      cplx w = make_double2(0.0, 0.0);
-      for (int i = j + g; i < m; i += 16) {
-        const cplx u = (i == j) ? make_double2(1.0, 0.0) : uj[i];
-        cfma(w, cconj(u), Q[(int64_t)i * s + c]);
-      }
-      w = row16_sum(w);
-      const cplx f = cscale(w, -t);
-      for (int i = j + g; i < m; i += 16) {
-        const cplx u = (i == j) ? make_double2(1.0, 0.0) : uj[i];
-        cfma(Q[(int64_t)i * s + c], u, f);
+    if (t != 0.0) {
+      for (int c = j + 1 + grp; c < s; c += QG) {
+        cplx* col = M + (int64_t)c * m;
+        cplx w = make_double2(0.0, 0.0);
+        for (int i = j + g; i < m; i += 16) {
+          const cplx u = (i == j) ? make_double2(1.0, 0.0) : uj[i];
+          cfma(w, cconj(u), col[i]);
+        }
+        w = row16_sum(w);
+        const cplx f = cscale(w, -t);
+        for (int i = j + g; i < m; i += 16) {
+          const cplx u = (i == j) ? make_double2(1.0, 0.0) : uj[i];
+          cfma(col[i], u, f);
+        }
       }
     }
     __syncthreads();
+    cplx* colj = M + (int64_t)j * m;
+    for (int i = threadIdx.x; i < m; i += blockDim.x) {
+      cplx v;
+      if (i < j) v = make_double2(0.0, 0.0);
+      else if (i == j) v = make_double2(1.0 - t, 0.0);
+      else v = cscale(colj[i], -t);
+      colj[i] = v;
+    }
+    __syncthreads();
+  }
+  for (int64_t e = threadIdx.x; e < (int64_t)m * s; e += blockDim.x) {
+    const int i = (int)(e / s), c = (int)(e % s);
+    Q[e] = M[(int64_t)c * m + i];
   }
   if (threadIdx.x == 0 && s_out) s_out[(int64_t)b * s_stride] = s;
 }

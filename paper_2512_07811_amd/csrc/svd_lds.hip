@@ -65,12 +65,21 @@ __global__ __launch_bounds__(1024) void k_jacobi_lds(
     __syncthreads();
     for (int r = 0; r < nbp - 1; ++r) {
       for (int pi0 = 0; pi0 < nbp / 2; pi0 += ngrp) {
+        // waves whose four groups all lie beyond the last pair of this round
+        // have nothing to do (wave-uniform skip)
+        if (pi0 + 4 * wv >= nbp / 2) continue;
         const int pi = pi0 + grp;
         int p = 0, q = 0;
         bool valid = pi < nbp / 2;
         if (valid) {
-          if (pi == 0) { p = nbp - 1; q = r; }
-          else { p = (r + pi) % (nbp - 1); q = (r - pi + nbp - 1) % (nbp - 1); }
+          const int mod = nbp - 1;
+          if (pi == 0) { p = mod; q = r; }
+          else {
+            p = r + pi;
+            if (p >= mod) p -= mod;
+            q = r - pi;
+            if (q < 0) q += mod;
+          }
           if (p >= nb || q >= nb) valid = false;
           if (p > q) { int t = p; p = q; q = t; }
         }
@@ -90,10 +99,11 @@ __global__ __launch_bounds__(1024) void k_jacobi_lds(
         const double gabs = sqrt(cabs2(ga));
         const bool rot = valid && al > negl && be > negl && gabs > 0.0 && gabs > jtol * sqrt(al * be);
         if (rot) {
-          const double zeta = (be - al) / (2.0 * gabs);
+          const double ig = 1.0 / gabs;
+          const double zeta = 0.5 * (be - al) * ig;
           const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-          const cplx e = make_double2(ga.x / gabs, ga.y / gabs);
+          const cplx e = make_double2(ga.x * ig, ga.y * ig);
           const cplx se = cscale(e, s), sec = cscale(cconj(e), s);
           for (int i = g; i < nb; i += 16) {
             cplx x = bp[i], y = bq[i];
