@@ -190,6 +190,9 @@ typedef struct {
   qt_mpo G;                 /* Green operator, momentum convention, diag spatial */
   qt_tt E;                  /* rank-1 mean field(s), batch = field batch         */
   const double* E_norm;     /* host [B]: |E| of each load                        */
+  qt_tt SE;                 /* S applied to E (rank 1, batch = field batch);     */
+                            /* read by the sketch modes, which round the last    */
+                            /* step as S^dagger (S E - eps^) = E - S^dagger eps^ */
 } qt_operands;
 
 typedef struct {
@@ -201,6 +204,9 @@ typedef struct {
 /* n_iter basic-scheme iterations (Algorithm 2) on the field batch e (in/out):
  *   tau = round(k' (.) e); tau^ = round(S tau); eps^ = round(G tau^);
  *   e' = round(E - S^dagger eps^); r = ||e' - e||_F / (|E| N^{3/2}).
+ * In the sketch and learned modes every rounding acts on the product
+ * structure, and the last one rounds S^dagger t with t = S E - eps^ (the rank-1
+ * term S E is added before the rounding, so there are four roundings).
  * residual_out: device [n_iter][B] doubles (may be NULL).
  * e->cap must hold opts->round.max_rank on every bond. */
 qt_status ls_iterate(qt_ctx ctx, const qt_operands* ops, qt_tt* e, const qt_solve_opts* opts,

@@ -246,6 +246,11 @@ static size_t iteration_bytes(const IterPlan& P, int B, int rmax) {
          4096;
 }
 
+__global__ void k_take_re(int batch, const double* pairs, double* out) {
+  int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < batch) out[b] = pairs[2 * b];
+}
+
 __global__ void k_residual(int batch, const double* norm, const double* inv_scale, double* out) {
   int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b < batch) out[b] = norm[b] * inv_scale[b];
@@ -393,24 +398,23 @@ static SketchPlan plan_sketch(const qt_operands* ops, const qt_tt* e, const qt_r
   P.ell3 = sketch_ranks(&ops->G, &y, rmax, os);
   P.c3r = capmin(P.ell3, rmax);
   y.cap = P.c3r.data();
-  P.ell4 = sketch_ranks(&ops->Sinv, &y, rmax, os);
-  P.c4r = capmin(P.ell4, rmax);
+  // t = S E - eps^ (rank c3r + 1), then e' = R(S^H t)
   P.c5.resize(n + 1);
   P.c6.resize(n + 1);
-  P.c5r.resize(n + 1);
-  for (int k = 0; k <= n; ++k) {
-    P.c5[k] = (k == 0 || k == n) ? 1 : ops->E.cap[k] + P.c4r[k];
-    P.c5r[k] = std::min(P.c5[k], std::min(nat[k], rmax > 0 ? rmax : P.c5[k]));
-    P.c6[k] = (k == 0 || k == n) ? 1 : P.c5r[k] + P.ce[k];
-  }
+  for (int k = 0; k <= n; ++k) P.c5[k] = (k == 0 || k == n) ? 1 : P.c3r[k] + ops->SE.cap[k];
+  y.cap = P.c5.data();
+  P.ell4 = sketch_ranks(&ops->Sinv, &y, rmax, os);
+  P.c4r = capmin(P.ell4, rmax);
+  for (int k = 0; k <= n; ++k) P.c6[k] = (k == 0 || k == n) ? 1 : P.c4r[k] + P.ce[k];
+  (void)nat;
   P.l1 = make_layout(P.modes, P.ell1);
   P.l2 = make_layout(P.modes, P.ell2);
   P.l3 = make_layout(P.modes, P.ell3);
   P.l4 = make_layout(P.modes, P.ell4);
   P.l5 = make_layout(P.modes, P.c5);
   P.l6 = make_layout(P.modes, P.c6);
-  P.bytesA = sizeof(cplx) * B * std::max({P.l1.stride, P.l3.stride, P.l5.stride});
-  P.bytesB = sizeof(cplx) * B * std::max({P.l2.stride, P.l4.stride, P.l6.stride});
+  P.bytesA = sizeof(cplx) * B * std::max({P.l1.stride, P.l3.stride, P.l4.stride});
+  P.bytesB = sizeof(cplx) * B * std::max({P.l2.stride, P.l5.stride, P.l6.stride});
   const int lmax = rmax > 0 ? rmax : (1 << 30);
   size_t ws = 0;
   qt_tt yv = *e, ov;
@@ -423,12 +427,19 @@ static SketchPlan plan_sketch(const qt_operands* ops, const qt_tt* e, const qt_r
   ov = P.l3.view(nullptr, nullptr, B);
   ws = std::max(ws, sround_ws_layout(&ops->G, &yv, &ov, P.ell3, lmax).bytes);
   ws = std::max(ws, sandwich_ws_layout(&ops->G, &yv).bytes);
-  yv.cap = P.c3r.data();
+  yv.cap = P.c5.data();
   ov = P.l4.view(nullptr, nullptr, B);
   ws = std::max(ws, sround_ws_layout(&ops->Sinv, &yv, &ov, P.ell4, lmax).bytes);
+  {
+    // <t, t> by environments (dot_impl)
+    int64_t env = 1, tcap = 1;
+    for (int k = 0; k <= n; ++k) env = std::max<int64_t>(env, (int64_t)P.c5[k] * P.c5[k]);
+    for (int k = 0; k < n; ++k)
+      tcap = std::max<int64_t>(tcap, (int64_t)P.c5[k] * P.modes[k] * P.c5[k + 1]);
+    ws = std::max(ws, sizeof(cplx) * B * (2 * env + tcap) + sizeof(double) * 2 * B + 8192);
+  }
   yv = *e;
   ws = std::max(ws, sandwich_ws_layout(&ops->K2, &yv).bytes);
-  ws = std::max(ws, round_bytes(P.l5, B, rmax));
   ws = std::max(ws, round_bytes(P.l6, B, rmax));
   P.ws = ws;
   return P;
@@ -461,7 +472,9 @@ static qt_status round_step(qt_ctx ctx, int step, const qt_mpo* A, const qt_tt* 
   const bool use_learned = learned && L->have_prev && L->params && !L->pred_ell[step].empty();
   bool sketch_mode = true;
   if (use_learned) {
-    for (size_t k = 1; k + 1 < ell.size(); ++k) ell[k] = std::min(ell[k], L->pred_ell[step][k]);
+    const int rcap = base.max_rank > 0 ? base.max_rank : (1 << 30);
+    for (size_t k = 1; k + 1 < ell.size(); ++k)
+      ell[k] = std::min({ell[k], L->pred_ell[step][k], rcap});
     so.mode = QT_ROUND_LEARNED;
     sketch_mode = false;
   }
@@ -572,33 +585,39 @@ static qt_status iterate_once_sketch(qt_ctx ctx, const qt_operands* ops, qt_tt* 
   QT_TRY(round_step(ctx, 2, &ops->G, &t2r, P.ell3, ro, xn2, &t3, err_dev, iter_id, learned, logging,
                     &lo));
   qt_tt t3r = view_caps(t3, P.c3r);
-  // t4 = R(S^H eps^)
-  weight_norm2(st, t3r, lo, xn2);
-  qt_tt t4 = P.l4.view(bufB, rB, B);
-  QT_TRY(round_step(ctx, 3, &ops->Sinv, &t3r, P.ell4, ro, xn2, &t4, err_dev, iter_id, learned,
+  // t = S E - eps^;  ||t||^2 by environments (no cancellation: Gamma(0) = 0
+  // makes eps^ vanish at the zero frequency, where S E lives)
+  qt_tt tt = P.l5.view(bufB, rB, B);
+  QT_TRY(add_impl(ctx, 1.0, 0.0, &ops->SE, -1.0, 0.0, &t3r, &tt));
+  qt_tt ttr = view_caps(tt, P.c5);
+  {
+    double* pairs = (double*)ws_take(ctx, sizeof(double) * 2 * B);
+    QT_CHECK(pairs, QT_ENOMEM, "iteration workspace (norm)");
+    QT_TRY(dot_impl(ctx, &ttr, &ttr, pairs, false));
+    k_take_re<<<(B + 127) / 128, 128, 0, st>>>(B, pairs, xn2);
+    ctx->ws_top = mark;
+  }
+  // e' = R(S^H t) = E - S^H eps^
+  qt_tt t4 = P.l4.view(bufA, rA, B);
+  QT_TRY(round_step(ctx, 3, &ops->Sinv, &ttr, P.ell4, ro, xn2, &t4, err_dev, iter_id, learned,
                     logging, &lo));
   qt_tt t4r = view_caps(t4, P.c4r);
   if (learned || logging) {
     const std::vector<int32_t>* ells[4] = {&P.ell1, &P.ell2, &P.ell3, &P.ell4};
     QT_TRY(learn_advance(ctx, learned, ells));
   }
-  // e' = round(E - t4)
-  qt_tt t5 = P.l5.view(bufA, rA, B);
-  QT_TRY(add_impl(ctx, 1.0, 0.0, &ops->E, -1.0, 0.0, &t4r, &t5));
+  // residual: ||e' - e|| from a left-orthogonalizing sweep of the difference
+  qt_tt t6 = P.l6.view(bufB, rB, B);
+  QT_TRY(add_impl(ctx, 1.0, 0.0, &t4r, -1.0, 0.0, e, &t6));
   qt_round_opts po = ro;
   po.mode = QT_ROUND_SVD;
-  QT_TRY(round_impl(ctx, &t5, &po, nullptr, nullptr, false, nullptr, 0, 0));
-  ctx->ws_top = mark;
-  qt_tt t5r = view_caps(t5, P.c5r);
-  qt_tt t6 = P.l6.view(bufB, rB, B);
-  QT_TRY(add_impl(ctx, 1.0, 0.0, &t5r, -1.0, 0.0, e, &t6));
   QT_TRY(round_impl(ctx, &t6, &po, nullptr, dnorm, true, nullptr, 0, 0));
   ctx->ws_top = mark;
   if (res_out) {
     k_residual<<<(B + 127) / 128, 128, 0, st>>>(B, dnorm, dinv, res_out);
     QT_HIP(hipGetLastError());
   }
-  QT_TRY(tt_copy(ctx, &t5r, e));
+  QT_TRY(tt_copy(ctx, &t4r, e));
   return QT_OK;
 }
 
@@ -637,6 +656,11 @@ static qt_status solver_setup(qt_ctx ctx, const qt_operands* ops, qt_tt* e,
   if (S.sketch) {
     QT_CHECK(ops->Kp.n == n && ops->K2.n == n && ops->k0 > 0.0, QT_EINVAL,
              "solver: sketch mode needs Kp, K2 and k0 operands");
+    QT_TRY(tt_validate(&ops->SE, "operands.SE"));
+    QT_CHECK(ops->SE.n == n && ops->SE.batch == B, QT_EINVAL,
+             "solver: operands.SE must match the field batch");
+    for (int k = 0; k < n; ++k)
+      QT_CHECK(ops->SE.modes[k] == e->modes[k], QT_EINVAL, "solver: operands.SE modes");
     S.SP = plan_sketch(ops, e, opts->round);
     bytesA = S.SP.bytesA; bytesB = S.SP.bytesB; ws = S.SP.ws;
   } else {

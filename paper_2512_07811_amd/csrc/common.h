@@ -90,6 +90,25 @@ __device__ inline cplx wave_sum(cplx v) {
   return v;
 }
 
+// Reciprocal and reciprocal square root for the small serial kernels (QR
+// reflectors, Jacobi rotations), whose steps are latency-bound: the hardware
+// approximations v_rcp_f64 / v_rsq_f64 refined by two Newton steps each
+// (error a few ulp, x > 0 finite), instead of the IEEE-rounded division and
+// square-root sequences, which are several times longer.
+__device__ inline double fast_rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(fma(-x, r, 1.0), r, r);
+  r = fma(fma(-x, r, 1.0), r, r);
+  return r;
+}
+__device__ inline double fast_rsq(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  r = r * fma(-h * r, r, 1.5);
+  r = r * fma(-h * r, r, 1.5);
+  return r;
+}
+
 // Sum over the 16 lanes of a DPP row; every lane of the row receives the same
 // bits.  quad_perm [1,0,3,2] and [2,3,0,1] add within quads (lane i adds lane
 // i^1, then i^2), row_half_mirror pairs quad 0 with 1 and 2 with 3, row_mirror

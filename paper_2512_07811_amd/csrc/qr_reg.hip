@@ -34,7 +34,9 @@ __global__ __launch_bounds__(1024) void k_qr_reg(Dim Md, Dim Nd, const cplx* __r
   const bool trans = ORIENT && (m0 < n0);
   const int m = trans ? n0 : m0, n = trans ? m0 : n0;
   const int s = min(m, n);
-  A += b * sA; U += b * sU; tau += b * sTau; Q += b * sQ; R += b * sR;
+  const bool want_q = Q != nullptr;   // decided before Q is offset
+  A += b * sA; U += b * sU; tau += b * sTau; R += b * sR;
+  if (want_q) Q += b * sQ;
   const int g = threadIdx.x & 15;          // lane in the row group
   const int grp = threadIdx.x >> 4;        // row group 0..63 (= column residue)
   __shared__ cplx ul[SMAX * MAXM];     // reflector j in ul[j * MAXM ...]
@@ -72,19 +74,25 @@ __global__ __launch_bounds__(1024) void k_qr_reg(Dim Md, Dim Nd, const cplx* __r
       }
       sig2 = row16_sum(sig2);
       al = row16_sum(al);  // one lane contributes
-      const double aa = sqrt(cabs2(al));
-      const double xn = sqrt(aa * aa + sig2);
+      const double a2 = cabs2(al), x2 = a2 + sig2;
       double t;
       cplx beta, iu0;
-      if (xn == 0.0) {
+      if (x2 == 0.0) {
         t = 0.0; beta = al; iu0 = make_double2(0.0, 0.0);
       } else {
-        cplx ph = aa > 0.0 ? make_double2(al.x / aa, al.y / aa) : make_double2(1.0, 0.0);
+        const double ixn = fast_rsq(x2), xn = x2 * ixn;
+        double aa = 0.0;
+        cplx ph = make_double2(1.0, 0.0);
+        if (a2 > 0.0) {
+          const double ia = fast_rsq(a2);
+          aa = a2 * ia;
+          ph = make_double2(al.x * ia, al.y * ia);
+        }
         beta = make_double2(-ph.x * xn, -ph.y * xn);
         cplx u0 = csub(al, beta);
-        double d = cabs2(u0);
-        iu0 = make_double2(u0.x / d, -u0.y / d);
-        t = 1.0 + aa / xn;
+        const double id = fast_rcp(cabs2(u0));
+        iu0 = make_double2(u0.x * id, -u0.y * id);
+        t = 1.0 + aa * ixn;
       }
 #pragma unroll
       for (int r = 0; r < RPL; ++r) {
@@ -134,7 +142,12 @@ __global__ __launch_bounds__(1024) void k_qr_reg(Dim Md, Dim Nd, const cplx* __r
       if (i < s) R[(int64_t)i * n + c] = (c >= i) ? a[cs][r] : make_double2(0.0, 0.0);
     }
   }
-  // Q (m x s) accumulated backwards: Q <- H_j Q for j = s-1 .. 0
+  // Q (m x s) accumulated backwards: Q <- H_j Q for j = s-1 .. 0 (skipped
+  // when only R is wanted)
+  if (!want_q) {
+    if (threadIdx.x == 0 && s_out) s_out[(int64_t)b * s_stride] = s;
+    return;
+  }
 #pragma unroll
   for (int cs = 0; cs < CPS; ++cs) {
     const int c = grp + QG * cs;
@@ -212,6 +225,84 @@ bool qr_reg(hipStream_t st, int batch, int mcap, int ncap, Dim m, Dim n, const c
 // one barrier per column) for matrices that do not fit in registers: the
 // matrix lives in LDS when m*n*16 bytes fit (dynamic shared memory), else in
 // the global scratch W (L2-resident for these sizes).
+// Rows per lane handled per batch of loads: the loops below issue all loads of
+// a chunk of QM_CH rows before using any of them (the memory latency, not the
+// arithmetic, bounds these steps), and keep the chunk in registers when the
+// column is short enough (m - j <= 16 QM_CH) to be updated in place.
+constexpr int QM_CH = 9;
+
+// H = I - t u u^H (u_j = 1, u below the diagonal of column j) applied to the
+// column col over rows j..m-1 by one 16-lane group (lane g).
+__device__ inline void qm_apply(const cplx* __restrict__ uj, cplx* __restrict__ col, int j, int m,
+                                int g, double t) {
+  if (m - j <= 16 * QM_CH) {
+    cplx uu[QM_CH], cc[QM_CH];
+#pragma unroll
+    for (int r = 0; r < QM_CH; ++r) {
+      const int i = j + g + 16 * r;
+      uu[r] = make_double2(0.0, 0.0);
+      cc[r] = make_double2(0.0, 0.0);
+      if (i < m) {
+        uu[r] = (i == j) ? make_double2(1.0, 0.0) : uj[i];
+        cc[r] = col[i];
+      }
+    }
+    cplx w = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int r = 0; r < QM_CH; ++r) cfma(w, cconj(uu[r]), cc[r]);
+    w = row16_sum(w);
+    const cplx f = cscale(w, -t);
+#pragma unroll
+    for (int r = 0; r < QM_CH; ++r) {
+      const int i = j + g + 16 * r;
+      if (i < m) {
+        cfma(cc[r], uu[r], f);
+        col[i] = cc[r];
+      }
+    }
+    return;
+  }
+  cplx w = make_double2(0.0, 0.0);
+  for (int i0 = j; i0 < m; i0 += 16 * QM_CH) {
+    cplx uu[QM_CH], cc[QM_CH];
+#pragma unroll
+    for (int r = 0; r < QM_CH; ++r) {
+      const int i = i0 + g + 16 * r;
+      uu[r] = make_double2(0.0, 0.0);
+      cc[r] = make_double2(0.0, 0.0);
+      if (i < m) {
+        uu[r] = (i == j) ? make_double2(1.0, 0.0) : uj[i];
+        cc[r] = col[i];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < QM_CH; ++r) cfma(w, cconj(uu[r]), cc[r]);
+  }
+  w = row16_sum(w);
+  const cplx f = cscale(w, -t);
+  for (int i0 = j; i0 < m; i0 += 16 * QM_CH) {
+    cplx uu[QM_CH], cc[QM_CH];
+#pragma unroll
+    for (int r = 0; r < QM_CH; ++r) {
+      const int i = i0 + g + 16 * r;
+      uu[r] = make_double2(0.0, 0.0);
+      cc[r] = make_double2(0.0, 0.0);
+      if (i < m) {
+        uu[r] = (i == j) ? make_double2(1.0, 0.0) : uj[i];
+        cc[r] = col[i];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < QM_CH; ++r) {
+      const int i = i0 + g + 16 * r;
+      if (i < m) {
+        cfma(cc[r], uu[r], f);
+        col[i] = cc[r];
+      }
+    }
+  }
+}
+
 template <bool IN_LDS>
 __global__ __launch_bounds__(1024) void k_qr_mem(Dim Md, Dim Nd, const cplx* __restrict__ A,
                                                  int64_t sA, cplx* __restrict__ W, int64_t sW,
@@ -225,7 +316,9 @@ __global__ __launch_bounds__(1024) void k_qr_mem(Dim Md, Dim Nd, const cplx* __r
   const bool trans = orient && (m0 < n0);   // factor A^H when A is wide
   const int m = trans ? n0 : m0, n = trans ? m0 : n0;
   const int s = min(m, n);
-  A += b * sA; W += b * sW; tau += b * sTau; Q += b * sQ; R += b * sR;
+  const bool want_q = Q != nullptr;   // decided before Q is offset
+  A += b * sA; W += b * sW; tau += b * sTau; R += b * sR;
+  if (want_q) Q += b * sQ;
   // column-major m x n work matrix; the reflector of step j (u_j = 1 implicit)
   // is kept below the diagonal of column j and read from there by all groups
   cplx* M = IN_LDS ? dyn : W;
@@ -241,24 +334,51 @@ __global__ __launch_bounds__(1024) void k_qr_mem(Dim Md, Dim Nd, const cplx* __r
     cplx* colj = M + (int64_t)j * m;
     if (grp == (j % QG)) {
       double sig2 = 0.0;
-      for (int i = j + 1 + g; i < m; i += 16) sig2 += cabs2(colj[i]);
+      for (int i0 = j + 1; i0 < m; i0 += 16 * QM_CH) {
+        cplx xx[QM_CH];
+#pragma unroll
+        for (int r = 0; r < QM_CH; ++r) {
+          const int i = i0 + g + 16 * r;
+          xx[r] = i < m ? colj[i] : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int r = 0; r < QM_CH; ++r) sig2 += cabs2(xx[r]);
+      }
       sig2 = row16_sum(sig2);
       const cplx al = colj[j];
-      const double aa = sqrt(cabs2(al));
-      const double xn = sqrt(aa * aa + sig2);
+      const double a2 = cabs2(al), x2 = a2 + sig2;
       double t;
       cplx beta, iu0;
-      if (xn == 0.0) {
+      if (x2 == 0.0) {
         t = 0.0; beta = al; iu0 = make_double2(0.0, 0.0);
       } else {
-        cplx ph = aa > 0.0 ? make_double2(al.x / aa, al.y / aa) : make_double2(1.0, 0.0);
+        const double ixn = fast_rsq(x2), xn = x2 * ixn;
+        double aa = 0.0;
+        cplx ph = make_double2(1.0, 0.0);
+        if (a2 > 0.0) {
+          const double ia = fast_rsq(a2);
+          aa = a2 * ia;
+          ph = make_double2(al.x * ia, al.y * ia);
+        }
         beta = make_double2(-ph.x * xn, -ph.y * xn);
         cplx u0 = csub(al, beta);
-        double d = cabs2(u0);
-        iu0 = make_double2(u0.x / d, -u0.y / d);
-        t = 1.0 + aa / xn;
+        const double id = fast_rcp(cabs2(u0));
+        iu0 = make_double2(u0.x * id, -u0.y * id);
+        t = 1.0 + aa * ixn;
       }
-      for (int i = j + 1 + g; i < m; i += 16) colj[i] = cmul(colj[i], iu0);
+      for (int i0 = j + 1; i0 < m; i0 += 16 * QM_CH) {
+        cplx xx[QM_CH];
+#pragma unroll
+        for (int r = 0; r < QM_CH; ++r) {
+          const int i = i0 + g + 16 * r;
+          xx[r] = i < m ? colj[i] : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int r = 0; r < QM_CH; ++r) {
+          const int i = i0 + g + 16 * r;
+          if (i < m) colj[i] = cmul(xx[r], iu0);
+        }
+      }
       if (g == 0) {
         colj[j] = beta;
         tsh[buf] = t;
@@ -272,18 +392,7 @@ __global__ __launch_bounds__(1024) void k_qr_mem(Dim Md, Dim Nd, const cplx* __r
       // own updates (no barrier needed between the update and the next step)
       for (int c = grp; c < n; c += QG) {
         if (c <= j) continue;
-        cplx* col = M + (int64_t)c * m;
-        cplx w = make_double2(0.0, 0.0);
-        for (int i = j + g; i < m; i += 16) {
-          const cplx u = (i == j) ? make_double2(1.0, 0.0) : colj[i];
-          cfma(w, cconj(u), col[i]);
-        }
-        w = row16_sum(w);
-        const cplx f = cscale(w, -t);
-        for (int i = j + g; i < m; i += 16) {
-          const cplx u = (i == j) ? make_double2(1.0, 0.0) : colj[i];
-          cfma(col[i], u, f);
-        }
+        qm_apply(colj, M + (int64_t)c * m, j, m, g, t);
       }
     }
   }
@@ -291,6 +400,10 @@ __global__ __launch_bounds__(1024) void k_qr_mem(Dim Md, Dim Nd, const cplx* __r
   for (int64_t e = threadIdx.x; e < (int64_t)s * n; e += blockDim.x) {
     const int i = (int)(e / n), c = (int)(e % n);
     R[e] = (c >= i) ? M[(int64_t)c * m + i] : make_double2(0.0, 0.0);
+  }
+  if (!want_q) {   // only R is wanted
+    if (threadIdx.x == 0 && s_out) s_out[(int64_t)b * s_stride] = s;
+    return;
   }
   __syncthreads();   // R is read from M before M is overwritten below
   // Q (m x s) formed in place over the reflectors (backward accumulation):
@@ -301,20 +414,7 @@ __global__ __launch_bounds__(1024) void k_qr_mem(Dim Md, Dim Nd, const cplx* __r
     const double t = tau[j];
     const cplx* uj = M + (int64_t)j * m;
     if (t != 0.0) {
-      for (int c = j + 1 + grp; c < s; c += QG) {
-        cplx* col = M + (int64_t)c * m;
-        cplx w = make_double2(0.0, 0.0);
-        for (int i = j + g; i < m; i += 16) {
-          const cplx u = (i == j) ? make_double2(1.0, 0.0) : uj[i];
-          cfma(w, cconj(u), col[i]);
-        }
-        w = row16_sum(w);
-        const cplx f = cscale(w, -t);
-        for (int i = j + g; i < m; i += 16) {
-          const cplx u = (i == j) ? make_double2(1.0, 0.0) : uj[i];
-          cfma(col[i], u, f);
-        }
-      }
+      for (int c = j + 1 + grp; c < s; c += QG) qm_apply(uj, M + (int64_t)c * m, j, m, g, t);
     }
     __syncthreads();
     cplx* colj = M + (int64_t)j * m;

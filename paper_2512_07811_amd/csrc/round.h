@@ -12,7 +12,8 @@ struct RoundWs {
 };
 RoundWs round_ws_layout(const qt_tt* x, int lmax_cap);
 
-// left_only: orthogonalize (QR sweep) and report the norm without truncating.
+// left_only: QR sweep that carries only the R factors and reports the norm
+// (no truncation; Q is never formed, x's cores are consumed as scratch).
 // svlog: optional [bond][instance][nb] log of sorted singular values.
 qt_status round_impl(qt_ctx ctx, qt_tt* x, const qt_round_opts* o, double* err_out,
                      double* norm_out, bool left_only, double* svlog, int64_t svstride_bond,

@@ -84,8 +84,10 @@ qt_status round_impl(qt_ctx ctx, qt_tt* x, const qt_round_opts* o, double* err_o
     const int p = x->modes[k];
     const cplx* in = (k == 0) ? X + x->offsets[0] : scratch;
     const int64_t sin = (k == 0) ? sX : w.slot;
+    // left_only (norm of the train): R is all that is carried, Q is not formed
     qr_auto(st, B, x->cap[k] * p, x->cap[k + 1], dref(rkl + k, rs, p), dref(rk + k + 1, rs), in,
-            sin, Wq, w.slot, tau, w.tau, X + x->offsets[k], sX, Rb, w.rr, rkl + k + 1, rs);
+            sin, Wq, w.slot, tau, w.tau, left_only ? nullptr : X + x->offsets[k], sX, Rb, w.rr,
+            rkl + k + 1, rs);
     const int p1 = x->modes[k + 1];
     // scratch (s x p1 r_{k+2}) = R (s x r_{k+1}) * core_{k+1} (r_{k+1} x p1 r_{k+2})
     gemm(st, B, dref(rkl + k + 1, rs), dref(rk + k + 2, rs, p1), dref(rk + k + 1, rs),
@@ -96,10 +98,7 @@ qt_status round_impl(qt_ctx ctx, qt_tt* x, const qt_round_opts* o, double* err_o
   norm_delta(st, B, dref(rkl + n - 1, rs), dconst(x->modes[n - 1]), scratch, w.slot, norm, delta,
              disc2, o->eps, n - 1);
   if (left_only) {
-    // keep the orthogonalized train: copy the centre back and publish left ranks
-    copy(st, B, dref(rkl + n - 1, rs), dconst(x->modes[n - 1]),
-         (int64_t)x->cap[n - 1] * x->modes[n - 1], scratch, w.slot, X + x->offsets[n - 1], sX);
-    QT_HIP(hipMemcpyAsync(rk, rkl, sizeof(int32_t) * B * (n + 1), hipMemcpyDeviceToDevice, st));
+    // norm only: x is left as scratch (its cores were consumed, not rewritten)
     finalize_err(st, B, disc2, norm, err_out, norm_out);
     QT_HIP(hipGetLastError());
     return QT_OK;

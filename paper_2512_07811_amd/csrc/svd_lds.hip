@@ -49,7 +49,7 @@ __global__ __launch_bounds__(1024) void k_jacobi_lds(
   fro = 0.0;
   for (int i = 0; i < nw; ++i) fro += red[i];
   const double negl = SL_NEGL * fro;
-  const double jtol = SL_EPS * (double)nb;
+  const double jtol = SL_EPS * (double)nb, jtol2 = jtol * jtol;
   const int nbp = (nb + 1) & ~1;
   const int g = tid & 15, grp = tid >> 4, ngrp = blockDim.x >> 4;
   bool converged = nb < 2;
@@ -85,42 +85,65 @@ __global__ __launch_bounds__(1024) void k_jacobi_lds(
         }
         cplx* bp = Rs + p * nb;
         cplx* bq = Rs + q * nb;
+        // the pair's columns stay in registers between the dot products and
+        // the rotation (nb <= SL_NB = 68 -> at most 5 rows per lane)
+        constexpr int RPL = (SL_NB + 15) / 16;
+        cplx xs[RPL], ys[RPL];
         double al = 0.0, be = 0.0;
         cplx ga = make_double2(0.0, 0.0);
-        if (valid) {
-          for (int i = g; i < nb; i += 16) {
-            cplx x = bp[i], y = bq[i];
-            al += cabs2(x);
-            be += cabs2(y);
-            cfma(ga, cconj(x), y);
+#pragma unroll
+        for (int it = 0; it < RPL; ++it) {
+          const int i = g + 16 * it;
+          xs[it] = make_double2(0.0, 0.0);
+          ys[it] = make_double2(0.0, 0.0);
+          if (valid && i < nb) {
+            xs[it] = bp[i];
+            ys[it] = bq[i];
           }
+          al += cabs2(xs[it]);
+          be += cabs2(ys[it]);
+          cfma(ga, cconj(xs[it]), ys[it]);
         }
         al = row16_sum(al); be = row16_sum(be); ga = row16_sum(ga);
-        const double gabs = sqrt(cabs2(ga));
-        const bool rot = valid && al > negl && be > negl && gabs > 0.0 && gabs > jtol * sqrt(al * be);
+        const double g2 = cabs2(ga);
+        const bool rot = valid && al > negl && be > negl && g2 > 0.0 && g2 > jtol2 * al * be;
         if (rot) {
-          const double ig = 1.0 / gabs;
+          const double ig = fast_rsq(g2);                       // 1 / |gamma|
           const double zeta = 0.5 * (be - al) * ig;
-          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+          const double z2 = fma(zeta, zeta, 1.0);
+          const double w = z2 * fast_rsq(z2);                   // sqrt(1 + zeta^2)
+          const double t = copysign(fast_rcp(fabs(zeta) + w), zeta);
+          const double c = fast_rsq(fma(t, t, 1.0)), s = c * t;
           const cplx e = make_double2(ga.x * ig, ga.y * ig);
           const cplx se = cscale(e, s), sec = cscale(cconj(e), s);
-          for (int i = g; i < nb; i += 16) {
-            cplx x = bp[i], y = bq[i];
-            bp[i] = csub(cscale(x, c), cmul(sec, y));
-            bq[i] = cadd(cmul(se, x), cscale(y, c));
+#pragma unroll
+          for (int it = 0; it < RPL; ++it) {
+            const int i = g + 16 * it;
+            if (i < nb) {
+              bp[i] = csub(cscale(xs[it], c), cmul(sec, ys[it]));
+              bq[i] = cadd(cmul(se, xs[it]), cscale(ys[it], c));
+            }
           }
           cplx* vp = Vs + p * nb;
           cplx* vq = Vs + q * nb;
-          for (int i = g; i < nb; i += 16) {
-            cplx x = vp[i], y = vq[i];
-            vp[i] = csub(cscale(x, c), cmul(sec, y));
-            vq[i] = cadd(cmul(se, x), cscale(y, c));
+#pragma unroll
+          for (int it = 0; it < RPL; ++it) {     // all loads first, then the updates
+            const int i = g + 16 * it;
+            xs[it] = i < nb ? vp[i] : make_double2(0.0, 0.0);
+            ys[it] = i < nb ? vq[i] : make_double2(0.0, 0.0);
+          }
+#pragma unroll
+          for (int it = 0; it < RPL; ++it) {
+            const int i = g + 16 * it;
+            if (i < nb) {
+              vp[i] = csub(cscale(xs[it], c), cmul(sec, ys[it]));
+              vq[i] = cadd(cmul(se, xs[it]), cscale(ys[it], c));
+            }
           }
           if (g == 0) {
             sh_rot = 1;
             atomicMax(&sh_worst, (unsigned long long)__double_as_longlong(
-                                     gabs / (jtol * sqrt(al * be))));
+                                     sqrt(g2 / (al * be)) / jtol));
             atomicMin(&sh_small, (unsigned long long)__double_as_longlong(fmin(al, be) / fro));
           }
         }

@@ -206,6 +206,15 @@ def with_component_core(spatial, control):
         [c.astype(np.complex128) for c in spatial]
 
 
+def apply_mpo(op, x):
+    """Cores of A x for operator cores (r, p_out, p_in, r') and train cores (s, p_in, s')."""
+    out = []
+    for A, X in zip(op, x):
+        c = np.einsum("aijc,bjd->abicd", A, X)
+        out.append(c.reshape(A.shape[0] * X.shape[0], A.shape[1], A.shape[3] * X.shape[2]))
+    return out
+
+
 def mean_field(E, L):
     return with_component_core([np.ones((1, 2, 1)) for _ in range(3 * L)], E)
 
@@ -249,7 +258,11 @@ def upload(prob, loads, max_rank, device=0):
                                 device=device)
     ksel = [qtt.DeviceTT.from_cores(c, device=device) for c in prob["k_sel"]]
     E_norm = np.array([np.linalg.norm(Ej) for Ej in loads], dtype=np.float64)
-    ops = qtt.DeviceOperands(L, kp, Kp, K2, prob["k0"], S, Sinv, G, E, E_norm, ksel)
+    # S E (rank 1: the constant field maps onto the zero frequency)
+    SE = qtt.DeviceTT.from_cores(
+        [compress(apply_mpo(prob["S"], mean_field(np.asarray(Ej, dtype=float), L)), 1e-14)
+         for Ej in loads], device=device)
+    ops = qtt.DeviceOperands(L, kp, Kp, K2, prob["k0"], S, Sinv, G, E, E_norm, ksel, SE)
     modes, cap = qtt.field_capacity(L, max_rank)
     e = qtt.DeviceTT.empty(modes, cap, B, device)
     return ops, e

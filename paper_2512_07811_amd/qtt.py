@@ -56,7 +56,7 @@ class RoundOpts(C.Structure):
 class Operands(C.Structure):
     _fields_ = [("L", C.c_int32), ("kp", TTDesc), ("Kp", MPODesc), ("K2", MPODesc),
                 ("k0", C.c_double), ("S", MPODesc), ("Sinv", MPODesc), ("G", MPODesc),
-                ("E", TTDesc), ("E_norm", C.POINTER(C.c_double))]
+                ("E", TTDesc), ("E_norm", C.POINTER(C.c_double)), ("SE", TTDesc)]
 
 
 class SolveOpts(C.Structure):
@@ -411,12 +411,13 @@ class DeviceOperands:
     E: DeviceTT
     E_norm: np.ndarray
     k_sel: list
+    SE: DeviceTT
     _struct: Operands = field(default=None, repr=False)
 
     def struct(self) -> Operands:
         s = Operands(self.L, self.kp.desc(), self.Kp.desc(), self.K2.desc(), self.k0,
                      self.S.desc(), self.Sinv.desc(), self.G.desc(), self.E.desc(),
-                     self.E_norm.ctypes.data_as(C.POINTER(C.c_double)))
+                     self.E_norm.ctypes.data_as(C.POINTER(C.c_double)), self.SE.desc())
         self._struct = s
         return s
 

@@ -37,3 +37,21 @@ def test_material_tt_bits_and_z_invariance():
     a = T.full(P.material_tt_z_invariant(sec, 1.0, 1e-12)).reshape(16, 16, 16)
     b = T.full(P.material_tt(k3, 1.0, 1e-12)).reshape(16, 16, 16)
     assert np.allclose(a, k3 - 1.0, atol=1e-11) and np.allclose(b, k3 - 1.0, atol=1e-11)
+
+
+def test_sfft_of_mean_field_is_zero_frequency_delta():
+    # S E for a constant field E: rank 1, E N^{3/2} at index 0 (zero frequency,
+    # which bit reversal leaves in place), zero elsewhere
+    L = 3
+    N = 2 ** L
+    S, _ = P.sfft_3d(L)
+    E = np.array([0.3, -1.2, 2.0])
+    se = P.compress(P.apply_mpo(S, P.mean_field(E, L)), 1e-14)
+    assert max(c.shape[2] for c in se[:-1]) == 1
+    full = se[0]
+    for c in se[1:]:
+        full = np.tensordot(full, c, axes=(full.ndim - 1, 0))
+    full = full.reshape(3, N ** 3)
+    want = np.zeros((3, N ** 3), dtype=complex)
+    want[:, 0] = E * N ** 1.5
+    assert np.max(np.abs(full - want)) < 1e-12 * N ** 1.5
