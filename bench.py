@@ -38,6 +38,13 @@ CONFIGS = {
 }
 
 
+# HBM bytes per k_gemm_ex launch from two copy-calibrated rocprofv3 counter runs
+# (FETCH_SIZE, WRITE_SIZE) of this bench on the learned path; the summary with the
+# commands is profiles/k_gemm_ex_sphere256_hbm_traffic.md.  Reported only for
+# the workload and mode it was measured on.
+GEMM_TRAFFIC = {("sphere256", "learned"): 18.54e6}
+
+
 def voxels(cfg):
     from paper_2512_07811_amd import inputs as I
     if cfg["geom"] == "sphere":
@@ -207,7 +214,10 @@ def main():
         "kernel": "structured GEMM (k_gemm_ex with its split-K sums)", "bound": "alu",
         "achieved": achieved,
         "peak": 78.6, "unit": "TFLOP/s",
-        "frac": (achieved / 78.6) if achieved else None, "traffic": None,
+        "frac": (achieved / 78.6) if achieved else None,
+        "traffic": GEMM_TRAFFIC.get((args.config, args.mode)),
+        "traffic_unit": "HBM bytes per launch (rocprofv3, copy-calibrated)",
+        "algorithmic_bytes_per_launch": gemm_bytes_step / g_n if g_n else None,
         "flops_per_step": gemm_flops_step, "bytes_per_step": gemm_bytes_step,
         "avg_launch_us": 1000.0 * g_ms / g_n if g_n else None,
         "kernel_ms_per_step": {k: v[0] for k, v in split.items()},
