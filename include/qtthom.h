@@ -69,7 +69,14 @@ typedef struct {
 /* A tensor-train operator (eq. tto_format) with fixed, host-known ranks.
  * Core k is (r_k, p_out, p_in, r_{k+1}) row-major, or, when diag[k] != 0, a
  * diagonal core stored as (r_k, p, r_{k+1}) meaning D(a,i,j,b) = B(a,i,b) d(i,j)
- * (the TT -> TTO lift, eq. tt_to_tto). */
+ * (the TT -> TTO lift, eq. tt_to_tto).
+ * Several operator instances (one per microstructure of a batch) share the
+ * ranks, modes and offsets: instance i starts at data + i*inst_stride elements
+ * and field b of a batch uses instance b / inst_group.  Instances with lower
+ * ranks are zero-padded to the common ranks (exact).  inst_stride = 0 means one
+ * operator for every field.  Per-instance operators are read by the
+ * product-aware (sketch/learned) kernels; the materializing tt_mpo_apply and
+ * the plain iteration require inst_stride = 0. */
 typedef struct {
   int32_t n;
   const int32_t* modes_out; /* host [n] */
@@ -78,6 +85,8 @@ typedef struct {
   const int32_t* diag;      /* host [n]  */
   const int64_t* offsets;   /* host [n]  */
   const void* data;         /* device complex double */
+  int64_t inst_stride;      /* elements between operator instances (0: shared) */
+  int32_t inst_group;       /* fields per operator instance (>= 1)             */
 } qt_mpo;
 
 typedef struct {
@@ -214,7 +223,8 @@ qt_status ls_iterate(qt_ctx ctx, const qt_operands* ops, qt_tt* e, const qt_solv
 
 /* Full solve: e_0 = E (per instance), iterate until every residual < tol or
  * max_iter; then A_eff[b][c] = Re <k_sel[c], e_b> / N^3 (Appendix A).
- * k_sel: three single-instance TTs of k (not k') with unit control cores.
+ * k_sel: three TTs of k (not k') with unit control cores, each holding one
+ *   train for every field or one train per field (batch = e->batch).
  * e: field batch used as the iterate (capacities as for ls_iterate).
  * A_eff: host [B][3]; iters: host [B] (iterations to convergence);
  * residuals: host [max_iter][B] (may be NULL). */

@@ -171,6 +171,8 @@ qt_status mpo_impl(qt_ctx ctx, const qt_mpo* A, const qt_tt* x, qt_tt* out) {
   QT_CHECK(A->n == x->n && x->n == out->n, QT_EINVAL, "tt_mpo_apply: core counts differ");
   QT_CHECK(out->batch == x->batch, QT_EINVAL, "tt_mpo_apply: batch mismatch");
   QT_CHECK(out->data != x->data, QT_EINVAL, "tt_mpo_apply: out aliases x");
+  QT_CHECK(A->inst_stride == 0, QT_EINVAL,
+           "tt_mpo_apply: per-instance operators are read by the sketch modes only");
   const int n = x->n, B = x->batch;
   for (int k = 0; k < n; ++k) {
     QT_CHECK(A->modes_in[k] == x->modes[k] && A->modes_out[k] == out->modes[k], QT_EINVAL,

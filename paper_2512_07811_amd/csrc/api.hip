@@ -664,6 +664,8 @@ static qt_status solver_setup(qt_ctx ctx, const qt_operands* ops, qt_tt* e,
     S.SP = plan_sketch(ops, e, opts->round);
     bytesA = S.SP.bytesA; bytesB = S.SP.bytesB; ws = S.SP.ws;
   } else {
+    QT_CHECK(ops->Kp.inst_stride == 0 && ops->K2.inst_stride == 0, QT_EINVAL,
+             "solver: the plain (materializing) iteration needs shared operators");
     S.P = plan_iteration(ops, e, rmax);
     bytesA = S.P.bytesA; bytesB = S.P.bytesB; ws = iteration_bytes(S.P, B, rmax) - S.P.bytesA - S.P.bytesB;
   }
@@ -822,7 +824,8 @@ qt_status homogenize(qt_ctx ctx, const qt_operands* ops, const qt_tt* k_sel, qt_
   QT_TRY(validate_ops(ops, e));
   for (int c = 0; c < 3; ++c) {
     QT_TRY(tt_validate(&k_sel[c], "k_sel"));
-    QT_CHECK(k_sel[c].batch == 1 && k_sel[c].n == e->n, QT_EINVAL, "homogenize: k_sel shape");
+    QT_CHECK((k_sel[c].batch == 1 || k_sel[c].batch == e->batch) && k_sel[c].n == e->n,
+             QT_EINVAL, "homogenize: k_sel must hold 1 or batch trains");
   }
   QT_CHECK(opts->max_iter >= 1, QT_EINVAL, "homogenize: max_iter < 1");
   QT_TRY(validate_field_cap(e, opts->round.max_rank));

@@ -69,14 +69,25 @@ inline Str sref(const int32_t* p, int stride, int64_t mul = 1, int64_t cst = 0) 
 
 // A strided matrix operand: element (r, c) of batch item (b1, b2) of instance b at
 // base + b*inst + b1*s1 + b2*s2 + r*rs + c*cs.
+// Instance b of a batch reads base + (b / grp) * inst (grp > 1: several fields
+// share one operator instance).
 struct Mat {
   cplx* base;
   int64_t inst;
   Str off, s1, s2, rs, cs;
+  int32_t grp;
 };
 inline Mat mat(const cplx* base, int64_t inst, Str rs, Str cs, Str s1 = Str{nullptr, 0, 0, 0},
                Str s2 = Str{nullptr, 0, 0, 0}, Str off = Str{nullptr, 0, 0, 0}) {
-  return Mat{const_cast<cplx*>(base), inst, off, s1, s2, rs, cs};
+  return Mat{const_cast<cplx*>(base), inst, off, s1, s2, rs, cs, 1};
+}
+// The same for data of a (possibly per-instance) operator.
+inline Mat mat_op(const qt_mpo* A, const cplx* base, Str rs, Str cs,
+                  Str s1 = Str{nullptr, 0, 0, 0}, Str s2 = Str{nullptr, 0, 0, 0},
+                  Str off = Str{nullptr, 0, 0, 0}) {
+  Mat m = mat(base, A->inst_stride, rs, cs, s1, s2, off);
+  m.grp = A->inst_group > 0 ? A->inst_group : 1;
+  return m;
 }
 
 // Wave-level reductions (wave64).

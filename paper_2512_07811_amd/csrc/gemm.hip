@@ -56,9 +56,11 @@ __global__ __launch_bounds__(256) void k_gemm_ex(int nb1, int nb2, int ntn, Dim 
     atomicAdd(counters + CNT_GEMM_BYTES, 16ull * ((unsigned long long)M * K + (unsigned long long)K * N +
                                                   (unsigned long long)M * N));
   }
-  const cplx* Ab = A.base + b * A.inst + strv(A.off, b) + b1 * strv(A.s1, b) + b2 * strv(A.s2, b);
-  const cplx* Bb = B.base + b * B.inst + strv(B.off, b) + b1 * strv(B.s1, b) + b2 * strv(B.s2, b);
-  cplx* Cb = C.base + b * C.inst + strv(C.off, b) + b1 * strv(C.s1, b) + b2 * strv(C.s2, b);
+  const cplx* Ab = A.base + (b / A.grp) * A.inst + strv(A.off, b) + b1 * strv(A.s1, b) +
+                   b2 * strv(A.s2, b);
+  const cplx* Bb = B.base + (b / B.grp) * B.inst + strv(B.off, b) + b1 * strv(B.s1, b) +
+                   b2 * strv(B.s2, b);
+  cplx* Cb = C.base + (b / C.grp) * C.inst + strv(C.off, b) + b1 * strv(C.s1, b) + b2 * strv(C.s2, b);
   const int64_t ars = strv(A.rs, b), acs = strv(A.cs, b);
   const int64_t brs = strv(B.rs, b), bcs = strv(B.cs, b);
   const int64_t crs = strv(C.rs, b), ccs = strv(C.cs, b);
@@ -178,7 +180,7 @@ __global__ void k_splitk_sum(int nb1, int nb2, Dim Md, Dim Nd, Mat C, cplx alpha
   if (gm >= dimv(Md, b) || gn >= dimv(Nd, b) || b1 >= dimv(lim1, b)) return;
   cplx acc = make_double2(0.0, 0.0);
   for (int s = 0; s < splits; ++s) acc = cadd(acc, part[((int64_t)s * items + z) * tile + (int64_t)gm * Ncap + gn]);
-  cplx* Cb = C.base + b * C.inst + strv(C.off, b) + b1 * strv(C.s1, b) + b2 * strv(C.s2, b);
+  cplx* Cb = C.base + (b / C.grp) * C.inst + strv(C.off, b) + b1 * strv(C.s1, b) + b2 * strv(C.s2, b);
   cplx* o = Cb + gm * strv(C.rs, b) + gn * strv(C.cs, b);
   cplx v = cmul(alpha, acc);
   if (accumulate) v = cadd(v, *o);

@@ -204,7 +204,7 @@ qt_status sketch_impl(qt_ctx ctx, const qt_mpo* A, const qt_tt* y, const cplx* o
     }
     // W_k[(a, b)][g] = sum_K D_k[a][K] T2[K][b][g]
     gemm_ex(st, B, 1, 1, dconst(rd), dref(ry + k, rs, lk), dconst(kd), rd, y->cap[k] * lk,
-            mat(Dd + A->offsets[k], 0, sc(kd), sc(1)), false, mat(T2, iT2, sc(t2_a), sc(1)), false,
+            mat_op(A, Dd + A->offsets[k], sc(kd), sc(1)), false, mat(T2, iT2, sc(t2_a), sc(1)), false,
             mat(Wall + w.Woff[k], iW, sref(ry + k, rs, lk), sc(1)), one, false,
             dconst(1 << 30), kd);
   }
@@ -222,7 +222,7 @@ qt_status sketch_impl(qt_ctx ctx, const qt_mpo* A, const qt_tt* y, const cplx* o
     // T3[s][b][K] = sum_a M[s][(a, b)] D_k[a][K]
     gemm_ex(st, B, lk, 1, dref(ry + k, rs), dconst(kd), dconst(rd), y->cap[k], kd,
             mat(Mb, iM, sc(1), sref(ry + k, rs, 1), sref(ry + k, rs, rd)), false,
-            mat(Dd + A->offsets[k], 0, sc(kd), sc(1)), false, mat(T3, iT3, sc(kd), sc(1), sc(t3_s)),
+            mat_op(A, Dd + A->offsets[k], sc(kd), sc(1)), false, mat(T3, iT3, sc(kd), sc(1), sc(t3_s)),
             one, false, dref(ro + k, rs), rd);
     // Z[(s, i)][(a', b')] = sum_j sum_b T3[s][b][(i [j] a')] Y_k[b, j, b']
     Mat Zc = mat(Zb, iZ, sref(ry + k + 1, rs, 1), sc(1), sref(ry + k + 1, rs, (int64_t)p * rd1),
@@ -318,14 +318,14 @@ qt_status sandwich_impl(qt_ctx ctx, const qt_mpo* Q, const qt_tt* y, double scal
     const int64_t g_b = (int64_t)p * rq1 * cy1, g_i = (int64_t)rq1 * cy1;
     if (Q->diag[k]) {
       gemm_ex(st, B, cy, p, dconst(rq1), dref(ry + k + 1, rs), dconst(rq), rq1, cy1,
-              mat(Qk, 0, sc(1), sc((int64_t)p * rq1), S0, sc(rq1)), false,
+              mat_op(Q, Qk, sc(1), sc((int64_t)p * rq1), S0, sc(rq1)), false,
               mat(F, w.F, sc((int64_t)p * cy1), sc(1), sc((int64_t)rq * p * cy1),
                   sref(ry + k + 1, rs, 1)),
               false, mat(G, w.G, sc(cy1), sc(1), sc(g_b), sc(g_i)), one, false, dref(ry + k, rs));
     } else {
       for (int j = 0; j < p; ++j)
         gemm_ex(st, B, cy, p, dconst(rq1), dref(ry + k + 1, rs), dconst(rq), rq1, cy1,
-                mat(Qk + (int64_t)j * rq1, 0, sc(1), sc((int64_t)p * p * rq1), S0,
+                mat_op(Q, Qk + (int64_t)j * rq1, sc(1), sc((int64_t)p * p * rq1), S0,
                     sc((int64_t)p * rq1)),
                 false,
                 mat(F, w.F, sc((int64_t)p * cy1), sc(1), sc((int64_t)rq * p * cy1), S0,

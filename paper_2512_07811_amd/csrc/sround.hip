@@ -120,6 +120,8 @@ qt_status sround_impl(qt_ctx ctx, const qt_mpo* A, const qt_tt* y, const cplx* o
 static qt_status validate_mpo(const qt_mpo* A, const qt_tt* y) {
   QT_CHECK(A->n == y->n, QT_EINVAL, "operator and train core counts differ");
   QT_CHECK(A->ranks[0] == 1 && A->ranks[A->n] == 1, QT_EINVAL, "operator boundary ranks");
+  QT_CHECK(A->inst_stride >= 0 && A->inst_group >= 1, QT_EINVAL,
+           "operator instance stride/group");
   for (int k = 0; k < y->n; ++k) {
     QT_CHECK(A->modes_in[k] == y->modes[k] && A->modes_out[k] == y->modes[k], QT_EINVAL,
              "operator modes must equal train modes (square operator)");

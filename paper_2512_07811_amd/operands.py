@@ -266,3 +266,37 @@ def upload(prob, loads, max_rank, device=0):
     modes, cap = qtt.field_capacity(L, max_rank)
     e = qtt.DeviceTT.empty(modes, cap, B, device)
     return ops, e
+
+
+def upload_batch(probs, loads, max_rank, device=0):
+    """Device operands for several microstructures (one `build_problem` each, equal L
+    and k0) times the same loads: field b = instance * len(loads) + load.  k' and (k')^2
+    are per-instance operators (zero-padded to common ranks); S, S^H and the Green
+    operator are shared; E, S E and the k selectors are per field."""
+    from . import qtt
+    L = probs[0]["L"]
+    k0 = probs[0]["k0"]
+    if any(p["L"] != L or p["k0"] != k0 for p in probs):
+        raise ValueError("instances must share L and k0")
+    nl = len(loads)
+    n = 3 * L + 1
+    Kp = qtt.DeviceMPO.from_cores([p["kp"] for p in probs], [1] * n, device=device,
+                                  inst_group=nl)
+    K2 = qtt.DeviceMPO.from_cores([p["k2"] for p in probs], [1] * n, device=device,
+                                  inst_group=nl)
+    S = qtt.DeviceMPO.from_cores(probs[0]["S"], device=device)
+    Sinv = qtt.DeviceMPO.from_cores(probs[0]["Sinv"], device=device)
+    G = qtt.DeviceMPO.from_cores(probs[0]["G"], [0] + [1] * (n - 1), device=device)
+    fields = [np.asarray(Ej, dtype=float) for _ in probs for Ej in loads]
+    E = qtt.DeviceTT.from_cores([mean_field(Ej, L) for Ej in fields], device=device)
+    SE = qtt.DeviceTT.from_cores(
+        [compress(apply_mpo(probs[0]["S"], mean_field(Ej, L)), 1e-14) for Ej in fields],
+        device=device)
+    ksel = [qtt.DeviceTT.from_cores([p["k_sel"][c] for p in probs for _ in loads], device=device)
+            for c in range(3)]
+    kp = qtt.DeviceTT.from_cores(probs[0]["kp"], device=device)   # plain path only
+    E_norm = np.array([np.linalg.norm(Ej) for Ej in fields], dtype=np.float64)
+    ops = qtt.DeviceOperands(L, kp, Kp, K2, k0, S, Sinv, G, E, E_norm, ksel, SE)
+    modes, cap = qtt.field_capacity(L, max_rank)
+    e = qtt.DeviceTT.empty(modes, cap, len(fields), device)
+    return ops, e

@@ -44,7 +44,7 @@ class MPODesc(C.Structure):
     _fields_ = [("n", C.c_int32), ("modes_out", C.POINTER(C.c_int32)),
                 ("modes_in", C.POINTER(C.c_int32)), ("ranks", C.POINTER(C.c_int32)),
                 ("diag", C.POINTER(C.c_int32)), ("offsets", C.POINTER(C.c_int64)),
-                ("data", C.c_void_p)]
+                ("data", C.c_void_p), ("inst_stride", C.c_int64), ("inst_group", C.c_int32)]
 
 
 class RoundOpts(C.Structure):
@@ -293,32 +293,49 @@ class DeviceMPO:
     def n(self):
         return len(self.ranks) - 1
 
+    inst_stride: int = 0
+    inst_group: int = 1
+
     @staticmethod
-    def from_cores(cores, diag_flags=None, device: int = 0):
-        """cores: (r, p_out, p_in, r') arrays, or (r, p, r') where diag_flags[k] is set."""
+    def from_cores(cores, diag_flags=None, device: int = 0, inst_group: int = 1):
+        """cores: (r, p_out, p_in, r') arrays, or (r, p, r') where diag_flags[k] is set;
+        or a list of such lists (one operator instance per microstructure), which
+        are zero-padded to common ranks; field b then uses instance b // inst_group."""
         torch = _torch()
-        n = len(cores)
+        multi = isinstance(cores[0], (list, tuple))
+        insts = cores if multi else [cores]
+        n = len(insts[0])
         diag_flags = [0] * n if diag_flags is None else [int(d) for d in diag_flags]
-        mo, mi, rk, off = [], [], [], []
+        rk = [max(cs[k].shape[0] for cs in insts) for k in range(n)]
+        rk.append(max(cs[-1].shape[-1] for cs in insts))
+        mo, mi, off, shapes = [], [], [], []
         o = 0
-        for c, d in zip(cores, diag_flags):
+        for k, d in enumerate(diag_flags):
+            c = insts[0][k]
             if d:
                 mo.append(c.shape[1]); mi.append(c.shape[1])
+                shp = (rk[k], c.shape[1], rk[k + 1])
             else:
                 mo.append(c.shape[1]); mi.append(c.shape[2])
-            rk.append(c.shape[0])
+                shp = (rk[k], c.shape[1], c.shape[2], rk[k + 1])
+            shapes.append(shp)
             off.append(o)
-            o += (c.size + 31) & ~31
-        rk.append(cores[-1].shape[-1])
-        host = np.zeros(max(o, 1), dtype=np.complex128)
-        for c, s in zip(cores, off):
-            host[s:s + c.size] = np.ascontiguousarray(c, dtype=np.complex128).reshape(-1)
+            o += (int(np.prod(shp)) + 31) & ~31
+        stride = max(o, 1)
+        host = np.zeros(stride * len(insts), dtype=np.complex128)
+        for i, cs in enumerate(insts):
+            for k, (c, s0) in enumerate(zip(cs, off)):
+                padded = np.zeros(shapes[k], dtype=np.complex128)
+                padded[tuple(slice(0, m) for m in c.shape)] = c
+                host[i * stride + s0:i * stride + s0 + padded.size] = padded.reshape(-1)
         data = torch.from_numpy(host).to(f"cuda:{device}")
-        return DeviceMPO(_i32(mo), _i32(mi), _i32(rk), _i32(diag_flags), _i64(off), data)
+        return DeviceMPO(_i32(mo), _i32(mi), _i32(rk), _i32(diag_flags), _i64(off), data,
+                         inst_stride=stride if multi else 0, inst_group=int(inst_group))
 
     def desc(self) -> MPODesc:
         d = MPODesc(self.n, _p32(self.modes_out), _p32(self.modes_in), _p32(self.ranks),
-                    _p32(self.diag), _p64(self.offsets), C.c_void_p(self.data.data_ptr()))
+                    _p32(self.diag), _p64(self.offsets), C.c_void_p(self.data.data_ptr()),
+                    self.inst_stride, self.inst_group)
         self._desc = d
         return d
 
