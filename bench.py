@@ -35,6 +35,11 @@ CONFIGS = {
                        loads=[[1.0, 0.0, 0.0], [0.0, 1.0, 0.0]]),
     "sphere32": dict(L=5, geom="sphere", frac=0.2, k_in=100.0, k_out=1.0, k0=50.5, eps=1e-6,
                      rmax=16, loads=[[1.0, 0.0, 0.0]]),
+    # 64 instances of 128^3 with 1-8 periodic boxes (edges 8-48, k in [5, 50]) in
+    # k = 1, loads e_x, e_y, e_z: 192 fields in one batched solve, per-instance k'
+    # operators, one reference medium k0 = (1 + 50) / 2 for all instances
+    "boxes128": dict(L=7, geom="boxes", instances=64, seed0=1000, k0=25.5, eps=1e-6, rmax=96,
+                     loads=[[1.0, 0.0, 0.0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0]]),
 }
 
 
@@ -45,13 +50,31 @@ CONFIGS = {
 GEMM_TRAFFIC = {("sphere256", "learned"): 18.54e6}
 
 
-def voxels(cfg):
+def voxels(cfg, inst=0):
     from paper_2512_07811_amd import inputs as I
+    if cfg["geom"] == "boxes":
+        return I.random_boxes(cfg["L"], cfg["seed0"] + inst)
     if cfg["geom"] == "sphere":
         return I.sphere(cfg["L"], cfg["frac"], cfg["k_in"], cfg["k_out"])
     if cfg["geom"] == "laminate":
         return I.laminate(cfg["L"])
     raise ValueError(cfg["geom"])
+
+
+_WORKER = {}
+
+
+def _init_worker(cfg, shared):
+    from threadpoolctl import threadpool_limits
+    threadpool_limits(1)          # one BLAS thread per worker process
+    _WORKER["cfg"] = cfg
+    _WORKER["shared"] = shared
+
+
+def _instance_problem(i):
+    from paper_2512_07811_amd import operands as P
+    cfg = _WORKER["cfg"]
+    return P.build_problem(kvox=voxels(cfg, i), k0=cfg["k0"], shared=_WORKER["shared"])
 
 
 def cpu_baseline(cfg, kvox, budget_s=20.0):
@@ -87,6 +110,8 @@ def main():
                     help="SVD-truncated iterations logged for training the rank predictor")
     ap.add_argument("--epochs", type=int, default=400)
     ap.add_argument("--no-ablation", action="store_true")
+    ap.add_argument("--instances", type=int, default=0,
+                    help="override the instance count of a batched config")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 512 MiB device copy first (HBM counter calibration)")
     ap.add_argument("--oversample", type=int, default=4)
@@ -104,6 +129,34 @@ def main():
     from paper_2512_07811_amd import operands as P
     from paper_2512_07811_amd import qtt
 
+    cfg = dict(CONFIGS[args.config])
+    batched = "instances" in cfg
+    if batched and args.instances > 0:
+        cfg["instances"] = args.instances
+    if batched and args.mode == "learned":
+        print("[bench] learned rounding runs one field at a time; batched config uses --mode sketch",
+              file=sys.stderr, flush=True)
+        args.mode = "sketch"
+    t0 = time.perf_counter()
+    # host set-up first: worker processes are forked before the GPU is touched
+    if batched:
+        first = P.build_problem(kvox=voxels(cfg, 0), k0=cfg["k0"])
+        shared = {k: first[k] for k in ("S", "Sinv", "G")}
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1), initializer=_init_worker,
+                                         initargs=(cfg, shared)) as pool:
+            probs = [first] + pool.map(_instance_problem, range(1, cfg["instances"]))
+        prob = first
+        fields = [E for _ in probs for E in cfg["loads"]]
+    else:
+        prob = P.build_problem(kvox=voxels(cfg), k0=cfg["k0"])
+        probs = [prob]
+        fields = list(cfg["loads"])
+    kvox = voxels(cfg)
+    t_setup = time.perf_counter() - t0
+    print(f"[bench] setup {t_setup:.1f}s  instances {len(probs)}  fields {len(fields)}  k' max rank "
+          f"{max(max(c.shape[0] for c in p['kp']) for p in probs)}  "
+          f"G max rank {max(c.shape[0] for c in prob['G'])}", file=sys.stderr, flush=True)
     if args.calibrate_copy:
         # a plain copy of known size: 512 MiB read, 512 MiB written
         src = torch.ones(1 << 26, dtype=torch.float64, device="cuda")
@@ -111,20 +164,16 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    cfg = CONFIGS[args.config]
-    kvox = voxels(cfg)
-    t0 = time.perf_counter()
-    prob = P.build_problem(kvox=kvox, k0=cfg["k0"])
-    t_setup = time.perf_counter() - t0
-    print(f"[bench] setup {t_setup:.1f}s  k' max rank {max(c.shape[0] for c in prob['kp'])}  "
-          f"G max rank {max(c.shape[0] for c in prob['G'])}", file=sys.stderr, flush=True)
     ctx = qtt.Context(0)
-    ops, e = P.upload(prob, cfg["loads"], cfg["rmax"])
+    if batched:
+        ops, e = P.upload_batch(probs, cfg["loads"], cfg["rmax"])
+    else:
+        ops, e = P.upload(prob, cfg["loads"], cfg["rmax"])
     mode = {"learned": qtt.ROUND_LEARNED, "sketch": qtt.ROUND_SKETCH, "svd": qtt.ROUND_SVD}[args.mode]
     opts = qtt.solve_opts(cfg["eps"], cfg["rmax"], mode=mode, oversample=args.oversample, seed=17)
     sk_opts = qtt.solve_opts(cfg["eps"], cfg["rmax"], mode=qtt.ROUND_SKETCH,
                              oversample=args.oversample, seed=17)
-    e = qtt.DeviceTT.from_cores([P.mean_field(np.asarray(E), ops.L) for E in cfg["loads"]], e.cap)
+    e = qtt.DeviceTT.from_cores([P.mean_field(np.asarray(E), ops.L) for E in fields], e.cap)
     train_info = None
     if args.mode == "learned":
         from paper_2512_07811_amd import learned
@@ -186,12 +235,12 @@ def main():
         cnt_sk = ctx.counters(reset=True)
         r_l = res.cpu().numpy()[:, 0]
         r_s = res_sk.cpu().numpy()[:, 0]
-        ablation = {"sketch_svd_iters_per_s": args.steps * len(cfg["loads"]) / dt_sk,
+        ablation = {"sketch_svd_iters_per_s": args.steps * len(fields) / dt_sk,
                     "speedup_learned_over_sketch_svd": dt_sk / dt,
                     "gemm_flops_ratio": cnt["gemm_flops"] / max(cnt_sk["gemm_flops"], 1),
                     "svd_calls_learned": cnt["svd_calls"], "svd_calls_sketch": cnt_sk["svd_calls"],
                     "max_residual_rel_diff": float(np.max(np.abs(r_l - r_s) / r_s))}
-    B = len(cfg["loads"])
+    B = len(fields)
     value = args.steps * B / dt
     print(f"[bench] {args.steps} steps in {dt:.3f}s; residuals {res.cpu().numpy()[:, 0].tolist()}",
           file=sys.stderr, flush=True)
@@ -201,6 +250,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c128",
         "data": "synthetic",
         "config": {"workload": args.config, "L": cfg["L"], "grid": f"{2 ** cfg['L']}^3",
+                   "instances": len(probs),
                    "rounding": args.mode, "eps": cfg["eps"], "max_rank": cfg["rmax"],
                    "oversample": args.oversample,
                    "batch": B, "parallelism": "single GPU"},

@@ -219,8 +219,12 @@ def mean_field(E, L):
     return with_component_core([np.ones((1, 2, 1)) for _ in range(3 * L)], E)
 
 
-def build_problem(kvox=None, k0=None, L=None, section=None, op_eps=1e-10, sfft_eps=1e-13):
-    """All host trains of one cell problem (k given as N^3 voxels or a z-invariant section)."""
+def build_problem(kvox=None, k0=None, L=None, section=None, op_eps=1e-10, sfft_eps=1e-13,
+                  shared=None):
+    """All host trains of one cell problem (k given as N^3 voxels or a z-invariant section).
+
+    shared: the "S", "Sinv" and "G" entries of an earlier problem with the same L and
+    k0, reused instead of rebuilt (they do not depend on the microstructure)."""
     if kvox is not None:
         sp_k = material_tt(kvox, 0.0, op_eps)
         sp_kp = material_tt(kvox, k0, op_eps)
@@ -236,8 +240,11 @@ def build_problem(kvox=None, k0=None, L=None, section=None, op_eps=1e-10, sfft_e
     ksel = [with_component_core(sp_k, np.eye(3)[c]) for c in range(3)]
     # (k')^2 for the exact norm ||k' e||^2 = <e, diag((k')^2) e>
     k2 = with_component_core(sp_k2, np.ones(3))
-    S, Sinv = sfft_3d(L, sfft_eps)
-    G = green_tt(L, k0, op_eps)
+    if shared is not None:
+        S, Sinv, G = shared["S"], shared["Sinv"], shared["G"]
+    else:
+        S, Sinv = sfft_3d(L, sfft_eps)
+        G = green_tt(L, k0, op_eps)
     return {"L": L, "k0": float(k0), "kp": kp, "k2": k2, "k_sel": ksel, "S": S, "Sinv": Sinv,
             "G": G}
 
