@@ -161,6 +161,8 @@ static qt_status validate_ops(const qt_operands* ops, const qt_tt* e) {
   QT_CHECK(ops->kp.batch == 1, QT_EINVAL, "operands: kp must be a single train");
   QT_CHECK(ops->E.batch == e->batch, QT_EINVAL, "operands: E batch must equal e batch");
   QT_CHECK(ops->E_norm != nullptr, QT_EINVAL, "operands: E_norm missing");
+  for (int b = 0; b < e->batch; ++b)
+    QT_CHECK(ops->E_norm[b] > 0.0, QT_EINVAL, "operands: every load E must be nonzero");
   for (int k = 0; k < n; ++k) QT_CHECK(e->modes[k] == (k == 0 ? 3 : 2), QT_EINVAL, "e: modes must be [3,2,...]");
   return QT_OK;
 }
@@ -201,9 +203,9 @@ static IterPlan plan_iteration(const qt_operands* ops, const qt_tt* e, int rmax)
     int r2 = std::min<int64_t>(P.c2[k], std::min<int64_t>(nat[k], rmax > 0 ? rmax : P.c2[k]));
     P.c3[k] = clampi((int64_t)ops->G.ranks[k] * r2);
     int r3 = std::min<int64_t>(P.c3[k], std::min<int64_t>(nat[k], rmax > 0 ? rmax : P.c3[k]));
+    // S^H eps^ is not rounded on its own: E - S^H eps^ is rounded once
     P.c4[k] = clampi((int64_t)ops->Sinv.ranks[k] * r3);
-    int r4 = std::min<int64_t>(P.c4[k], std::min<int64_t>(nat[k], rmax > 0 ? rmax : P.c4[k]));
-    P.c5[k] = (k == 0 || k == n) ? 1 : clampi((int64_t)ops->E.cap[k] + r4);
+    P.c5[k] = (k == 0 || k == n) ? 1 : clampi((int64_t)ops->E.cap[k] + P.c4[k]);
     int r5 = std::min<int64_t>(P.c5[k], std::min<int64_t>(nat[k], rmax > 0 ? rmax : P.c5[k]));
     P.c6[k] = (k == 0 || k == n) ? 1 : clampi((int64_t)r5 + ce);
   }
@@ -263,7 +265,7 @@ static qt_status iterate_once(qt_ctx ctx, const qt_operands* ops, qt_tt* e, cons
   const int B = e->batch;
   const int rmax = ro.max_rank;
   const size_t mark = ctx->ws_top;
-  std::vector<int32_t> s1, s2, s3, s4, s5;
+  std::vector<int32_t> s1, s2, s3, s5;
   // tau = round(k' (.) e)
   qt_tt t1 = P.l1.view(bufA, rA, B);
   QT_TRY(hadamard_impl(ctx, &ops->kp, e, &t1));
@@ -282,15 +284,12 @@ static qt_status iterate_once(qt_ctx ctx, const qt_operands* ops, qt_tt* e, cons
   QT_TRY(round_impl(ctx, &t3, &ro, nullptr, nullptr, false, nullptr, 0, 0));
   ctx->ws_top = mark;
   qt_tt t3r = shrink(t3, P.c3, rmax, s3);
-  // S^dagger eps^
+  // S^dagger eps^ (materialized, not rounded on its own)
   qt_tt t4 = P.l4.view(bufB, rB, B);
   QT_TRY(mpo_impl(ctx, &ops->Sinv, &t3r, &t4));
-  QT_TRY(round_impl(ctx, &t4, &ro, nullptr, nullptr, false, nullptr, 0, 0));
-  ctx->ws_top = mark;
-  qt_tt t4r = shrink(t4, P.c4, rmax, s4);
-  // e' = round(E - S^dagger eps^)
+  // e' = round(E - S^dagger eps^): the fourth and last rounding of the iteration
   qt_tt t5 = P.l5.view(bufA, rA, B);
-  QT_TRY(add_impl(ctx, 1.0, 0.0, &ops->E, -1.0, 0.0, &t4r, &t5));
+  QT_TRY(add_impl(ctx, 1.0, 0.0, &ops->E, -1.0, 0.0, &t4, &t5));
   QT_TRY(round_impl(ctx, &t5, &ro, nullptr, nullptr, false, nullptr, 0, 0));
   ctx->ws_top = mark;
   qt_tt t5r = shrink(t5, P.c5, rmax, s5);

@@ -166,6 +166,30 @@ def test_ls_iterates_match_oracle_without_truncation(q, ctx, L):
         assert abs(res[0, 0] - r_ref) < 1e-9 * max(r_ref, 1e-6)
 
 
+def test_ls_iterates_match_oracle_with_binding_rank_cap(q, ctx):
+    # a cap that binds on the middle bonds of three of the four roundings; the
+    # spectra are separated at the cut, so the truncation is well defined and
+    # the GPU iterates equal the oracle's (four roundings per iteration, the
+    # last one of E - S^H eps^)
+    from paper_2512_07811_amd import operands as P
+    L = 3
+    k = I.random_boxes(L, 7, edge_min=2, edge_max=5, k_min=2.0, k_max=6.0)
+    k0 = (k.min() + k.max()) / 2
+    E = np.array([1.0, 0.0, 0.0])
+    prob = P.build_problem(kvox=k, k0=k0)
+    ops, e = P.upload(prob, [E], max_rank=16)
+    e = q.DeviceTT.from_cores([O.mean_field_tt(E, L)], e.cap)
+    oprob = ls_tt.Problem(k, k0)
+    E_tt = O.mean_field_tt(E, L)
+    ref = O.mean_field_tt(E, L)
+    for m in range(3):
+        res = q.ls_iterate(ctx, ops, e, q.solve_opts(1e-8, 16), 1).cpu().numpy()
+        ref, r = ls_tt.ls_iterate(ref, oprob.kp, oprob.S, oprob.G, oprob.Sinv, E_tt, E, 1e-8, 16)
+        assert max(T.ranks(ref)) == 16
+        assert rel(T.full(e.to_cores()[0]), T.full(ref)) < 1e-10
+        assert abs(res[0, 0] - r) < 1e-9 * r
+
+
 def test_homogenize_laminate_closed_form(q, ctx):
     from paper_2512_07811_amd import operands as P
     k = I.laminate(5)
