@@ -110,6 +110,8 @@ def main():
                     help="SVD-truncated iterations logged for training the rank predictor")
     ap.add_argument("--epochs", type=int, default=400)
     ap.add_argument("--no-ablation", action="store_true")
+    ap.add_argument("--graph", action="store_true",
+                    help="sketch mode: replay a captured HIP graph of one iteration")
     ap.add_argument("--instances", type=int, default=0,
                     help="override the instance count of a batched config")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -170,7 +172,8 @@ def main():
     else:
         ops, e = P.upload(prob, cfg["loads"], cfg["rmax"])
     mode = {"learned": qtt.ROUND_LEARNED, "sketch": qtt.ROUND_SKETCH, "svd": qtt.ROUND_SVD}[args.mode]
-    opts = qtt.solve_opts(cfg["eps"], cfg["rmax"], mode=mode, oversample=args.oversample, seed=17)
+    opts = qtt.solve_opts(cfg["eps"], cfg["rmax"], mode=mode, oversample=args.oversample, seed=17,
+                          graph=args.graph)
     sk_opts = qtt.solve_opts(cfg["eps"], cfg["rmax"], mode=qtt.ROUND_SKETCH,
                              oversample=args.oversample, seed=17)
     e = qtt.DeviceTT.from_cores([P.mean_field(np.asarray(E), ops.L) for E in fields], e.cap)
@@ -252,7 +255,7 @@ def main():
         "config": {"workload": args.config, "L": cfg["L"], "grid": f"{2 ** cfg['L']}^3",
                    "instances": len(probs),
                    "rounding": args.mode, "eps": cfg["eps"], "max_rank": cfg["rmax"],
-                   "oversample": args.oversample,
+                   "oversample": args.oversample, "graph": bool(args.graph and args.mode == "sketch"),
                    "batch": B, "parallelism": "single GPU"},
     }
     dom = max(split, key=lambda k: split[k][0])

@@ -211,6 +211,10 @@ typedef struct {
   qt_round_opts round;      /* applied after every step                          */
   double tol;               /* residual tolerance delta_tol                      */
   int32_t max_iter;
+  int32_t graph;            /* ls_iterate, sketch mode: capture one iteration in */
+                            /* a HIP graph and replay it (no host work between   */
+                            /* iterations); ignored in the other modes, with the */
+                            /* rank log or the kernel-class timing on            */
 } qt_solve_opts;
 
 /* n_iter basic-scheme iterations (Algorithm 2) on the field batch e (in/out):

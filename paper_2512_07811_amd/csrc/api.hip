@@ -698,6 +698,70 @@ static qt_status solver_step(qt_ctx ctx, const qt_operands* ops, qt_tt* e, const
   return iterate_once(ctx, ops, e, S.P, ro, S.bufA, S.bufB, S.rA, S.rB, S.dnorm, S.dinv, res_out);
 }
 
+__global__ void k_inc_u64(uint64_t* p) { p[0] += 1; }
+
+// Iterations 2..n of a sketch-mode ls_iterate as replays of one captured
+// iteration: the capture runs on the context's private stream with the
+// context stream swapped out (nothing executes while capturing), the replays
+// run on the context stream.  The Gaussian stream of each replay comes from a
+// device counter (incremented inside the graph), the residual goes to a
+// scratch slot copied out after each replay.
+static qt_status iterate_graph(qt_ctx ctx, const qt_operands* ops, qt_tt* e, const Solver& S,
+                               const qt_round_opts& ro, int32_t n_iter, double* residual_out,
+                               double* res_tmp) {
+  const int B = e->batch;
+  if (!ctx->cap_stream) QT_HIP(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+  hipStream_t run = ctx->stream;
+  const size_t mark = ctx->ws_top;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ctx->stream = ctx->cap_stream;
+  ctx->capturing = true;
+  qt_status st = QT_OK;
+  hipError_t he = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
+  if (he == hipSuccess) {
+    st = iterate_once_sketch(ctx, ops, e, S.SP, ro, S.bufA, S.bufB, S.rA, S.rB, S.dnorm, S.dinv,
+                             S.xn2, S.err, residual_out ? res_tmp : nullptr, 0, false, false);
+    k_inc_u64<<<1, 1, 0, ctx->cap_stream>>>(ctx->dev_iter);
+    hipError_t he2 = hipStreamEndCapture(ctx->cap_stream, &graph);
+    if (he == hipSuccess) he = he2;
+  }
+  ctx->stream = run;
+  ctx->capturing = false;
+  ctx->ws_top = mark;
+  if (st != QT_OK || he != hipSuccess) {
+    if (graph) hipGraphDestroy(graph);
+    if (st != QT_OK) return st;
+    set_error(hip_msg(he, "ls_iterate: graph capture"));
+    return QT_EHIP;
+  }
+  he = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (he != hipSuccess) {
+    hipGraphDestroy(graph);
+    set_error(hip_msg(he, "ls_iterate: graph instantiation"));
+    return QT_EHIP;
+  }
+  const uint64_t first = ctx->sketch_counter;
+  he = hipMemcpyAsync(ctx->dev_iter, &first, sizeof(uint64_t), hipMemcpyHostToDevice, run);
+  for (int it = 0; it < n_iter && he == hipSuccess; ++it) {
+    he = hipGraphLaunch(exec, run);
+    if (he == hipSuccess && residual_out)
+      he = hipMemcpyAsync(residual_out + (int64_t)it * B, res_tmp, sizeof(double) * B,
+                          hipMemcpyDeviceToDevice, run);
+  }
+  // the host copy of the counter must stay alive until the copy above ran
+  hipError_t hs = hipStreamSynchronize(run);
+  hipGraphExecDestroy(exec);
+  hipGraphDestroy(graph);
+  if (he == hipSuccess) he = hs;
+  if (he != hipSuccess) {
+    set_error(hip_msg(he, "ls_iterate: graph replay"));
+    return QT_EHIP;
+  }
+  ctx->sketch_counter += n_iter;
+  return QT_OK;
+}
+
 }  // namespace qt
 
 using namespace qt;
@@ -726,10 +790,13 @@ qt_status qt_ctx_create(int device, void* stream, size_t ws_bytes, qt_ctx* out) 
     e = hipMalloc((void**)&c->splitk.p, sizeof(cplx) * QT_SPLITK_ELEMS);
     if (e == hipSuccess) c->splitk.elems = QT_SPLITK_ELEMS;
   }
+  if (e == hipSuccess) e = hipMalloc((void**)&c->dev_iter, sizeof(uint64_t));
+  if (e == hipSuccess) e = hipMemset(c->dev_iter, 0, sizeof(uint64_t));
   if (e != hipSuccess) {
     hipFree(c->status);
     if (c->counters) hipFree(c->counters);
     if (c->splitk.p) hipFree(c->splitk.p);
+    if (c->dev_iter) hipFree(c->dev_iter);
     delete c;
     set_error(hip_msg(e, "qt_ctx_create: device allocations"));
     return QT_EHIP;
@@ -753,6 +820,8 @@ void qt_ctx_destroy(qt_ctx ctx) {
   if (ctx->status) hipFree(ctx->status);
   if (ctx->counters) hipFree(ctx->counters);
   if (ctx->splitk.p) hipFree(ctx->splitk.p);
+  if (ctx->dev_iter) hipFree(ctx->dev_iter);
+  if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
   for (hipEvent_t e : ctx->prof.ev) hipEventDestroy(e);
   qt_learn_free(ctx);
   delete ctx;
@@ -807,11 +876,20 @@ qt_status ls_iterate(qt_ctx ctx, const qt_operands* ops, qt_tt* e, const qt_solv
   QT_CHECK(n_iter >= 0, QT_EINVAL, "ls_iterate: n_iter < 0");
   QT_TRY(validate_field_cap(e, opts->round.max_rank));
   Solver S;
-  QT_TRY(solver_setup(ctx, ops, e, opts, S, 0));
-  for (int it = 0; it < n_iter; ++it) {
+  QT_TRY(solver_setup(ctx, ops, e, opts, S, sizeof(double) * e->batch + 256));
+  double* res_tmp = (double*)ws_take(ctx, sizeof(double) * e->batch);
+  QT_CHECK(res_tmp, QT_ENOMEM, "ls_iterate: workspace");
+  const bool graph = opts->graph && S.sketch && !S.learned && !S.logging && !ctx->prof.cls;
+  // the first iteration runs eagerly (it also performs any one-time set-up)
+  const int eager = graph ? std::min(n_iter, 1) : n_iter;
+  for (int it = 0; it < eager; ++it) {
     QT_TRY(solver_step(ctx, ops, e, S, opts->round,
                        residual_out ? residual_out + (int64_t)it * e->batch : nullptr));
   }
+  if (graph && n_iter > eager)
+    QT_TRY(iterate_graph(ctx, ops, e, S, opts->round, n_iter - eager,
+                         residual_out ? residual_out + (int64_t)eager * e->batch : nullptr,
+                         res_tmp));
   return QT_OK;
 }
 

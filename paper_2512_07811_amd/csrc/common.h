@@ -232,6 +232,9 @@ struct qt_ctx_s {
   qt::LearnCtx* learn = nullptr;   // learned-rank state (created on demand)
   int jacobi_default = 30;
   uint64_t sketch_counter = 0;  // distinct Gaussian streams across iterations
+  uint64_t* dev_iter = nullptr;  // device copy of the iteration number (graph replays)
+  bool capturing = false;        // a graph of one iteration is being captured
+  hipStream_t cap_stream = nullptr;  // private stream for captures (default priority)
 };
 
 namespace qt {

@@ -89,4 +89,7 @@ void finalize_err(hipStream_t st, int batch, const double* disc2, const double* 
 // r[b] = scale_b * value[b] for residual bookkeeping (scale from host array uploaded to dev).
 void scale_vec(hipStream_t st, int batch, const double* in, const double* scale, double* out);
 
+// dst[i] = src[i] for i < count (a kernel, so that graphs hold no copy nodes).
+void copy_i32(hipStream_t st, int64_t count, const int32_t* src, int32_t* dst);
+
 }  // namespace qt

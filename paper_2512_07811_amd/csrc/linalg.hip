@@ -491,4 +491,14 @@ void scale_vec(hipStream_t st, int batch, const double* in, const double* scale,
   k_scale_vec<<<(batch + 127) / 128, 128, 0, st>>>(batch, in, scale, out);
 }
 
+__global__ void k_copy_i32(int64_t count, const int32_t* __restrict__ src, int32_t* __restrict__ dst) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < count) dst[t] = src[t];
+}
+
+void copy_i32(hipStream_t st, int64_t count, const int32_t* src, int32_t* dst) {
+  if (count <= 0) return;
+  k_copy_i32<<<(unsigned)((count + 255) / 256), 256, 0, st>>>(count, src, dst);
+}
+
 }  // namespace qt

@@ -31,7 +31,8 @@ SandwichWs sandwich_ws_layout(const qt_mpo* Q, const qt_tt* y);
 // out[b] = scale * Re <y_b, Q y_b>
 qt_status sandwich_impl(qt_ctx ctx, const qt_mpo* Q, const qt_tt* y, double scale, double* out);
 
-void gauss_fill(hipStream_t st, int64_t count, uint64_t seed, uint64_t stream, cplx* out);
+void gauss_fill(hipStream_t st, int64_t count, uint64_t seed, uint64_t stream, cplx* out,
+                const uint64_t* base = nullptr);
 void sumsq(hipStream_t st, int batch, Dim rows, Dim cols, const cplx* X, int64_t sX, double* out,
            double scale);
 

@@ -47,14 +47,19 @@ __device__ inline double gauss(uint64_t seed, uint64_t stream, uint64_t t) {
   return sqrt(-2.0 * log(u0)) * cos(6.283185307179586 * u1);
 }
 
-__global__ void k_gauss_fill(int64_t count, uint64_t seed, uint64_t stream, cplx* out) {
+// stream = (base ? 4 * base[0] : 0) + add: a captured graph reads the iteration
+// number from device memory, so that every replay draws new Gaussians.
+__global__ void k_gauss_fill(int64_t count, uint64_t seed, const uint64_t* base, uint64_t add,
+                             cplx* out) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t stream = (base ? 4 * base[0] : 0) + add;
   if (t < count) out[t] = make_double2(gauss(seed, stream, (uint64_t)t), 0.0);
 }
 
-void gauss_fill(hipStream_t st, int64_t count, uint64_t seed, uint64_t stream, cplx* out) {
+void gauss_fill(hipStream_t st, int64_t count, uint64_t seed, uint64_t stream, cplx* out,
+                const uint64_t* base) {
   if (count <= 0) return;
-  k_gauss_fill<<<(unsigned)((count + 255) / 256), 256, 0, st>>>(count, seed, stream, out);
+  k_gauss_fill<<<(unsigned)((count + 255) / 256), 256, 0, st>>>(count, seed, base, stream, out);
 }
 
 // ----------------------------------------------------------- helpers

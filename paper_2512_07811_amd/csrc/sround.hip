@@ -83,7 +83,7 @@ qt_status sround_impl(qt_ctx ctx, const qt_mpo* A, const qt_tt* y, const cplx* o
   if (!omega) {
     cplx* om = (cplx*)ws_take(ctx, sizeof(cplx) * w.om_tot);
     QT_CHECK(om, QT_ENOMEM, "sketch rounding: workspace too small");
-    gauss_fill(st, w.om_tot, o->seed, stream_id, om);
+    gauss_fill(st, w.om_tot, o->seed, stream_id, om, ctx->capturing ? ctx->dev_iter : nullptr);
     omega = om;
     om_off = &w.om_off;
   }
@@ -102,8 +102,7 @@ qt_status sround_impl(qt_ctx ctx, const qt_mpo* A, const qt_tt* y, const cplx* o
     cplx* V = (cplx*)ws_take(ctx, sizeof(cplx) * B * w.sweep.vv);
     cplx* Cb = (cplx*)ws_take(ctx, sizeof(cplx) * B * w.sweep.carry);
     QT_CHECK(scratch && Bsv && V && Cb, QT_ENOMEM, "sketch rounding: workspace too small");
-    QT_HIP(hipMemcpyAsync(rkl, out->ranks, sizeof(int32_t) * B * (n + 1), hipMemcpyDeviceToDevice,
-                          st));
+    copy_i32(st, (int64_t)B * (n + 1), out->ranks, rkl);
     SweepBufs buf{scratch, Bsv, V, Cb, w.sweep.slot, w.sweep.vv, w.sweep.carry};
     QT_TRY(take_sweep_extra(ctx, B, w.sweep, buf));
     const int sweeps = o->jacobi_max_sweeps > 0 ? o->jacobi_max_sweeps : ctx->jacobi_default;

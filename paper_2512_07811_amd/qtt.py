@@ -60,7 +60,8 @@ class Operands(C.Structure):
 
 
 class SolveOpts(C.Structure):
-    _fields_ = [("round", RoundOpts), ("tol", C.c_double), ("max_iter", C.c_int32)]
+    _fields_ = [("round", RoundOpts), ("tol", C.c_double), ("max_iter", C.c_int32),
+                ("graph", C.c_int32)]
 
 
 _lib = None
@@ -445,8 +446,8 @@ def field_capacity(L: int, max_rank: int):
     return modes, [min(r, max_rank) if max_rank > 0 else r for r in nat]
 
 
-def solve_opts(eps, max_rank, tol=1e-8, max_iter=200, mode=ROUND_SVD, **kw):
-    return SolveOpts(round_opts(eps, max_rank, mode, **kw), tol, max_iter)
+def solve_opts(eps, max_rank, tol=1e-8, max_iter=200, mode=ROUND_SVD, graph=False, **kw):
+    return SolveOpts(round_opts(eps, max_rank, mode, **kw), tol, max_iter, 1 if graph else 0)
 
 
 def ls_iterate(ctx: Context, ops: DeviceOperands, e: DeviceTT, opts: SolveOpts, n_iter: int):
