@@ -1,4 +1,5 @@
-// Truncated SVD for the right-to-left sweep, small sizes (min(m, c) <= 68):
+// Truncated SVD for the right-to-left sweep, small sizes (min(m, c) <= 100;
+// R and V in LDS up to 68, R in LDS and V in global memory up to 100):
 //   1. B = A (m >= c) or A^H (m < c); B = Q R by the register-resident QR;
 //   2. one-sided (Hestenes) Jacobi on the square R with R and V in LDS
 //      (R V = U_R Sigma), 16 waves, round-robin pairs, one barrier per round;
@@ -14,19 +15,25 @@
 namespace qt {
 
 constexpr int SL_NB = 68;            // LDS holds two SL_NB x SL_NB complex matrices
+constexpr int SL_NB_BIG = 100;       // LDS holds R only (160000 bytes), V in global memory
 constexpr double SL_EPS = 2.0 * 2.220446049250313e-16;
 constexpr double SL_NEGL = 1e-34;
 
+// NBMAX: largest order; VG: V kept in global memory (Vg + b * sV, nb x nb);
+// the large variant re-reads R from LDS for the rotation to stay within the
+// register budget of 1024 threads.
+template <int NBMAX, bool VG>
 __global__ __launch_bounds__(1024) void k_jacobi_lds(
     Dim Md, Dim Cd, const cplx* __restrict__ Rin, int64_t sR, cplx* __restrict__ RVp, int64_t sRV,
     double* __restrict__ sigp, int64_t sSig, cplx* __restrict__ core, int64_t sCore,
     cplx* __restrict__ carry, int64_t sCarry, int32_t* l_out, int l_stride,
     const double* __restrict__ delta, double* __restrict__ disc2, int lmax, int max_sweeps,
-    int32_t* status, double* svlog, int64_t svstride, unsigned long long* counters) {
-  __shared__ cplx Rs[SL_NB * SL_NB];
-  __shared__ cplx Vs[SL_NB * SL_NB];
-  __shared__ double sig[SL_NB];
-  __shared__ int perm[SL_NB];
+    int32_t* status, double* svlog, int64_t svstride, unsigned long long* counters,
+    cplx* __restrict__ Vg, int64_t sV) {
+  __shared__ cplx Rs[NBMAX * NBMAX];
+  __shared__ cplx Vl[VG ? 1 : NBMAX * NBMAX];
+  __shared__ double sig[NBMAX];
+  __shared__ int perm[NBMAX];
   __shared__ double red[16];
   __shared__ int sh_rot, sh_l;
   __shared__ unsigned long long sh_worst, sh_small;   // bit patterns of positive doubles
@@ -35,6 +42,7 @@ __global__ __launch_bounds__(1024) void k_jacobi_lds(
   const bool tall = m >= nc;
   const int nb = tall ? nc : m;
   Rin += b * sR; RVp += b * sRV; sigp += b * sSig; core += b * sCore; carry += b * sCarry;
+  cplx* Vs = VG ? Vg + b * sV : Vl;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
   for (int e = tid; e < nb * nb; e += blockDim.x) {
     const int i = e / nb, c = e % nb;       // R row-major (nb x nb)
@@ -86,23 +94,26 @@ __global__ __launch_bounds__(1024) void k_jacobi_lds(
         cplx* bp = Rs + p * nb;
         cplx* bq = Rs + q * nb;
         // the pair's columns stay in registers between the dot products and
-        // the rotation (nb <= SL_NB = 68 -> at most 5 rows per lane)
-        constexpr int RPL = (SL_NB + 15) / 16;
+        // the rotation (at most NBMAX / 16 rounded up rows per lane)
+        constexpr int RPL = (NBMAX + 15) / 16;
         cplx xs[RPL], ys[RPL];
         double al = 0.0, be = 0.0;
         cplx ga = make_double2(0.0, 0.0);
 #pragma unroll
         for (int it = 0; it < RPL; ++it) {
           const int i = g + 16 * it;
-          xs[it] = make_double2(0.0, 0.0);
-          ys[it] = make_double2(0.0, 0.0);
+          cplx x = make_double2(0.0, 0.0), y = make_double2(0.0, 0.0);
           if (valid && i < nb) {
-            xs[it] = bp[i];
-            ys[it] = bq[i];
+            x = bp[i];
+            y = bq[i];
           }
-          al += cabs2(xs[it]);
-          be += cabs2(ys[it]);
-          cfma(ga, cconj(xs[it]), ys[it]);
+          if (!VG) {
+            xs[it] = x;
+            ys[it] = y;
+          }
+          al += cabs2(x);
+          be += cabs2(y);
+          cfma(ga, cconj(x), y);
         }
         al = row16_sum(al); be = row16_sum(be); ga = row16_sum(ga);
         const double g2 = cabs2(ga);
@@ -120,8 +131,10 @@ __global__ __launch_bounds__(1024) void k_jacobi_lds(
           for (int it = 0; it < RPL; ++it) {
             const int i = g + 16 * it;
             if (i < nb) {
-              bp[i] = csub(cscale(xs[it], c), cmul(sec, ys[it]));
-              bq[i] = cadd(cmul(se, xs[it]), cscale(ys[it], c));
+              // the large variant re-reads R from LDS (registers hold V)
+              const cplx x = VG ? bp[i] : xs[it], y = VG ? bq[i] : ys[it];
+              bp[i] = csub(cscale(x, c), cmul(sec, y));
+              bq[i] = cadd(cmul(se, x), cscale(y, c));
             }
           }
           cplx* vp = Vs + p * nb;
@@ -268,13 +281,18 @@ bool svd_trunc_fast(hipStream_t st, int batch, int mcap, int ccap, Dim m, Dim c,
                     double* disc2, int lmax, int max_sweeps, int32_t* status, double* svlog,
                     int64_t svstride, unsigned long long* counters) {
   const int mbcap = std::max(mcap, ccap), nbcap = std::min(mcap, ccap);
-  if (nbcap > SL_NB) return false;
+  if (nbcap > SL_NB_BIG) return false;
   if (!qr_reg(st, batch, mbcap, nbcap, m, c, A, sA, Uw, sQ, tau, sT, Qw, sQ, Rw, sR, nullptr, 0,
               true))
     qr_mem(st, batch, mbcap, nbcap, m, c, A, sA, Uw, sQ, tau, sT, Qw, sQ, Rw, sR, nullptr, 0, true);
-  k_jacobi_lds<<<batch, 1024, 0, st>>>(m, c, Rw, sR, RVw, sR, sig, sT, core, sCore, carry, sCarry,
-                                       l_out, l_stride, delta, disc2, lmax, max_sweeps, status,
-                                       svlog, svstride, counters);
+  if (nbcap <= SL_NB)
+    k_jacobi_lds<SL_NB, false><<<batch, 1024, 0, st>>>(
+        m, c, Rw, sR, RVw, sR, sig, sT, core, sCore, carry, sCarry, l_out, l_stride, delta, disc2,
+        lmax, max_sweeps, status, svlog, svstride, counters, nullptr, 0);
+  else   // V in the QR scratch Uw (mbcap x nbcap >= nb x nb per instance), free after the QR
+    k_jacobi_lds<SL_NB_BIG, true><<<batch, 1024, 0, st>>>(
+        m, c, Rw, sR, RVw, sR, sig, sT, core, sCore, carry, sCarry, l_out, l_stride, delta, disc2,
+        lmax, max_sweeps, status, svlog, svstride, counters, Uw, sQ);
   k_svd_finalize<<<batch, 1024, 0, st>>>(m, c, Qw, sQ, RVw, sR, sig, sT, l_out, l_stride, core,
                                          sCore, carry, sCarry);
   return true;
