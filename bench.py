@@ -99,6 +99,79 @@ def cpu_baseline(cfg, kvox, budget_s=20.0):
                       f"the naive TT oracle cannot form this workload's product ranks"}
 
 
+def round_model_flops(modes, r_in, r_out):
+    """Real flops of one rounding by the Householder/Golub-Reinsch model (complex = 4x).
+
+    Left QR sweep over the cores (absorb the carried R factor, factor the
+    unfolding), then the right truncated-SVD sweep (QR of the unfolding, square
+    SVD of its triangle, carried factor, absorb into the next core), Sec. 2.2.
+    r_in are the input ranks, r_out the ranks after rounding."""
+    n = len(modes)
+
+    def qr(m, N):
+        big, small = max(m, N), min(m, N)
+        return 2.0 * big * small * small - 2.0 / 3.0 * small ** 3
+
+    f = 0.0
+    rl = [1] * (n + 1)
+    for k in range(n):
+        f += 2.0 * rl[k] * r_in[k] * modes[k] * r_in[k + 1]          # absorb
+        if k < n - 1:
+            m, N = rl[k] * modes[k], r_in[k + 1]
+            f += qr(m, N)
+            rl[k + 1] = min(m, N)
+    for k in range(n - 1, 0, -1):
+        m, N = rl[k], modes[k] * r_out[k + 1]
+        small = min(m, N)
+        f += qr(m, N) + 21.0 * small ** 3                                # QR + square SVD
+        f += 2.0 * m * N * r_out[k]                                     # carried factor
+        f += 2.0 * rl[k - 1] * modes[k - 1] * rl[k] * r_out[k]           # absorb into k-1
+    return 4.0 * f
+
+
+def round_microbench(ctx, ranks, L=8, max_runs=100, budget_s=3.0):
+    """tt_round on i.i.d. complex N(0, 1) cores of uniform rank R, zero tolerance
+    (nothing is truncated beyond the natural ranks: pure cost), mean time per
+    rounding over up to `max_runs` runs; the input is restored between runs
+    outside the timed events."""
+    import numpy as np
+    import torch
+
+    from paper_2512_07811_amd import inputs as I
+    from paper_2512_07811_amd import qtt
+    modes = [3] + [2] * (3 * L)
+    n = len(modes)
+    out = []
+    for R in ranks:
+        rk = [1] + [R] * (n - 1) + [1]
+        cores = I.random_tt(modes, rk, seed=100 + R)
+        x = qtt.DeviceTT.from_cores(cores, cap=rk)
+        d0, r0 = x.data.clone(), x.ranks.clone()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        times = []
+        t_start = time.perf_counter()
+        while len(times) < max_runs and (len(times) < 2 or time.perf_counter() - t_start < budget_s):
+            x.data.copy_(d0)
+            x.ranks.copy_(r0)
+            ev0.record()
+            qtt.tt_round(ctx, x, 0.0)
+            ev1.record()
+            ev1.synchronize()
+            times.append(ev0.elapsed_time(ev1))
+        times = times[1:]                      # the first run pays the workspace set-up
+        r_out = x.rank_array()[0].tolist()
+        ms = float(np.mean(times))
+        fl = round_model_flops(modes, rk, r_out)
+        out.append({"R": R, "runs": len(times), "ms": ms, "model_gflop": fl / 1e9,
+                    "gflops": fl / (ms * 1e-3) / 1e9, "frac_fp64_peak": fl / (ms * 1e-3) / 78.6e12})
+        print(f"[bench] tt_round R={R}: {ms:.3f} ms, {out[-1]['gflops']:.1f} GFLOP/s "
+              f"({len(times)} runs)", file=sys.stderr, flush=True)
+        del x, d0, r0
+    return {"family": f"i.i.d. complex N(0,1) cores, {n} cores (modes 3, 2, ..., 2), uniform "
+                      f"rank R, eps 0", "flop_model": "Householder QR 2mN^2 - 2N^3/3, square "
+                      "SVD 21N^3, absorb/carry products 2mnk; x4 for complex", "results": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -119,6 +192,10 @@ def main():
     ap.add_argument("--oversample", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--round-ranks", default="16,32,64,128",
+                    help="uniform ranks of the tt_round micro-benchmark ('' skips it)")
+    ap.add_argument("--round-only", action="store_true",
+                    help="run only the tt_round micro-benchmark and print its JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; the multi-GPU layout is described "
@@ -130,6 +207,13 @@ def main():
 
     from paper_2512_07811_amd import operands as P
     from paper_2512_07811_amd import qtt
+
+    if args.round_only:
+        ctx = qtt.Context(0)
+        res = round_microbench(ctx, [int(v) for v in args.round_ranks.split(",")])
+        ctx.close()
+        print(json.dumps({"tt_round": res}), flush=True)
+        return
 
     cfg = dict(CONFIGS[args.config])
     batched = "instances" in cfg
@@ -292,6 +376,8 @@ def main():
         out["predictor"] = train_info
     if ablation:
         out["ablation"] = ablation
+    if args.round_ranks:
+        out["tt_round"] = round_microbench(ctx, [int(v) for v in args.round_ranks.split(",")])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, kvox, args.cpu_budget)
     ctx.close()
