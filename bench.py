@@ -129,11 +129,11 @@ def round_model_flops(modes, r_in, r_out):
     return 4.0 * f
 
 
-def round_microbench(ctx, ranks, L=8, max_runs=100, budget_s=3.0):
+def round_microbench(ctx, ranks, batches=(1,), L=8, max_runs=100, budget_s=3.0):
     """tt_round on i.i.d. complex N(0, 1) cores of uniform rank R, zero tolerance
     (nothing is truncated beyond the natural ranks: pure cost), mean time per
-    rounding over up to `max_runs` runs; the input is restored between runs
-    outside the timed events."""
+    call over up to `max_runs` runs; the input is restored between runs outside
+    the timed events.  A call rounds `batch` independent trains at once."""
     import numpy as np
     import torch
 
@@ -142,10 +142,10 @@ def round_microbench(ctx, ranks, L=8, max_runs=100, budget_s=3.0):
     modes = [3] + [2] * (3 * L)
     n = len(modes)
     out = []
-    for R in ranks:
+    for R, B in ((R, B) for R in ranks for B in batches):
         rk = [1] + [R] * (n - 1) + [1]
-        cores = I.random_tt(modes, rk, seed=100 + R)
-        x = qtt.DeviceTT.from_cores(cores, cap=rk)
+        x = qtt.DeviceTT.from_cores([I.random_tt(modes, rk, seed=100 + R + 7919 * b)
+                                     for b in range(B)], cap=rk)
         d0, r0 = x.data.clone(), x.ranks.clone()
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         times = []
@@ -161,10 +161,10 @@ def round_microbench(ctx, ranks, L=8, max_runs=100, budget_s=3.0):
         times = times[1:]                      # the first run pays the workspace set-up
         r_out = x.rank_array()[0].tolist()
         ms = float(np.mean(times))
-        fl = round_model_flops(modes, rk, r_out)
-        out.append({"R": R, "runs": len(times), "ms": ms, "model_gflop": fl / 1e9,
+        fl = B * round_model_flops(modes, rk, r_out)
+        out.append({"R": R, "batch": B, "runs": len(times), "ms": ms, "model_gflop": fl / 1e9,
                     "gflops": fl / (ms * 1e-3) / 1e9, "frac_fp64_peak": fl / (ms * 1e-3) / 78.6e12})
-        print(f"[bench] tt_round R={R}: {ms:.3f} ms, {out[-1]['gflops']:.1f} GFLOP/s "
+        print(f"[bench] tt_round R={R} batch {B}: {ms:.3f} ms, {out[-1]['gflops']:.1f} GFLOP/s "
               f"({len(times)} runs)", file=sys.stderr, flush=True)
         del x, d0, r0
     return {"family": f"i.i.d. complex N(0,1) cores, {n} cores (modes 3, 2, ..., 2), uniform "
@@ -194,6 +194,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--round-ranks", default="16,32,64,128",
                     help="uniform ranks of the tt_round micro-benchmark ('' skips it)")
+    ap.add_argument("--round-batches", default="1,64",
+                    help="batch sizes of the tt_round micro-benchmark (trains per call)")
     ap.add_argument("--round-only", action="store_true",
                     help="run only the tt_round micro-benchmark and print its JSON")
     args = ap.parse_args()
@@ -210,7 +212,8 @@ def main():
 
     if args.round_only:
         ctx = qtt.Context(0)
-        res = round_microbench(ctx, [int(v) for v in args.round_ranks.split(",")])
+        res = round_microbench(ctx, [int(v) for v in args.round_ranks.split(",")],
+                               [int(v) for v in args.round_batches.split(",")])
         ctx.close()
         print(json.dumps({"tt_round": res}), flush=True)
         return
@@ -377,7 +380,8 @@ def main():
     if ablation:
         out["ablation"] = ablation
     if args.round_ranks:
-        out["tt_round"] = round_microbench(ctx, [int(v) for v in args.round_ranks.split(",")])
+        out["tt_round"] = round_microbench(ctx, [int(v) for v in args.round_ranks.split(",")],
+                                           [int(v) for v in args.round_batches.split(",")])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, kvox, args.cpu_budget)
     ctx.close()

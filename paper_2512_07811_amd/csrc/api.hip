@@ -313,7 +313,20 @@ static qt_status check_status(qt_ctx ctx) {
   QT_HIP(hipStreamSynchronize(ctx->stream));
   if (st) {
     QT_HIP(hipMemsetAsync(ctx->status, 0, sizeof(int32_t), ctx->stream));
-    if (st & ST_NONFINITE) { set_error("non-finite values in a rounding"); return QT_ENUMERIC; }
+    if (st & ST_NONFINITE) {
+      double d[QT_DIAG_N];
+      QT_HIP(hipMemcpyAsync(d, status_diag(ctx->status), sizeof(d), hipMemcpyDeviceToHost,
+                            ctx->stream));
+      QT_HIP(hipStreamSynchronize(ctx->stream));
+      char msg[256];
+      snprintf(msg, sizeof(msg),
+               "non-finite values in a rounding (%s, order %d, ||R||_F^2 %.3e, %d sweeps)",
+               d[8] == 1.0 ? "LDS Jacobi" : (d[8] == 3.0 ? "triangle given to the LDS Jacobi"
+                                                          : "global-memory Jacobi"),
+               (int)d[5], d[6], (int)d[9]);
+      set_error(msg);
+      return QT_ENUMERIC;
+    }
     if (st & ST_JACOBI_CAP) {
       double d[QT_DIAG_N];
       QT_HIP(hipMemcpyAsync(d, status_diag(ctx->status), sizeof(d), hipMemcpyDeviceToHost,

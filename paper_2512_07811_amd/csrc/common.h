@@ -105,19 +105,30 @@ __device__ inline cplx wave_sum(cplx v) {
 // reflectors, Jacobi rotations), whose steps are latency-bound: the hardware
 // approximations v_rcp_f64 / v_rsq_f64 refined by two Newton steps each
 // (error a few ulp, x > 0 finite), instead of the IEEE-rounded division and
-// square-root sequences, which are several times longer.
+// square-root sequences, which are several times longer.  The approximations
+// do not cover the whole exponent range (a denormal argument comes back as
+// infinity), so arguments outside [2^-960, 2^960] are scaled by an exact power
+// of two first; that branch is taken only for numerically vanishing blocks
+// (for instance the rounding of a Green-operator output that is zero in exact
+// arithmetic).
 __device__ inline double fast_rcp(double x) {
+  double sc = 1.0;
+  if (x < 0x1p-960) { x *= 0x1p+960; sc = 0x1p+960; }
+  else if (x > 0x1p+960) { x *= 0x1p-960; sc = 0x1p-960; }
   double r = __builtin_amdgcn_rcp(x);
   r = fma(fma(-x, r, 1.0), r, r);
   r = fma(fma(-x, r, 1.0), r, r);
-  return r;
+  return r * sc;
 }
 __device__ inline double fast_rsq(double x) {
+  double sc = 1.0;
+  if (x < 0x1p-960) { x *= 0x1p+960; sc = 0x1p+480; }
+  else if (x > 0x1p+960) { x *= 0x1p-960; sc = 0x1p-480; }
   double r = __builtin_amdgcn_rsq(x);
   const double h = 0.5 * x;
   r = r * fma(-h * r, r, 1.5);
   r = r * fma(-h * r, r, 1.5);
-  return r;
+  return r * sc;
 }
 
 // Sum over the 16 lanes of a DPP row; every lane of the row receives the same
@@ -182,7 +193,7 @@ enum : int32_t { ST_JACOBI_CAP = 1, ST_NONFINITE = 2 };
 // written by the first kernel that raises ST_JACOBI_CAP: matrix order, squared
 // Frobenius norm, largest |b_p^H b_q| / (||b_p|| ||b_q|| tol) of the last sweep,
 // smallest rotated column norm^2 / Frobenius^2 of the last sweep, sweeps.
-constexpr int QT_DIAG_N = 5;
+constexpr int QT_DIAG_N = 10;   // [0, 5): sweep cap, [5, 10): non-finite values
 constexpr size_t QT_STATUS_BYTES = 16 + 8 * QT_DIAG_N;
 __host__ __device__ inline double* status_diag(int32_t* status) {
   return (double*)((char*)status + 16);

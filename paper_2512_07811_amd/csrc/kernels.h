@@ -50,6 +50,33 @@ void qr_mem(hipStream_t st, int batch, int mcap, int ncap, Dim m, Dim n, const c
 void qr_auto(hipStream_t st, int batch, int mcap, int ncap, Dim m, Dim n, const cplx* A,
              int64_t sA, cplx* W, int64_t sW, double* tau, int64_t sTau, cplx* Q, int64_t sQ,
              cplx* R, int64_t sR, int32_t* s_out, int s_stride);
+// Capacities that the register-resident / LDS-resident kernels cover.
+bool qr_reg_fits(int mcap, int ncap);
+bool qr_lds_fits(int mcap, int ncap);
+
+// Blocked Householder QR (panels of 32 columns, trailing updates and Q
+// formation on the MFMA GEMM) for unfoldings beyond one workgroup's LDS.
+// Same contract as qr (Q may be null: R and s_out only).  Mw is the m x n work
+// matrix (column-major, leading dimension mcap, stride sM >= mcap * ncap).
+struct QrBlkWs {
+  cplx* V;            // reflectors, mcap x (panels * 32) per instance
+  int64_t v_stride;
+  cplx* T;            // panels x 32 x 32 per instance
+  int64_t t_stride;
+  cplx* W1;           // 32 x ncap per instance
+  cplx* W2;
+  int64_t w_stride;
+  double* tau;        // panels * 32 per instance
+  int64_t tau_stride;
+  int32_t* s_dev;     // batch
+};
+bool qr_blocked_wanted(int mcap, int ncap);
+// element counts per instance of V, T and one W buffer; returns V + T + 2 W
+size_t qr_blocked_ws_elems(int mcap, int ncap, int64_t* v_elems, int64_t* t_elems,
+                           int64_t* w_elems);
+void qr_blocked(hipStream_t st, int batch, int mcap, int ncap, Dim m, Dim n, const cplx* A,
+                int64_t sA, cplx* Mw, int64_t sM, const QrBlkWs& ws, cplx* Q, int64_t sQ,
+                cplx* R, int64_t sR, int32_t* s_out, int s_stride);
 
 // Truncated SVD of the packed m x c matrix A by one-sided (Hestenes) Jacobi:
 // keeps the smallest l >= 1 whose discarded tail does not exceed delta[b],

@@ -382,7 +382,17 @@ __global__ __launch_bounds__(256) void k_svd_trunc(
       if (!isfinite(sj)) finite = false;
       if (j >= l) d2 += sj * sj;
     }
-    if (!finite) atomicOr(status, (int32_t)ST_NONFINITE);
+    if (!finite) {
+      const int32_t old = atomicOr(status, (int32_t)ST_NONFINITE);
+      if (!(old & ST_NONFINITE)) {
+        double* d = status_diag(status) + 5;
+        d[0] = nb;
+        d[1] = fro;
+        d[2] = -1.0;
+        d[3] = 2.0;   // global-memory Jacobi
+        d[4] = sweep;
+      }
+    }
     disc2[b] += d2;
     sh_l = l;
     if (l_out) l_out[(int64_t)b * l_stride] = l;

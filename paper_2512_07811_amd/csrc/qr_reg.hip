@@ -436,6 +436,16 @@ __global__ __launch_bounds__(1024) void k_qr_mem(Dim Md, Dim Nd, const cplx* __r
 
 constexpr size_t QR_LDS_BYTES = 160 * 1024 - 64;
 
+bool qr_reg_fits(int mcap, int ncap) {
+  const int rpl = (mcap + 15) / 16, cps = (ncap + QG - 1) / QG;
+  if (rpl < 1 || cps < 1) return false;
+  return (cps == 1 && rpl <= 9) || (cps == 2 && rpl <= 6);
+}
+
+bool qr_lds_fits(int mcap, int ncap) {
+  return sizeof(cplx) * (size_t)mcap * ncap <= QR_LDS_BYTES;
+}
+
 void qr_mem(hipStream_t st, int batch, int mcap, int ncap, Dim m, Dim n, const cplx* A,
             int64_t sA, cplx* W, int64_t sW, double* tau, int64_t sTau, cplx* Q, int64_t sQ,
             cplx* R, int64_t sR, int32_t* s_out, int s_stride, bool orient) {

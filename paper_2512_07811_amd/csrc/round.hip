@@ -33,6 +33,14 @@ RoundWs round_ws_layout(const qt_tt* x, int lmax_cap) {
     carry = std::max<int64_t>(carry, (int64_t)x->cap[k] * std::min(x->cap[k], lmax_cap));
     tau = std::max<int64_t>(tau, x->cap[k + 1]);
     w.max_nb = std::max<int64_t>(w.max_nb, nb);
+    if (k < n - 1 && qr_blocked_wanted(x->cap[k] * x->modes[k], x->cap[k + 1])) {
+      int64_t v, t, wq;
+      qr_blocked_ws_elems(x->cap[k] * x->modes[k], x->cap[k + 1], &v, &t, &wq);
+      w.qb_v = std::max(w.qb_v, v);
+      w.qb_t = std::max(w.qb_t, t);
+      w.qb_w = std::max(w.qb_w, wq);
+      w.qb_tau = std::max(w.qb_tau, t / 32);
+    }
   }
   w.slot = slot; w.rr = rr; w.vv = vv; w.carry = carry; w.tau = tau;
   const int B = x->batch;
@@ -40,6 +48,9 @@ RoundWs round_ws_layout(const qt_tt* x, int lmax_cap) {
   w.sweep_bytes = sizeof(cplx) * B * (slot + vv) + sizeof(double) * B * 2 * w.max_nb + 4 * 256;
   w.bytes = sizeof(cplx) * B * (3 * slot + rr + vv + carry) + sizeof(double) * B * (tau + 4) +
             sizeof(int32_t) * B * (n + 1) + 16 * 256 + w.sweep_bytes;
+  if (w.qb_v > 0)
+    w.bytes += sizeof(cplx) * B * (w.qb_v + w.qb_t + 2 * w.qb_w) + sizeof(double) * B * w.qb_tau +
+               sizeof(int32_t) * B + 8 * 256;
   return w;
 }
 
@@ -65,6 +76,21 @@ qt_status round_impl(qt_ctx ctx, qt_tt* x, const qt_round_opts* o, double* err_o
   int32_t* rkl = (int32_t*)ws_take(ctx, sizeof(int32_t) * B * (n + 1));
   QT_CHECK(scratch && Wq && Bsv && Rb && Vb && Cb && tau && norm && delta && disc2 && rkl,
            QT_ENOMEM, "tt_round: workspace too small");
+  QrBlkWs qb{};
+  if (w.qb_v > 0) {
+    qb.V = (cplx*)ws_take(ctx, sizeof(cplx) * B * w.qb_v);
+    qb.v_stride = w.qb_v;
+    qb.T = (cplx*)ws_take(ctx, sizeof(cplx) * B * w.qb_t);
+    qb.t_stride = w.qb_t;
+    qb.W1 = (cplx*)ws_take(ctx, sizeof(cplx) * B * w.qb_w);
+    qb.W2 = (cplx*)ws_take(ctx, sizeof(cplx) * B * w.qb_w);
+    qb.w_stride = w.qb_w;
+    qb.tau = (double*)ws_take(ctx, sizeof(double) * B * w.qb_tau);
+    qb.tau_stride = w.qb_tau;
+    qb.s_dev = (int32_t*)ws_take(ctx, sizeof(int32_t) * B);
+    QT_CHECK(qb.V && qb.T && qb.W1 && qb.W2 && qb.tau && qb.s_dev, QT_ENOMEM,
+             "tt_round: blocked QR workspace too small");
+  }
   cplx* X = (cplx*)x->data;
   const int64_t sX = x->inst_stride;
   const int rs = n + 1;
@@ -85,9 +111,14 @@ qt_status round_impl(qt_ctx ctx, qt_tt* x, const qt_round_opts* o, double* err_o
     const cplx* in = (k == 0) ? X + x->offsets[0] : scratch;
     const int64_t sin = (k == 0) ? sX : w.slot;
     // left_only (norm of the train): R is all that is carried, Q is not formed
-    qr_auto(st, B, x->cap[k] * p, x->cap[k + 1], dref(rkl + k, rs, p), dref(rk + k + 1, rs), in,
-            sin, Wq, w.slot, tau, w.tau, left_only ? nullptr : X + x->offsets[k], sX, Rb, w.rr,
-            rkl + k + 1, rs);
+    if (qr_blocked_wanted(x->cap[k] * p, x->cap[k + 1]))
+      qr_blocked(st, B, x->cap[k] * p, x->cap[k + 1], dref(rkl + k, rs, p), dref(rk + k + 1, rs),
+                 in, sin, Wq, w.slot, qb, left_only ? nullptr : X + x->offsets[k], sX, Rb, w.rr,
+                 rkl + k + 1, rs);
+    else
+      qr_auto(st, B, x->cap[k] * p, x->cap[k + 1], dref(rkl + k, rs, p), dref(rk + k + 1, rs),
+              in, sin, Wq, w.slot, tau, w.tau, left_only ? nullptr : X + x->offsets[k], sX, Rb,
+              w.rr, rkl + k + 1, rs);
     const int p1 = x->modes[k + 1];
     // scratch (s x p1 r_{k+2}) = R (s x r_{k+1}) * core_{k+1} (r_{k+1} x p1 r_{k+2})
     gemm(st, B, dref(rkl + k + 1, rs), dref(rk + k + 2, rs, p1), dref(rk + k + 1, rs),
@@ -113,6 +144,12 @@ qt_status round_impl(qt_ctx ctx, qt_tt* x, const qt_round_opts* o, double* err_o
   return QT_OK;
 }
 
+// Sweep cap of the global-memory Jacobi: twice the context default unless the
+// caller set a cap of its own.
+static int sweeps_global(qt_ctx ctx, int sweeps) {
+  return sweeps == ctx->jacobi_default ? 2 * sweeps : sweeps;
+}
+
 qt_status take_sweep_extra(qt_ctx ctx, int B, const RoundWs& w, SweepBufs& buf) {
   buf.U = (cplx*)ws_take(ctx, sizeof(cplx) * B * w.slot);
   buf.RV = (cplx*)ws_take(ctx, sizeof(cplx) * B * w.vv);
@@ -127,6 +164,7 @@ qt_status right_sweep_impl(qt_ctx ctx, qt_tt* x, const int32_t* rkl, const cplx*
                            int64_t cstride, const SweepBufs& buf, const double* delta,
                            double* disc2, int lmax_cap, int sweeps, double* svlog, int64_t svb,
                            int64_t svi) {
+  const int sweeps_glb = sweeps_global(ctx, sweeps);
   const int n = x->n, B = x->batch, rs = n + 1;
   hipStream_t st = ctx->stream;
   cplx* X = (cplx*)x->data;
@@ -146,9 +184,12 @@ qt_status right_sweep_impl(qt_ctx ctx, qt_tt* x, const int32_t* rkl, const cplx*
                         buf.Bsv, buf.U, buf.slot, buf.V, buf.RV, buf.vv, buf.tau, buf.sig,
                         buf.nbmax, X + x->offsets[k], sX, buf.C, buf.carry, rk + k, rs, delta,
                         disc2, lmax, sweeps, ctx->status, svk, svi, ctx->counters))
+      // the global-memory Jacobi works on B itself, without the QR preconditioning
+      // of the fast path: graded spectra with long tails of negligible singular
+      // values take it past 30 sweeps at orders above 100
       svd_trunc(st, B, dref(rkl + k, rs), dref(rk + k + 1, rs, p), in, sin, buf.Bsv, buf.slot,
                 buf.V, buf.vv, X + x->offsets[k], sX, buf.C, buf.carry, rk + k, rs, delta, disc2,
-                lmax, sweeps, ctx->status, svk, svi, 0);
+                lmax, sweeps_glb, ctx->status, svk, svi, 0);
     if (prof) g_prof->end();
     const int pp = x->modes[k - 1];
     // scratch (r'_{k-1} p x l_k) = core_{k-1} (r'_{k-1} p x r'_k) * carry (r'_k x l_k)

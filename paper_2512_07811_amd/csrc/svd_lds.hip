@@ -56,6 +56,17 @@ __global__ __launch_bounds__(1024) void k_jacobi_lds(
   __syncthreads();
   fro = 0.0;
   for (int i = 0; i < nw; ++i) fro += red[i];
+  if (tid == 0 && !isfinite(fro)) {
+    const int32_t old = atomicOr(status, (int32_t)ST_NONFINITE);
+    if (!(old & ST_NONFINITE)) {
+      double* d = status_diag(status) + 5;
+      d[0] = nb;
+      d[1] = fro;
+      d[2] = -1.0;
+      d[3] = 3.0;   // the triangle handed to the Jacobi
+      d[4] = 0.0;
+    }
+  }
   const double negl = SL_NEGL * fro;
   const double jtol = SL_EPS * (double)nb, jtol2 = jtol * jtol;
   const int nbp = (nb + 1) & ~1;
@@ -214,7 +225,17 @@ __global__ __launch_bounds__(1024) void k_jacobi_lds(
       if (!isfinite(sj)) finite = false;
       if (j >= l) d2 += sj * sj;
     }
-    if (!finite) atomicOr(status, (int32_t)ST_NONFINITE);
+    if (!finite) {
+      const int32_t old = atomicOr(status, (int32_t)ST_NONFINITE);
+      if (!(old & ST_NONFINITE)) {
+        double* d = status_diag(status) + 5;
+        d[0] = nb;
+        d[1] = fro;
+        d[2] = -1.0;
+        d[3] = 1.0;   // LDS Jacobi
+        d[4] = sweeps_done;
+      }
+    }
     disc2[b] += d2;
     sh_l = l;
     if (l_out) l_out[(int64_t)b * l_stride] = l;

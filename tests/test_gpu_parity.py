@@ -126,6 +126,33 @@ def test_round_large_ranks_matches_oracle(q, ctx, eps):
         assert abs(nrm[b] - info["norm"]) < 1e-12 * info["norm"]
 
 
+@pytest.mark.parametrize("eps,rmax", [(0.0, 0), (1e-6, 0), (1e-12, 40)])
+def test_round_blocked_qr_matches_oracle(q, ctx, eps, rmax):
+    # capacities of 280 make the left sweep's unfoldings (up to 560 x 280)
+    # take the blocked Householder QR (panels of 32 columns, trailing updates
+    # and Q on the MFMA GEMM); the actual ranks (up to 160, the second instance
+    # smaller) leave panels idle or partial inside those launches
+    modes = [3] + [2] * 15
+    r0 = [1, 3, 6, 12, 24, 48, 96, 160, 160, 128, 64, 32, 16, 8, 4, 2, 1]
+    r1 = [1, 3, 6, 12, 24, 48, 70, 100, 90, 64, 40, 32, 16, 8, 4, 2, 1]
+    cap = [1, 3, 6, 12, 24, 48, 96, 280, 280, 256, 64, 32, 16, 8, 4, 2, 1]
+    xs = [I.graded_tt(modes, r0, decay=0.93, seed=170),
+          I.graded_tt(modes, r1, decay=0.9, seed=171)]
+    X = q.DeviceTT.from_cores(xs, cap)
+    err, nrm = q.tt_round(ctx, X, eps, rmax)
+    ctx.sync()
+    out = X.to_cores()
+    nrm = nrm.cpu().numpy()
+    err = err.cpu().numpy()
+    for b in range(2):
+        ref, info = T.round_tt(xs[b], eps, rmax or None, return_info=True)
+        assert T.ranks(out[b]) == T.ranks(ref)
+        assert rel(T.full(out[b]), T.full(ref)) < 1e-10
+        assert abs(nrm[b] - info["norm"]) < 1e-12 * info["norm"]
+        # the discarded tails (~eps ||x||) carry absolute errors ~1e-16 ||x||
+        assert abs(err[b] - info["err"]) <= 1e-6 * info["err"] + 1e-13
+
+
 def test_round_product_train_and_ragged_batch(q, ctx):
     # a materialized Hadamard product is rounded exactly like the oracle does
     modes = [3] + [2] * 8
