@@ -239,10 +239,24 @@ static size_t round_bytes(const TTLayout& L, int B, int rmax) {
   return round_ws_layout(&t, rmax > 0 ? rmax : (1 << 30)).bytes;
 }
 
+// Workspace of residual_norm beyond the difference train itself.
+static size_t residual_bytes(const TTLayout& ld, int B, int rmax) {
+  const int n = (int)ld.modes.size();
+  int64_t env = 1, tcap = 1;
+  for (int k = 0; k <= n; ++k) env = std::max<int64_t>(env, (int64_t)ld.cap[k] * ld.cap[k]);
+  for (int k = 0; k < n; ++k)
+    tcap = std::max<int64_t>(tcap, (int64_t)ld.cap[k] * ld.modes[k] * ld.cap[k + 1]);
+  const size_t dot = sizeof(cplx) * B * (2 * env + tcap) + 4096;
+  qt_tt t = ld.view(nullptr, nullptr, B);
+  const size_t sweep = round_ws_layout(&t, rmax > 0 ? rmax : (1 << 30)).bytes;
+  return std::max(dot, sweep) + sizeof(double) * 8 * B + sizeof(int32_t) * B + 4 * 256;
+}
+
 static size_t iteration_bytes(const IterPlan& P, int B, int rmax) {
   size_t r = 0;
-  for (const TTLayout* L : {&P.l1, &P.l2, &P.l3, &P.l4, &P.l5, &P.l6})
+  for (const TTLayout* L : {&P.l1, &P.l2, &P.l3, &P.l4, &P.l5})
     r = std::max(r, round_bytes(*L, B, rmax));
+  r = std::max(r, residual_bytes(P.l6, B, rmax));
   const int n = (int)P.modes.size();
   return P.bytesA + P.bytesB + r + sizeof(int32_t) * B * (n + 1) * 2 + sizeof(double) * B * 4 +
          4096;
@@ -256,6 +270,61 @@ __global__ void k_take_re(int batch, const double* pairs, double* out) {
 __global__ void k_residual(int batch, const double* norm, const double* inv_scale, double* out) {
   int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b < batch) out[b] = norm[b] * inv_scale[b];
+}
+
+// Residual ||e' - e|| of the stopping rule (Alg. 2) for d = e' - e.
+// Environment contractions give ||d||^2, ||e'||^2 and ||e||^2; their rounding
+// error is about n R u (||e'||^2 + ||e||^2) (n cores, R the summed rank, u the
+// unit roundoff), so where ||d||^2 > RES_DOT_TOL (||e'||^2 + ||e||^2) the dot
+// value is accurate to a relative 2 n R u / RES_DOT_TOL (< 1e-8 at n R <= 1e4)
+// and the instance takes it.  Closer to convergence the difference cancels
+// and the left-orthogonalizing sweep of d (relative error ~ u ||e|| / ||d||)
+// decides; instances that took the dot value get rank-0 interior bonds, so
+// every kernel of that sweep finds nothing to do for them.
+constexpr double RES_DOT_TOL = 1e-4;
+
+__global__ void k_res_choose(int batch, int n, const double* __restrict__ pd,
+                             const double* __restrict__ pe1, const double* __restrict__ pe0,
+                             int32_t* dranks, double* rdot, int32_t* use_dot) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= batch) return;
+  const double d2 = pd[2 * b], s2 = pe1[2 * b] + pe0[2 * b];
+  const bool dot = d2 > RES_DOT_TOL * s2;
+  use_dot[b] = dot ? 1 : 0;
+  rdot[b] = dot ? sqrt(d2) : 0.0;
+  if (dot)
+    for (int k = 1; k < n; ++k) dranks[(int64_t)b * (n + 1) + k] = 0;
+}
+
+__global__ void k_res_merge(int batch, const int32_t* __restrict__ use_dot,
+                            const double* __restrict__ rdot, double* dnorm) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < batch && use_dot[b]) dnorm[b] = rdot[b];
+}
+
+static qt_status residual_norm(qt_ctx ctx, const qt_tt* enew, const qt_tt* e, qt_tt* d,
+                               double* dnorm, const qt_round_opts& ro) {
+  const int B = d->batch, n = d->n;
+  hipStream_t st = ctx->stream;
+  double* pairs = (double*)ws_take(ctx, sizeof(double) * 6 * B);
+  double* rdot = (double*)ws_take(ctx, sizeof(double) * B);
+  int32_t* use = (int32_t*)ws_take(ctx, sizeof(int32_t) * B);
+  QT_CHECK(pairs && rdot && use, QT_ENOMEM, "residual workspace");
+  const size_t mark = ctx->ws_top;
+  QT_TRY(dot_impl(ctx, d, d, pairs, false));
+  ctx->ws_top = mark;
+  QT_TRY(dot_impl(ctx, enew, enew, pairs + 2 * B, false));
+  ctx->ws_top = mark;
+  QT_TRY(dot_impl(ctx, e, e, pairs + 4 * B, false));
+  ctx->ws_top = mark;
+  k_res_choose<<<(B + 127) / 128, 128, 0, st>>>(B, n, pairs, pairs + 2 * B, pairs + 4 * B,
+                                                d->ranks, rdot, use);
+  qt_round_opts po = ro;
+  po.mode = QT_ROUND_SVD;
+  QT_TRY(round_impl(ctx, d, &po, nullptr, dnorm, true, nullptr, 0, 0));
+  k_res_merge<<<(B + 127) / 128, 128, 0, st>>>(B, use, rdot, dnorm);
+  QT_HIP(hipGetLastError());
+  return QT_OK;
 }
 
 // One iteration of Algorithm 2 with materialized products and SVD rounding.
@@ -293,10 +362,10 @@ static qt_status iterate_once(qt_ctx ctx, const qt_operands* ops, qt_tt* e, cons
   QT_TRY(round_impl(ctx, &t5, &ro, nullptr, nullptr, false, nullptr, 0, 0));
   ctx->ws_top = mark;
   qt_tt t5r = shrink(t5, P.c5, rmax, s5);
-  // residual ||e' - e|| by left orthogonalization of the difference
+  // residual ||e' - e||
   qt_tt t6 = P.l6.view(bufB, rB, B);
   QT_TRY(add_impl(ctx, 1.0, 0.0, &t5r, -1.0, 0.0, e, &t6));
-  QT_TRY(round_impl(ctx, &t6, &ro, nullptr, dnorm, true, nullptr, 0, 0));
+  QT_TRY(residual_norm(ctx, &t5r, e, &t6, dnorm, ro));
   ctx->ws_top = mark;
   if (res_out) {
     k_residual<<<(B + 127) / 128, 128, 0, ctx->stream>>>(B, dnorm, dinv, res_out);
@@ -452,7 +521,7 @@ static SketchPlan plan_sketch(const qt_operands* ops, const qt_tt* e, const qt_r
   }
   yv = *e;
   ws = std::max(ws, sandwich_ws_layout(&ops->K2, &yv).bytes);
-  ws = std::max(ws, round_bytes(P.l6, B, rmax));
+  ws = std::max(ws, residual_bytes(P.l6, B, rmax));
   P.ws = ws;
   return P;
 }
@@ -618,12 +687,10 @@ static qt_status iterate_once_sketch(qt_ctx ctx, const qt_operands* ops, qt_tt* 
     const std::vector<int32_t>* ells[4] = {&P.ell1, &P.ell2, &P.ell3, &P.ell4};
     QT_TRY(learn_advance(ctx, learned, ells));
   }
-  // residual: ||e' - e|| from a left-orthogonalizing sweep of the difference
+  // residual ||e' - e||
   qt_tt t6 = P.l6.view(bufB, rB, B);
   QT_TRY(add_impl(ctx, 1.0, 0.0, &t4r, -1.0, 0.0, e, &t6));
-  qt_round_opts po = ro;
-  po.mode = QT_ROUND_SVD;
-  QT_TRY(round_impl(ctx, &t6, &po, nullptr, dnorm, true, nullptr, 0, 0));
+  QT_TRY(residual_norm(ctx, &t4r, e, &t6, dnorm, ro));
   ctx->ws_top = mark;
   if (res_out) {
     k_residual<<<(B + 127) / 128, 128, 0, st>>>(B, dnorm, dinv, res_out);
