@@ -193,6 +193,36 @@ def test_ls_iterates_match_oracle_without_truncation(q, ctx, L):
         assert abs(res[0, 0] - r_ref) < 1e-9 * max(r_ref, 1e-6)
 
 
+def test_residual_dot_value_and_exact_sweep_in_one_batch(q, ctx):
+    # the residual takes the environment dot value where ||e' - e|| is large
+    # against ||e'|| + ||e|| and the exact left-orthogonalizing sweep close to
+    # convergence; field 0 starts at E (residual 0.11, dot value), field 1
+    # three oracle iterations in (residual 2.8e-4, exact sweep), one batch
+    from paper_2512_07811_amd import operands as P
+    L, N = 2, 4
+    g = I.rng(77)
+    k = g.uniform(1.0, 3.0, size=(N, N, N))
+    k0 = 2.0
+    E = np.array([1.0, 0.0, 0.0])
+    prob = P.build_problem(kvox=k, k0=k0, op_eps=1e-14, sfft_eps=1e-14)
+    oprob = ls_tt.Problem(k, k0, op_eps=1e-14, sfft_eps=1e-14)
+    E_tt = O.mean_field_tt(E, L)
+    x = O.mean_field_tt(E, L)
+    for _ in range(3):
+        x, r = ls_tt.ls_iterate(x, oprob.kp, oprob.S, oprob.G, oprob.Sinv, E_tt, E, 0.0)
+    starts = [O.mean_field_tt(E, L), x]
+    refs = [ls_tt.ls_iterate(s0, oprob.kp, oprob.S, oprob.G, oprob.Sinv, E_tt, E, 0.0)
+            for s0 in starts]
+    assert refs[0][1] > 1e-2 and refs[1][1] < 1e-3
+    ops, e = P.upload(prob, [E, E], max_rank=0)
+    e = q.DeviceTT.from_cores(starts, e.cap)
+    res = q.ls_iterate(ctx, ops, e, q.solve_opts(0.0, 0, mode=q.ROUND_SVD), 1).cpu().numpy()
+    out = e.to_cores()
+    for b in range(2):
+        assert rel(T.full(out[b]), T.full(refs[b][0])) < 1e-10
+        assert abs(res[0, b] - refs[b][1]) < 1e-8 * refs[b][1]
+
+
 def test_ls_iterates_match_oracle_with_binding_rank_cap(q, ctx):
     # a cap that binds on the middle bonds of three of the four roundings; the
     # spectra are separated at the cut, so the truncation is well defined and
