@@ -388,11 +388,14 @@ static qt_status check_status(qt_ctx ctx) {
                             ctx->stream));
       QT_HIP(hipStreamSynchronize(ctx->stream));
       char msg[256];
+      static const char* where[] = {"", "LDS Jacobi", "global-memory Jacobi",
+                                    "triangle given to the LDS Jacobi", "",
+                                    "", "core from the Jacobi (tall)", "core from the finalizer (wide)",
+                                    "carry from the Jacobi (wide)", "carry from the finalizer (tall)"};
+      const int w = (int)d[8];
       snprintf(msg, sizeof(msg),
-               "non-finite values in a rounding (%s, order %d, ||R||_F^2 %.3e, %d sweeps)",
-               d[8] == 1.0 ? "LDS Jacobi" : (d[8] == 3.0 ? "triangle given to the LDS Jacobi"
-                                                          : "global-memory Jacobi"),
-               (int)d[5], d[6], (int)d[9]);
+               "non-finite values in a rounding (%s, order %d, values %.3e %.3e, count %d)",
+               (w >= 1 && w <= 9) ? where[w] : "?", (int)d[5], d[6], d[7], (int)d[9]);
       set_error(msg);
       return QT_ENUMERIC;
     }

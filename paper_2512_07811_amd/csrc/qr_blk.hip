@@ -181,8 +181,12 @@ __global__ __launch_bounds__(QB_T) void k_qrb_panel(int j0, Dim Md, Dim Nd, cplx
       const cplx ph = a2 > 0.0 ? make_double2(al.x / aa, al.y / aa) : make_double2(1.0, 0.0);
       beta = make_double2(-ph.x * xn, -ph.y * xn);
       const cplx u0 = csub(al, beta);
-      const double d = cabs2(u0);
-      iu0 = make_double2(u0.x / d, -u0.y / d);
+      // 1 / u0 with u0 scaled by its larger component first (|u0|^2 can
+      // leave the double range for numerically vanishing columns)
+      const double sc = fmax(fabs(u0.x), fabs(u0.y));
+      const cplx v = make_double2(u0.x / sc, u0.y / sc);
+      const double d = cabs2(v) * sc;
+      iu0 = make_double2(v.x / d, -v.y / d);
       t = 1.0 + aa / xn;
     }
     cplx* vj = V + (int64_t)j * ld;

@@ -19,6 +19,37 @@ namespace qt {
 
 constexpr int QG = 64;  // row groups per workgroup
 
+// Householder reflector of a column x (head al = x_j, tail sum of squares
+// sig2): beta = -e^{i arg al} ||x||, iu0 = 1 / (al - beta), t = 1 + |al| / ||x||,
+// so that u = x / (al - beta) (u_j = 1) and H = I - t u u^H maps x to beta e_j.
+// When ||x||^2 < 2^-900 the caller passes al and sig2 of the column scaled by
+// sc = 2^600 (an exact power of two): squares and reciprocals of the unscaled
+// values would leave the double range; u and t do not depend on the scale,
+// beta and iu0 are returned for the unscaled column.
+__device__ inline void house_coef(cplx al, double sig2, double sc, double& t, cplx& beta,
+                                  cplx& iu0) {
+  const double a2 = cabs2(al), x2 = a2 + sig2;
+  if (x2 == 0.0) {
+    t = 0.0; beta = cscale(al, 1.0 / sc); iu0 = make_double2(0.0, 0.0);
+    return;
+  }
+  const double ixn = fast_rsq(x2), xn = x2 * ixn;
+  double aa = 0.0;
+  cplx ph = make_double2(1.0, 0.0);
+  if (a2 > 0.0) {
+    const double ia = fast_rsq(a2);
+    aa = a2 * ia;
+    ph = make_double2(al.x * ia, al.y * ia);
+  }
+  const cplx bs = make_double2(-ph.x * xn, -ph.y * xn);
+  const cplx u0 = csub(al, bs);
+  const double id = fast_rcp(cabs2(u0)) * sc;
+  iu0 = make_double2(u0.x * id, -u0.y * id);
+  beta = cscale(bs, 1.0 / sc);
+  t = 1.0 + aa * ixn;
+}
+constexpr double QR_TINY = 0x1p-900, QR_SCALE = 0x1p+600;
+
 template <int RPL, int CPS, bool ORIENT>
 __global__ __launch_bounds__(1024) void k_qr_reg(Dim Md, Dim Nd, const cplx* __restrict__ A,
                                                  int64_t sA, cplx* __restrict__ U, int64_t sU,
@@ -74,25 +105,22 @@ __global__ __launch_bounds__(1024) void k_qr_reg(Dim Md, Dim Nd, const cplx* __r
       }
       sig2 = row16_sum(sig2);
       al = row16_sum(al);  // one lane contributes
-      const double a2 = cabs2(al), x2 = a2 + sig2;
       double t;
       cplx beta, iu0;
-      if (x2 == 0.0) {
-        t = 0.0; beta = al; iu0 = make_double2(0.0, 0.0);
-      } else {
-        const double ixn = fast_rsq(x2), xn = x2 * ixn;
-        double aa = 0.0;
-        cplx ph = make_double2(1.0, 0.0);
-        if (a2 > 0.0) {
-          const double ia = fast_rsq(a2);
-          aa = a2 * ia;
-          ph = make_double2(al.x * ia, al.y * ia);
+      {
+        double sc = 1.0, s2 = sig2;
+        const double x2 = cabs2(al) + sig2;
+        if (x2 > 0.0 && x2 < QR_TINY) {   // uniform over the row group
+          sc = QR_SCALE;
+          s2 = 0.0;
+#pragma unroll
+          for (int r = 0; r < RPL; ++r) {
+            const int i = g + 16 * r;
+            if (i > j && i < m) s2 += cabs2(cscale(col[r], sc));
+          }
+          s2 = row16_sum(s2);
         }
-        beta = make_double2(-ph.x * xn, -ph.y * xn);
-        cplx u0 = csub(al, beta);
-        const double id = fast_rcp(cabs2(u0));
-        iu0 = make_double2(u0.x * id, -u0.y * id);
-        t = 1.0 + aa * ixn;
+        house_coef(cscale(al, sc), s2, sc, t, beta, iu0);
       }
 #pragma unroll
       for (int r = 0; r < RPL; ++r) {
@@ -346,25 +374,18 @@ __global__ __launch_bounds__(1024) void k_qr_mem(Dim Md, Dim Nd, const cplx* __r
       }
       sig2 = row16_sum(sig2);
       const cplx al = colj[j];
-      const double a2 = cabs2(al), x2 = a2 + sig2;
       double t;
       cplx beta, iu0;
-      if (x2 == 0.0) {
-        t = 0.0; beta = al; iu0 = make_double2(0.0, 0.0);
-      } else {
-        const double ixn = fast_rsq(x2), xn = x2 * ixn;
-        double aa = 0.0;
-        cplx ph = make_double2(1.0, 0.0);
-        if (a2 > 0.0) {
-          const double ia = fast_rsq(a2);
-          aa = a2 * ia;
-          ph = make_double2(al.x * ia, al.y * ia);
+      {
+        double sc = 1.0, s2 = sig2;
+        const double x2 = cabs2(al) + sig2;
+        if (x2 > 0.0 && x2 < QR_TINY) {   // uniform over the row group
+          sc = QR_SCALE;
+          s2 = 0.0;
+          for (int i = j + 1 + g; i < m; i += 16) s2 += cabs2(cscale(colj[i], sc));
+          s2 = row16_sum(s2);
         }
-        beta = make_double2(-ph.x * xn, -ph.y * xn);
-        cplx u0 = csub(al, beta);
-        const double id = fast_rcp(cabs2(u0));
-        iu0 = make_double2(u0.x * id, -u0.y * id);
-        t = 1.0 + aa * ixn;
+        house_coef(cscale(al, sc), s2, sc, t, beta, iu0);
       }
       for (int i0 = j + 1; i0 < m; i0 += 16 * QM_CH) {
         cplx xx[QM_CH];

@@ -1,12 +1,15 @@
 // Truncated SVD for the right-to-left sweep, small sizes (min(m, c) <= 100;
 // R and V in LDS up to 68, R in LDS and V in global memory up to 100):
 //   1. B = A (m >= c) or A^H (m < c); B = Q R by the register-resident QR;
-//   2. one-sided (Hestenes) Jacobi on the square R with R and V in LDS
-//      (R V = U_R Sigma), 16 waves, round-robin pairs, one barrier per round;
+//   2. one-sided (Hestenes) Jacobi on the columns of R^H (lower triangular),
+//      which converge in fewer sweeps than R's (the rows of a triangular
+//      factor are better separated than its columns; Drmac and Veselic,
+//      SIAM J. Matrix Anal. Appl. 29, 2008): R^H W = U Sigma, so R = W Sigma U^H
+//      (R^H and W in LDS, 16 waves, round-robin pairs, one barrier per round);
 //   3. truncation (smallest l whose discarded tail <= delta, l <= lmax);
-//   4. outputs: for A = Q R:   core = V^H[:l],  carry = Q (R V)[:, :l];
-//               for A^H = Q R: core = (Q (R V)[:, r] / sigma_r)^H,
-//                              carry = V[:, :l] Sigma[:l].
+//   4. outputs: for A = Q R:   core = U^H[:l] = ((R^H W)[:, r] / sigma_r)^H,
+//                              carry = Q W[:, :l] Sigma[:l];
+//               for A^H = Q R: core = (Q W[:, r])^H,  carry = (R^H W)[:, :l].
 // Rotation: gamma = b_p^H b_q = |gamma| e^{i phi}, zeta = (beta - alpha)/(2|gamma|),
 // t = sign(zeta)/(|zeta| + sqrt(1 + zeta^2)), c = 1/sqrt(1 + t^2), s = c t,
 // [b_p, b_q] <- [b_p, b_q] [[c, s e^{i phi}], [-s e^{-i phi}, c]].
@@ -18,6 +21,21 @@ constexpr int SL_NB = 68;            // LDS holds two SL_NB x SL_NB complex matr
 constexpr int SL_NB_BIG = 100;       // LDS holds R only (160000 bytes), V in global memory
 constexpr double SL_EPS = 2.0 * 2.220446049250313e-16;
 constexpr double SL_NEGL = 1e-34;
+
+// Flags a non-finite output of the truncated SVD (stage 5 + 2 * out + tall:
+// out 0 core, 1 carry) with the order, kept rank and extreme kept sigmas.
+__device__ inline void flag_out(int32_t* status, int stage, int nb, int l, double smax,
+                                double smin) {
+  const int32_t old = atomicOr(status, (int32_t)ST_NONFINITE);
+  if (!(old & ST_NONFINITE)) {
+    double* d = status_diag(status) + 5;
+    d[0] = nb;
+    d[1] = smax;
+    d[2] = smin;
+    d[3] = stage;
+    d[4] = l;
+  }
+}
 
 // NBMAX: largest order; VG: V kept in global memory (Vg + b * sV, nb x nb);
 // the large variant re-reads R from LDS for the rotation to stay within the
@@ -46,7 +64,7 @@ __global__ __launch_bounds__(1024) void k_jacobi_lds(
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
   for (int e = tid; e < nb * nb; e += blockDim.x) {
     const int i = e / nb, c = e % nb;       // R row-major (nb x nb)
-    Rs[c * nb + i] = Rin[e];
+    Rs[e] = cconj(Rin[e]);                  // column c of R^H = conj(row c of R)
     Vs[c * nb + i] = make_double2(i == c ? 1.0 : 0.0, 0.0);
   }
   double fro = 0.0;
@@ -244,35 +262,48 @@ __global__ __launch_bounds__(1024) void k_jacobi_lds(
   const int l = sh_l;
   if (svlog)
     for (int j = tid; j < nb; j += blockDim.x) svlog[b * svstride + j] = sig[perm[j]];
-  // (R V)[:, perm[:l]] column-major and sorted sigma for the finalizer
+  // W[:, perm[:l]] column-major and sorted sigma for the finalizer
   for (int e = tid; e < l * nb; e += blockDim.x) {
     const int r = e / nb, i = e % nb;
-    RVp[e] = Rs[perm[r] * nb + i];
+    RVp[e] = Vs[perm[r] * nb + i];
   }
   for (int r = tid; r < l; r += blockDim.x) sigp[r] = sig[perm[r]];
+  bool fin = true;
   if (tall) {
-    // core = V^H[:l]  (l x nc), nc = nb
+    // core = U^H[:l]  (l x nc), nc = nb; U[:, r] = (R^H W)[:, r] / sigma_r
     for (int e = tid; e < l * nb; e += blockDim.x) {
       const int r = e / nb, c = e % nb;
-      core[e] = cconj(Vs[perm[r] * nb + c]);
+      const double sv = sig[perm[r]];
+      const cplx v = sv > 0.0 ? cscale(cconj(Rs[perm[r] * nb + c]), 1.0 / sv)
+                              : make_double2(c == r ? 1.0 : 0.0, 0.0);
+      fin = fin && isfinite(v.x) && isfinite(v.y);
+      core[e] = v;
     }
   } else {
-    // carry = V[:, perm[:l]] Sigma  (m x l), m = nb
+    // carry = (R^H W)[:, perm[:l]] = U Sigma  (m x l), m = nb
     for (int e = tid; e < nb * l; e += blockDim.x) {
       const int i = e / l, r = e % l;
-      carry[e] = cscale(Vs[perm[r] * nb + i], sig[perm[r]]);
+      const cplx v = Rs[perm[r] * nb + i];
+      fin = fin && isfinite(v.x) && isfinite(v.y);
+      carry[e] = v;
     }
   }
+  for (int e = tid; e < l * nb; e += blockDim.x) {
+    const cplx v = RVp[e];
+    fin = fin && isfinite(v.x) && isfinite(v.y);
+  }
+  if (!fin) flag_out(status, tall ? 6 : 8, nb, l, sig[perm[0]], sig[perm[l - 1]]);
 }
 
-// Applies Q (mb x nb, row-major) to the kept columns of R V.
+// Applies Q (mb x nb, row-major) to the kept columns of W: the carry
+// Q W Sigma (A = Q R) or the core rows (Q W)^H (A^H = Q R).
 __global__ __launch_bounds__(1024) void k_svd_finalize(Dim Md, Dim Cd, const cplx* __restrict__ Q,
                                                        int64_t sQ, const cplx* __restrict__ RVp,
                                                        int64_t sRV, const double* __restrict__ sigp,
                                                        int64_t sSig, const int32_t* l_in,
                                                        int l_stride, cplx* __restrict__ core,
                                                        int64_t sCore, cplx* __restrict__ carry,
-                                                       int64_t sCarry) {
+                                                       int64_t sCarry, int32_t* status) {
   const int b = blockIdx.x;
   const int m = dimv(Md, b), nc = dimv(Cd, b);
   const bool tall = m >= nc;
@@ -286,10 +317,12 @@ __global__ __launch_bounds__(1024) void k_svd_finalize(Dim Md, Dim Cd, const cpl
     const cplx* rv = RVp + (int64_t)r * nb;
     for (int c = 0; c < nb; ++c) cfma(acc, qi[c], rv[c]);
     if (tall) {
-      carry[(int64_t)i * l + r] = acc;                     // carry (m x l)
+      const cplx v = cscale(acc, sigp[r]);
+      if (!(isfinite(v.x) && isfinite(v.y))) flag_out(status, 9, nb, l, sigp[0], sigp[l - 1]);
+      carry[(int64_t)i * l + r] = v;                       // carry (m x l)
     } else {
-      const double sv = sigp[r];
-      cplx v = sv > 0.0 ? cscale(cconj(acc), 1.0 / sv) : make_double2(i == r ? 1.0 : 0.0, 0.0);
+      const cplx v = cconj(acc);
+      if (!(isfinite(v.x) && isfinite(v.y))) flag_out(status, 7, nb, l, sigp[0], sigp[l - 1]);
       core[(int64_t)r * nc + i] = v;                       // core (l x nc), row r
     }
   }
@@ -315,7 +348,7 @@ bool svd_trunc_fast(hipStream_t st, int batch, int mcap, int ccap, Dim m, Dim c,
         m, c, Rw, sR, RVw, sR, sig, sT, core, sCore, carry, sCarry, l_out, l_stride, delta, disc2,
         lmax, max_sweeps, status, svlog, svstride, counters, Uw, sQ);
   k_svd_finalize<<<batch, 1024, 0, st>>>(m, c, Qw, sQ, RVw, sR, sig, sT, l_out, l_stride, core,
-                                         sCore, carry, sCarry);
+                                         sCore, carry, sCarry, status);
   return true;
 }
 

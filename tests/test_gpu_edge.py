@@ -85,3 +85,25 @@ def test_round_zero_and_single_core_trains(q, ctx):
     ctx.sync()
     assert abs(nrm.cpu().numpy()[0] - np.linalg.norm(one[0])) < 1e-14 * np.linalg.norm(one[0])
     assert np.allclose(X.to_cores()[0][0], one[0], atol=0)
+
+
+@pytest.mark.parametrize("eps", [0.0, 1e-12])
+def test_round_component_below_double_square_range(q, ctx, eps):
+    # x = a + 1e-160 b: after the first reflection the orthogonal part of a
+    # column is ~1e-160, whose squared norm is denormal; the reflector is then
+    # computed from the column scaled by 2^600 (a finite, exact rounding is
+    # required: the tiny component is kept at eps = 0, dropped at eps > 0)
+    modes = [3] + [2] * 7
+    a = I.random_tt(modes, [1] * 9, seed=91)
+    b = I.random_tt(modes, [1] * 9, seed=92)
+    x = T.add(a, T.scale(b, 1e-160))
+    X = q.DeviceTT.from_cores([x])
+    err, nrm = q.tt_round(ctx, X, eps)
+    ctx.sync()
+    out = X.to_cores()[0]
+    ref, info = T.round_tt(x, eps, None, return_info=True)
+    full_out = T.full(out)
+    assert np.all(np.isfinite(full_out))
+    assert T.ranks(out) == T.ranks(ref)
+    assert np.linalg.norm(full_out - T.full(ref)) <= 1e-14 * np.linalg.norm(T.full(ref))
+    assert abs(nrm.cpu().numpy()[0] - info["norm"]) <= 1e-14 * info["norm"]
