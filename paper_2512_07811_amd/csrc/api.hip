@@ -15,7 +15,10 @@ thread_local ProfSink* g_prof = nullptr;
 thread_local unsigned long long* g_counters = nullptr;
 thread_local SplitKBuf g_splitk;
 
+// Regions do not nest: work launched inside an open region (the finishing
+// products of a large SVD, the products of a blocked QR) counts to that region.
 void ProfSink::begin() {
+  if (depth++ > 0) return;
   if (used + 2 > ev.size()) {
     for (int i = 0; i < 64; ++i) {
       hipEvent_t e;
@@ -27,6 +30,7 @@ void ProfSink::begin() {
 }
 
 void ProfSink::end() {
+  if (--depth > 0) return;
   if (used + 2 > ev.size()) return;
   hipEventRecord(ev[used + 1], stream);
   used += 2;

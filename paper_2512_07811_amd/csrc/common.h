@@ -212,6 +212,7 @@ struct ProfSink {
   hipStream_t stream = nullptr;
   std::vector<hipEvent_t> ev;   // start/stop pairs
   size_t used = 0;
+  int depth = 0;                // open regions (nested ones add to the outer one)
   void begin();                 // record a start event (grows the pool)
   void end();                   // record the matching stop event
 };

@@ -90,9 +90,10 @@ void svd_trunc(hipStream_t st, int batch, Dim m, Dim c, const cplx* A, int64_t s
                int lmax, int max_sweeps, int32_t* status, double* svlog, int64_t svstride,
                int nbcap);
 
-// Fast path of svd_trunc for min(m, c) <= 68 and max(m, c) <= 256 (register
-// QR + LDS Jacobi); returns false when the capacities do not fit.  Scratch:
-// Qw, Uw (max x min, stride sQ), Rw, RVw (min^2, stride sR), tau, sig (stride sT).
+// Truncated SVD by QR then one-sided Jacobi on R^H: R^H and W in LDS for
+// min(m, c) <= 68, R^H in LDS and W in global memory up to 100, both in global
+// memory up to 1024; returns false above that.  Scratch: Qw, Uw (max x min,
+// stride sQ), Rw, RVw (min^2, stride sR), tau, sig (stride sT).
 bool svd_trunc_fast(hipStream_t st, int batch, int mcap, int ccap, Dim m, Dim c, const cplx* A,
                     int64_t sA, cplx* Qw, cplx* Uw, int64_t sQ, cplx* Rw, cplx* RVw, int64_t sR,
                     double* tau, double* sig, int64_t sT, cplx* core, int64_t sCore, cplx* carry,

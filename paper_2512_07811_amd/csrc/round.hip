@@ -144,8 +144,10 @@ qt_status round_impl(qt_ctx ctx, qt_tt* x, const qt_round_opts* o, double* err_o
   return QT_OK;
 }
 
-// Sweep cap of the global-memory Jacobi: twice the context default unless the
-// caller set a cap of its own.
+// Sweep cap of the Jacobi at orders above 100 (R^H and W in global memory):
+// twice the context default unless the caller set a cap of its own; graded
+// spectra with long tails of negligible singular values need more sweeps
+// there (33 at order 160 on the columns of R's unpreconditioned B).
 static int sweeps_global(qt_ctx ctx, int sweeps) {
   return sweeps == ctx->jacobi_default ? 2 * sweeps : sweeps;
 }
@@ -180,13 +182,12 @@ qt_status right_sweep_impl(qt_ctx ctx, qt_tt* x, const int32_t* rkl, const cplx*
     double* svk = svlog ? svlog + k * svb : nullptr;
     const bool prof = prof_on(PROF_SVD);
     if (prof) g_prof->begin();
+    const int nsw = std::min(mcap, ccap) > 100 ? sweeps_glb : sweeps;
     if (!svd_trunc_fast(st, B, mcap, ccap, dref(rkl + k, rs), dref(rk + k + 1, rs, p), in, sin,
                         buf.Bsv, buf.U, buf.slot, buf.V, buf.RV, buf.vv, buf.tau, buf.sig,
                         buf.nbmax, X + x->offsets[k], sX, buf.C, buf.carry, rk + k, rs, delta,
-                        disc2, lmax, sweeps, ctx->status, svk, svi, ctx->counters))
-      // the global-memory Jacobi works on B itself, without the QR preconditioning
-      // of the fast path: graded spectra with long tails of negligible singular
-      // values take it past 30 sweeps at orders above 100
+                        disc2, lmax, nsw, ctx->status, svk, svi, ctx->counters))
+      // orders above 1024 (not reached: tt_round rejects SVD blocks above 1024)
       svd_trunc(st, B, dref(rkl + k, rs), dref(rk + k + 1, rs, p), in, sin, buf.Bsv, buf.slot,
                 buf.V, buf.vv, X + x->offsets[k], sX, buf.C, buf.carry, rk + k, rs, delta, disc2,
                 lmax, sweeps_glb, ctx->status, svk, svi, 0);
