@@ -81,15 +81,8 @@ void qr_blocked(hipStream_t st, int batch, int mcap, int ncap, Dim m, Dim n, con
 // Truncated SVD of the packed m x c matrix A by one-sided (Hestenes) Jacobi:
 // keeps the smallest l >= 1 whose discarded tail does not exceed delta[b],
 // l <= lmax; writes V^dagger[:l] (l x c) to core, U Sigma[:, :l] (m x l) to
-// carry, l to l_out, adds the squared discarded tail to disc2[b].  Scratch:
-// B (mb x nb), V (nb x nb) per instance.  svlog (may be null) receives the
-// sorted singular values (nb entries, stride svstride).
-void svd_trunc(hipStream_t st, int batch, Dim m, Dim c, const cplx* A, int64_t sA, cplx* Bw,
-               int64_t sB, cplx* Vw, int64_t sV, cplx* core, int64_t sCore, cplx* carry,
-               int64_t sCarry, int32_t* l_out, int l_stride, const double* delta, double* disc2,
-               int lmax, int max_sweeps, int32_t* status, double* svlog, int64_t svstride,
-               int nbcap);
-
+// carry, l to l_out, adds the squared discarded tail to disc2[b].  svlog (may
+// be null) receives the sorted singular values (stride svstride).
 // Truncated SVD by QR then one-sided Jacobi on R^H: R^H and W in LDS for
 // min(m, c) <= 68, R^H in LDS and W in global memory up to 100, both in global
 // memory up to 1024; returns false above that.  Scratch: Qw, Uw (max x min,

@@ -235,210 +235,6 @@ void qr_auto(hipStream_t st, int batch, int mcap, int ncap, Dim m, Dim n, const 
   if (prof) g_prof->end();
 }
 
-// ------------------------------------------------------------ Jacobi SVD
-// Columns of B (mb x nb, stored column-major: column c at B + c*mb) are made
-// mutually orthogonal by plane rotations [b_p, b_q] <- [b_p, b_q] J with
-//   J = [[c, s e^{i phi}], [-s e^{-i phi}, c]],  gamma = b_p^H b_q = |gamma| e^{i phi},
-//   zeta = (beta - alpha)/(2|gamma|), t = sign(zeta)/(|zeta| + sqrt(1 + zeta^2)),
-//   c = 1/sqrt(1 + t^2), s = c t;  the same J accumulates into V.
-// Pairs follow a round-robin (circle) schedule: every round is a set of
-// disjoint pairs, one per wave at a time.
-// Convergence: rotate only while |gamma| > 2 mb eps sqrt(alpha beta) (the
-// rounding bound of a length-mb dot product), and never between columns whose
-// norms are below 1e-17 ||B||_F (they carry no significant digits; rotating
-// them can cycle on underflowed values).
-constexpr double JAC_EPS = 2.0 * 2.220446049250313e-16;
-constexpr double JAC_NEGL = 1e-34;
-constexpr int SVD_MAXNB = 1024;
-
-__global__ __launch_bounds__(256) void k_svd_trunc(
-    Dim Md, Dim Cd, const cplx* __restrict__ A, int64_t sA, cplx* __restrict__ Bw, int64_t sB,
-    cplx* __restrict__ Vw, int64_t sV, cplx* __restrict__ core, int64_t sCore,
-    cplx* __restrict__ carry, int64_t sCarry, int32_t* l_out, int l_stride,
-    const double* __restrict__ delta, double* __restrict__ disc2, int lmax, int max_sweeps,
-    int32_t* status, double* svlog, int64_t svstride) {
-  const int b = blockIdx.x;
-  const int m = dimv(Md, b), nc = dimv(Cd, b);
-  const bool tall = m >= nc;
-  const int mb = tall ? m : nc, nb = tall ? nc : m;
-  A += b * sA; Bw += b * sB; Vw += b * sV; core += b * sCore; carry += b * sCarry;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
-  __shared__ double sig[SVD_MAXNB];
-  __shared__ int perm[SVD_MAXNB];
-  __shared__ int sh_rot;
-  __shared__ int sh_l;
-  // B = A (tall) or A^H (wide), column-major
-  for (int64_t e = tid; e < (int64_t)mb * nb; e += blockDim.x) {
-    int c = (int)(e / mb), i = (int)(e % mb);
-    Bw[e] = tall ? A[(int64_t)i * nc + c] : cconj(A[(int64_t)c * nc + i]);
-  }
-  for (int64_t e = tid; e < (int64_t)nb * nb; e += blockDim.x) {
-    int c = (int)(e / nb), i = (int)(e % nb);
-    Vw[e] = make_double2(i == c ? 1.0 : 0.0, 0.0);
-  }
-  __syncthreads();
-  const int nbp = (nb + 1) & ~1;
-  const double jtol = JAC_EPS * (double)mb;
-  __shared__ double red_f[16];
-  double fro = 0.0;
-  for (int64_t e = tid; e < (int64_t)mb * nb; e += blockDim.x) fro += cabs2(Bw[e]);
-  fro = wave_sum(fro);
-  if (lane == 0) red_f[wv] = fro;
-  __syncthreads();
-  fro = 0.0;
-  for (int i = 0; i < nw; ++i) fro += red_f[i];
-  const double negl = JAC_NEGL * fro;
-  int sweep = 0;
-  bool converged = (nb < 2);
-  for (; sweep < max_sweeps && !converged; ++sweep) {
-    if (tid == 0) sh_rot = 0;
-    __syncthreads();
-    for (int r = 0; r < nbp - 1; ++r) {
-      for (int pi = wv; pi < nbp / 2; pi += nw) {
-        int p, q;
-        if (pi == 0) { p = nbp - 1; q = r; }
-        else { p = (r + pi) % (nbp - 1); q = (r - pi + nbp - 1) % (nbp - 1); }
-        if (p >= nb || q >= nb) continue;
-        if (p > q) { int t = p; p = q; q = t; }
-        cplx* bp = Bw + (int64_t)p * mb;
-        cplx* bq = Bw + (int64_t)q * mb;
-        double al = 0.0, be = 0.0;
-        cplx ga = make_double2(0.0, 0.0);
-        for (int i = lane; i < mb; i += 64) {
-          cplx x = bp[i], y = bq[i];
-          al += cabs2(x);
-          be += cabs2(y);
-          cfma(ga, cconj(x), y);
-        }
-        al = wave_sum(al); be = wave_sum(be); ga = wave_sum(ga);
-        double g = sqrt(cabs2(ga));
-        if (al <= negl || be <= negl) continue;
-        if (g == 0.0 || !(g > jtol * sqrt(al * be))) continue;
-        double zeta = (be - al) / (2.0 * g);
-        double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-        cplx e = make_double2(ga.x / g, ga.y / g);            // e^{i phi}
-        cplx se = cscale(e, s), sec = cscale(cconj(e), s);
-        for (int i = lane; i < mb; i += 64) {
-          cplx x = bp[i], y = bq[i];
-          bp[i] = csub(cscale(x, c), cmul(sec, y));
-          bq[i] = cadd(cmul(se, x), cscale(y, c));
-        }
-        cplx* vp = Vw + (int64_t)p * nb;
-        cplx* vq = Vw + (int64_t)q * nb;
-        for (int i = lane; i < nb; i += 64) {
-          cplx x = vp[i], y = vq[i];
-          vp[i] = csub(cscale(x, c), cmul(sec, y));
-          vq[i] = cadd(cmul(se, x), cscale(y, c));
-        }
-        if (lane == 0) sh_rot = 1;
-      }
-      __syncthreads();
-    }
-    converged = (sh_rot == 0);
-    __syncthreads();
-  }
-  if (!converged && tid == 0) {
-    const int32_t old = atomicOr(status, (int32_t)ST_JACOBI_CAP);
-    if (!(old & ST_JACOBI_CAP)) {
-      double* d = status_diag(status);
-      d[0] = nb;
-      d[1] = d[2] = d[3] = -1.0;   // not tracked by this variant
-      d[4] = max_sweeps;
-    }
-  }
-  // singular values
-  for (int c = wv; c < nb; c += nw) {
-    double a = 0.0;
-    for (int i = lane; i < mb; i += 64) a += cabs2(Bw[(int64_t)c * mb + i]);
-    a = wave_sum(a);
-    if (lane == 0) sig[c] = sqrt(a);
-  }
-  __syncthreads();
-  for (int c = tid; c < nb; c += blockDim.x) {
-    double v = sig[c];
-    int pos = 0;
-    for (int d = 0; d < nb; ++d) pos += (sig[d] > v) || (sig[d] == v && d < c);
-    perm[pos] = c;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    double dl = delta[b];
-    // tail[l] = sqrt(sum_{j >= l} s_j^2): smallest l >= 1 with tail[l] <= dl
-    double tail2 = 0.0;
-    int l = nb;
-    for (int j = nb - 1; j >= 0; --j) {
-      double sj = sig[perm[j]];
-      if (sqrt(tail2 + sj * sj) <= dl) { tail2 += sj * sj; l = j; }
-      else break;
-    }
-    if (l < 1) l = 1;
-    if (l > lmax) l = lmax;
-    if (l > nb) l = nb;
-    double d2 = 0.0;
-    bool finite = true;
-    for (int j = 0; j < nb; ++j) {
-      double sj = sig[perm[j]];
-      if (!isfinite(sj)) finite = false;
-      if (j >= l) d2 += sj * sj;
-    }
-    if (!finite) {
-      const int32_t old = atomicOr(status, (int32_t)ST_NONFINITE);
-      if (!(old & ST_NONFINITE)) {
-        double* d = status_diag(status) + 5;
-        d[0] = nb;
-        d[1] = fro;
-        d[2] = -1.0;
-        d[3] = 2.0;   // global-memory Jacobi
-        d[4] = sweep;
-      }
-    }
-    disc2[b] += d2;
-    sh_l = l;
-    if (l_out) l_out[(int64_t)b * l_stride] = l;
-  }
-  __syncthreads();
-  const int l = sh_l;
-  if (svlog)
-    for (int j = tid; j < nb; j += blockDim.x) svlog[b * svstride + j] = sig[perm[j]];
-  if (tall) {
-    // A V = U Sigma = B:  core = V^H[:l] (l x nc),  carry = B[:, perm[:l]] (m x l)
-    for (int64_t e = tid; e < (int64_t)l * nc; e += blockDim.x) {
-      int r = (int)(e / nc), c = (int)(e % nc);
-      core[e] = cconj(Vw[(int64_t)perm[r] * nb + c]);
-    }
-    for (int64_t e = tid; e < (int64_t)m * l; e += blockDim.x) {
-      int i = (int)(e / l), r = (int)(e % l);
-      carry[e] = Bw[(int64_t)perm[r] * mb + i];
-    }
-  } else {
-    // A^H W = U' Sigma = B:  A = W Sigma U'^H;  core = (B[:, perm[r]]/sigma)^H,
-    // carry = W[:, perm[:l]] Sigma
-    for (int64_t e = tid; e < (int64_t)l * nc; e += blockDim.x) {
-      int r = (int)(e / nc), c = (int)(e % nc);
-      double sv = sig[perm[r]];
-      cplx v;
-      if (sv > 0.0) v = cscale(cconj(Bw[(int64_t)perm[r] * mb + c]), 1.0 / sv);
-      else v = make_double2(c == r ? 1.0 : 0.0, 0.0);
-      core[e] = v;
-    }
-    for (int64_t e = tid; e < (int64_t)m * l; e += blockDim.x) {
-      int i = (int)(e / l), r = (int)(e % l);
-      carry[e] = cscale(Vw[(int64_t)perm[r] * nb + i], sig[perm[r]]);
-    }
-  }
-}
-
-void svd_trunc(hipStream_t st, int batch, Dim m, Dim c, const cplx* A, int64_t sA, cplx* Bw,
-               int64_t sB, cplx* Vw, int64_t sV, cplx* core, int64_t sCore, cplx* carry,
-               int64_t sCarry, int32_t* l_out, int l_stride, const double* delta, double* disc2,
-               int lmax, int max_sweeps, int32_t* status, double* svlog, int64_t svstride,
-               int nbcap) {
-  (void)nbcap;
-  k_svd_trunc<<<batch, 256, 0, st>>>(m, c, A, sA, Bw, sB, Vw, sV, core, sCore, carry, sCarry,
-                                     l_out, l_stride, delta, disc2, lmax, max_sweeps, status,
-                                     svlog, svstride);
-}
 
 // ------------------------------------------------------------ small kernels
 __global__ __launch_bounds__(256) void k_norm_delta(Dim Rd, Dim Cd, const cplx* X, int64_t sX,

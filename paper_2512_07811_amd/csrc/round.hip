@@ -174,6 +174,11 @@ qt_status right_sweep_impl(qt_ctx ctx, qt_tt* x, const int32_t* rkl, const cplx*
   int32_t* rk = x->ranks;
   const cplx one = make_double2(1.0, 0.0);
   for (int k = n - 1; k >= 1; --k) {
+    const int nbk = std::min(x->cap[k], x->modes[k] * std::min(x->cap[k + 1], lmax_cap));
+    QT_CHECK(nbk <= 1024, QT_ECAPACITY,
+             "rounding: SVD block above 1024 columns (cap the rank or the sketch width)");
+  }
+  for (int k = n - 1; k >= 1; --k) {
     const int p = x->modes[k];
     const int lmax = std::min(lmax_cap, x->cap[k]);
     const cplx* in = (k == n - 1) ? center : buf.scratch;
@@ -183,14 +188,12 @@ qt_status right_sweep_impl(qt_ctx ctx, qt_tt* x, const int32_t* rkl, const cplx*
     const bool prof = prof_on(PROF_SVD);
     if (prof) g_prof->begin();
     const int nsw = std::min(mcap, ccap) > 100 ? sweeps_glb : sweeps;
-    if (!svd_trunc_fast(st, B, mcap, ccap, dref(rkl + k, rs), dref(rk + k + 1, rs, p), in, sin,
-                        buf.Bsv, buf.U, buf.slot, buf.V, buf.RV, buf.vv, buf.tau, buf.sig,
-                        buf.nbmax, X + x->offsets[k], sX, buf.C, buf.carry, rk + k, rs, delta,
-                        disc2, lmax, nsw, ctx->status, svk, svi, ctx->counters))
-      // orders above 1024 (not reached: tt_round rejects SVD blocks above 1024)
-      svd_trunc(st, B, dref(rkl + k, rs), dref(rk + k + 1, rs, p), in, sin, buf.Bsv, buf.slot,
-                buf.V, buf.vv, X + x->offsets[k], sX, buf.C, buf.carry, rk + k, rs, delta, disc2,
-                lmax, sweeps_glb, ctx->status, svk, svi, 0);
+    const bool ok = svd_trunc_fast(st, B, mcap, ccap, dref(rkl + k, rs), dref(rk + k + 1, rs, p),
+                                   in, sin, buf.Bsv, buf.U, buf.slot, buf.V, buf.RV, buf.vv,
+                                   buf.tau, buf.sig, buf.nbmax, X + x->offsets[k], sX, buf.C,
+                                   buf.carry, rk + k, rs, delta, disc2, lmax, nsw, ctx->status,
+                                   svk, svi, ctx->counters);
+    QT_CHECK(ok, QT_ECAPACITY, "rounding: SVD block above 1024 columns");
     if (prof) g_prof->end();
     const int pp = x->modes[k - 1];
     // scratch (r'_{k-1} p x l_k) = core_{k-1} (r'_{k-1} p x r'_k) * carry (r'_k x l_k)
