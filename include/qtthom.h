@@ -131,6 +131,21 @@ qt_status qt_ctx_counters(qt_ctx ctx, int64_t* out, int32_t n, int32_t reset);
 qt_status qt_ctx_profile(qt_ctx ctx, int32_t classes);
 qt_status qt_ctx_profile_read(qt_ctx ctx, double* total_ms, int64_t* launches);
 
+/* Tile shape of the structured GEMM (the MFMA kernel of every contraction).
+ * Each call has one of four output-tile shapes (64 or 32 rows by 64 or 32
+ * columns); every shape sums each output element's terms in the same order,
+ * so results are bitwise equal across shapes.  mode 0: always 64 x 64;
+ * 1 (default): autotune - the first call of each signature (capacities in
+ * steps of 16 rows / columns and 64 terms, item count to a power of two,
+ * conjugations, stride pattern) that runs outside a graph capture and
+ * without split-K times every shape once on its first instance, writing to a
+ * context-owned scratch (allocated on demand, at most 256 MiB), and later
+ * calls of that signature use the fastest; 2..5: always shape mode - 2 (bit 0:
+ * 32 rows, bit 1: 32 columns).  Timing synchronizes the stream.  *entries
+ * (may be null) receives the number of tuned signatures.  QT_EINVAL for a
+ * mode outside 0..5. */
+qt_status qt_ctx_autotune(qt_ctx ctx, int32_t mode, int32_t* entries);
+
 /* ---- TT algebra (Sec. 2.1) --------------------------------------------- */
 
 /* out = a (Hadamard) b: C_k(i) = A_k(i) (Kronecker) B_k(i); exact, ranks

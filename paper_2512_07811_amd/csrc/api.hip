@@ -14,6 +14,7 @@ static thread_local std::string g_last_error;
 thread_local ProfSink* g_prof = nullptr;
 thread_local unsigned long long* g_counters = nullptr;
 thread_local SplitKBuf g_splitk;
+thread_local GemmTuner* g_tuner = nullptr;
 
 // Regions do not nest: work launched inside an open region (the finishing
 // products of a large SVD, the products of a blocked QR) counts to that region.
@@ -44,6 +45,7 @@ void enter(qt_ctx ctx) {
   g_prof = ctx->prof.cls ? &ctx->prof : nullptr;
   g_counters = ctx->counters;
   g_splitk = ctx->splitk;
+  g_tuner = &ctx->tuner;
 }
 
 void set_error(const std::string& msg) { g_last_error = msg; }
@@ -907,6 +909,10 @@ void qt_ctx_destroy(qt_ctx ctx) {
   if (ctx->status) hipFree(ctx->status);
   if (ctx->counters) hipFree(ctx->counters);
   if (ctx->splitk.p) hipFree(ctx->splitk.p);
+  if (ctx->tuner.scratch) hipFree(ctx->tuner.scratch);
+  for (hipEvent_t e : ctx->tuner.ev)
+    if (e) hipEventDestroy(e);
+  if (qt::g_tuner == &ctx->tuner) qt::g_tuner = nullptr;
   if (ctx->dev_iter) hipFree(ctx->dev_iter);
   if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
   for (hipEvent_t e : ctx->prof.ev) hipEventDestroy(e);
@@ -919,6 +925,13 @@ qt_status qt_ctx_profile(qt_ctx ctx, int32_t classes) {
   QT_HIP(hipStreamSynchronize(ctx->stream));
   ctx->prof.cls = classes;
   ctx->prof.used = 0;
+  return QT_OK;
+}
+
+qt_status qt_ctx_autotune(qt_ctx ctx, int32_t mode, int32_t* entries) {
+  QT_CHECK(ctx && mode >= 0 && mode <= 5, QT_EINVAL, "qt_ctx_autotune: bad argument");
+  ctx->tuner.mode = mode;
+  if (entries) *entries = (int32_t)ctx->tuner.choice.size();
   return QT_OK;
 }
 

@@ -7,6 +7,8 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <array>
+#include <map>
 #include <vector>
 
 #include "../../include/qtthom.h"
@@ -227,6 +229,18 @@ struct SplitKBuf {
 extern thread_local SplitKBuf g_splitk;
 constexpr int64_t QT_SPLITK_ELEMS = int64_t(1) << 22;   // 64 MiB of complex doubles
 
+// Tile shapes of the structured GEMM (64 or 32 rows by 64 or 32 columns),
+// chosen per call signature by timing each shape once (owned by the context).
+// mode 0: always 64 x 64; 1: autotune; 2..5: always shape mode - 2.
+struct GemmTuner {
+  int mode = 1;
+  std::map<std::array<int64_t, 9>, int> choice;
+  cplx* scratch = nullptr;      // output of the timing launches
+  int64_t scratch_elems = 0;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+};
+extern thread_local GemmTuner* g_tuner;
+
 struct LearnCtx;
 }  // namespace qt
 
@@ -240,6 +254,7 @@ struct qt_ctx_s {
   int32_t* status = nullptr;  // device status word
   unsigned long long* counters = nullptr;  // device [CNT_N] event counters
   qt::SplitKBuf splitk;                    // GEMM split-K partials
+  qt::GemmTuner tuner;                     // GEMM tile shapes per call signature
   qt::ProfSink prof;
   qt::LearnCtx* learn = nullptr;   // learned-rank state (created on demand)
   int jacobi_default = 30;

@@ -7,7 +7,7 @@
 
 namespace qt {
 
-constexpr int XT_M = 64, XT_N = 64, XT_K = 16;
+constexpr int XT_K = 16;
 constexpr int XT_PAD = 16;   // LDS row pitch 80 doubles: 16-lane groups of one read land 32 banks apart
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
@@ -19,15 +19,17 @@ __device__ inline dbl4 mfma16(double a, double b, dbl4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// One 64 x 64 complex output tile per workgroup of 4 waves (2 x 2 waves of
-// 32 x 32, each 2 x 2 MFMA tiles of 16 x 16).  Complex products as four real
-// MFMAs into a real and an imaginary accumulator:
+// One TM x TN complex output tile (TM, TN in {32, 64}) per workgroup of 4
+// waves (2 x 2 waves of TM/2 x TN/2, each TM/32 x TN/32 MFMA tiles of 16 x 16).
+// Every output element sums its K terms in the same order whatever the tile
+// shape, so the shapes give bitwise equal results.  Complex products as four
+// real MFMAs into a real and an imaginary accumulator:
 //   Re += Ar Br + (-Ai) Bi,   Im += Ar Bi + Ai Br.
 // The next K panel is fetched into registers while the current one is in use.
 // Split-K (gridDim.z = splits > 1): workgroup z takes K range
 // [z kper, (z + 1) kper) with kper a multiple of the panel depth and writes its
 // raw partial tile to part[z][item][Mcap][Ncap]; k_splitk_sum finishes.
-template <bool CA, bool CB>
+template <bool CA, bool CB, int TM, int TN>
 __global__ __launch_bounds__(256) void k_gemm_ex(int nb1, int nb2, int ntn, Dim Md, Dim Nd,
                                                  Dim Kd, Mat A, Mat B, Mat C, cplx alpha,
                                                  int accumulate, Dim lim1,
@@ -40,7 +42,9 @@ __global__ __launch_bounds__(256) void k_gemm_ex(int nb1, int nb2, int ntn, Dim 
   const int rem = z % nbt;
   const int b1 = rem / nb2, b2 = rem % nb2;
   const int M = dimv(Md, b), N = dimv(Nd, b), K = dimv(Kd, b);
-  const int m0 = blockIdx.y * XT_M, n0 = tn * XT_N;
+  constexpr int FM = TM / 32, FN = TN / 32;     // MFMA tiles per wave
+  constexpr int EA = TM * XT_K / 256, EB = TN * XT_K / 256;   // panel elements per thread
+  const int m0 = blockIdx.y * TM, n0 = tn * TN;
   if (m0 >= M || n0 >= N || b1 >= dimv(lim1, b)) return;
   const int splits = gridDim.z, sk = blockIdx.z;
   int kbeg = 0, kend = K;
@@ -66,26 +70,30 @@ __global__ __launch_bounds__(256) void k_gemm_ex(int nb1, int nb2, int ntn, Dim 
   const int64_t crs = strv(C.rs, b), ccs = strv(C.cs, b);
   const bool a_kfast = (acs == 1);
   const bool b_nfast = (bcs == 1);
-  __shared__ double Ar[XT_K][XT_M + XT_PAD], Ai[XT_K][XT_M + XT_PAD];
-  __shared__ double Br[XT_K][XT_N + XT_PAD], Bi[XT_K][XT_N + XT_PAD];
+  __shared__ double Ar[XT_K][TM + XT_PAD], Ai[XT_K][TM + XT_PAD];
+  __shared__ double Br[XT_K][TN + XT_PAD], Bi[XT_K][TN + XT_PAD];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
+  const int wm = (w & 1) * (TM / 2), wn = (w >> 1) * (TN / 2);
   const int li = lane & 15, lk = lane >> 4;
 
   // element e of this thread's share of a panel: (row/col, k) inside the tile
-  int am[4], ak[4], bk[4], bn[4];
+  int am[EA], ak[EA], bk[EB], bn[EB];
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
+  for (int e = 0; e < EA; ++e) {
     const int idx = tid + 256 * e;
     if (a_kfast) { am[e] = idx >> 4; ak[e] = idx & 15; }
-    else { ak[e] = idx >> 6; am[e] = idx & 63; }
-    if (b_nfast) { bk[e] = idx >> 6; bn[e] = idx & 63; }
+    else { ak[e] = idx / TM; am[e] = idx % TM; }
+  }
+#pragma unroll
+  for (int e = 0; e < EB; ++e) {
+    const int idx = tid + 256 * e;
+    if (b_nfast) { bk[e] = idx / TN; bn[e] = idx % TN; }
     else { bn[e] = idx >> 4; bk[e] = idx & 15; }
   }
-  cplx ra[4], rb[4];
+  cplx ra[EA], rb[EB];
   auto fetch = [&](int k0) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < EA; ++e) {
       const int gm = m0 + am[e], gk = k0 + ak[e];
       cplx v = make_double2(0.0, 0.0);
       if (gm < M && gk < kend) {
@@ -93,6 +101,9 @@ __global__ __launch_bounds__(256) void k_gemm_ex(int nb1, int nb2, int ntn, Dim 
         if (CA) v = cconj(v);
       }
       ra[e] = v;
+    }
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
       const int gk2 = k0 + bk[e], gn = n0 + bn[e];
       cplx u = make_double2(0.0, 0.0);
       if (gk2 < kend && gn < N) {
@@ -102,20 +113,23 @@ __global__ __launch_bounds__(256) void k_gemm_ex(int nb1, int nb2, int ntn, Dim 
       rb[e] = u;
     }
   };
-  dbl4 cre[2][2], cim[2][2];
+  dbl4 cre[FM][FN], cim[FM][FN];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < FN; ++j) {
       cre[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
       cim[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
     }
   fetch(kbeg);
   for (int k0 = kbeg; k0 < kend; k0 += XT_K) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < EA; ++e) {
       Ar[ak[e]][am[e]] = ra[e].x;
       Ai[ak[e]][am[e]] = ra[e].y;
+    }
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
       Br[bk[e]][bn[e]] = rb[e].x;
       Bi[bk[e]][bn[e]] = rb[e].y;
     }
@@ -123,18 +137,21 @@ __global__ __launch_bounds__(256) void k_gemm_ex(int nb1, int nb2, int ntn, Dim 
     if (k0 + XT_K < kend) fetch(k0 + XT_K);
 #pragma unroll
     for (int kc = 0; kc < XT_K; kc += 4) {
-      double far[2], fai[2], fbr[2], fbi[2];
+      double far[FM], fai[FM], fbr[FN], fbi[FN];
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
+      for (int t = 0; t < FM; ++t) {
         far[t] = Ar[kc + lk][wm + 16 * t + li];
         fai[t] = Ai[kc + lk][wm + 16 * t + li];
+      }
+#pragma unroll
+      for (int t = 0; t < FN; ++t) {
         fbr[t] = Br[kc + lk][wn + 16 * t + li];
         fbi[t] = Bi[kc + lk][wn + 16 * t + li];
       }
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < FN; ++j) {
           cre[i][j] = mfma16(far[i], fbr[j], cre[i][j]);
           cre[i][j] = mfma16(-fai[i], fbi[j], cre[i][j]);
           cim[i][j] = mfma16(far[i], fbi[j], cim[i][j]);
@@ -144,9 +161,9 @@ __global__ __launch_bounds__(256) void k_gemm_ex(int nb1, int nb2, int ntn, Dim 
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < FN; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int gm = m0 + wm + 16 * i + 4 * r + lk;
@@ -187,44 +204,146 @@ __global__ void k_splitk_sum(int nb1, int nb2, Dim Md, Dim Nd, Mat C, cplx alpha
   *o = v;
 }
 
+// Launch of tile shape v (bit 0: 32 rows, bit 1: 32 columns).
+struct GemmArgs {
+  int nb1, nb2;
+  Dim M, N, K;
+  Mat A, B, C;
+  cplx alpha;
+  int acc;
+  Dim lim1;
+  unsigned long long* cnt;
+  cplx* part;
+  int Mcap, Ncap;
+  int64_t items;
+};
+
+template <int TM, int TN>
+static void launch_tile(hipStream_t st, int splits, bool cA, bool cB, const GemmArgs& a) {
+  const int ntn = (a.Ncap + TN - 1) / TN, mtn = (a.Mcap + TM - 1) / TM;
+  dim3 grid((unsigned)((int64_t)ntn * a.items), mtn, splits);
+#define QT_GEMM_LAUNCH(X, Y)                                                                     \
+  k_gemm_ex<X, Y, TM, TN><<<grid, 256, 0, st>>>(a.nb1, a.nb2, ntn, a.M, a.N, a.K, a.A, a.B, a.C, \
+                                                a.alpha, a.acc, a.lim1, a.cnt, a.part, a.Mcap,   \
+                                                a.Ncap, a.items)
+  if (!cA && !cB) QT_GEMM_LAUNCH(false, false);
+  else if (cA && !cB) QT_GEMM_LAUNCH(true, false);
+  else if (!cA && cB) QT_GEMM_LAUNCH(false, true);
+  else QT_GEMM_LAUNCH(true, true);
+#undef QT_GEMM_LAUNCH
+}
+
+static void launch_shape(int v, hipStream_t st, int splits, bool cA, bool cB, const GemmArgs& a) {
+  switch (v) {
+    case 1: launch_tile<32, 64>(st, splits, cA, cB, a); break;
+    case 2: launch_tile<64, 32>(st, splits, cA, cB, a); break;
+    case 3: launch_tile<32, 32>(st, splits, cA, cB, a); break;
+    default: launch_tile<64, 64>(st, splits, cA, cB, a); break;
+  }
+}
+
+// Largest timing output of the tuner (complex elements, 256 MiB).
+constexpr int64_t QT_TUNE_MAX_ELEMS = int64_t(1) << 24;
+
+// Times every tile shape on instance 0 of the call (output to the tuner's
+// scratch, no accumulation, no split-K, no counters) and returns the fastest;
+// 64 x 64 unless another shape is at least 3 % faster.
+static int tune_shape(hipStream_t st, GemmTuner& T, bool cA, bool cB, GemmArgs a) {
+  const int64_t items1 = (int64_t)a.nb1 * a.nb2;
+  const int64_t need = items1 * a.Mcap * a.Ncap;
+  if (need > QT_TUNE_MAX_ELEMS) return 0;
+  if (need > T.scratch_elems) {
+    if (T.scratch) (void)hipFree(T.scratch);
+    T.scratch = nullptr;
+    T.scratch_elems = 0;
+    if (hipMalloc((void**)&T.scratch, sizeof(cplx) * need) != hipSuccess) {
+      (void)hipGetLastError();
+      T.scratch = nullptr;
+      return 0;
+    }
+    T.scratch_elems = need;
+  }
+  if (!T.ev[0] && (hipEventCreate(&T.ev[0]) != hipSuccess || hipEventCreate(&T.ev[1]) != hipSuccess))
+    return 0;
+  const Str one{nullptr, 0, 0, 1}, zero{nullptr, 0, 0, 0};
+  a.C = mat(T.scratch, 0, Str{nullptr, 0, 0, a.Ncap}, one,
+            Str{nullptr, 0, 0, (int64_t)a.nb2 * a.Mcap * a.Ncap},
+            Str{nullptr, 0, 0, (int64_t)a.Mcap * a.Ncap}, zero);
+  a.acc = 0;
+  a.cnt = nullptr;
+  a.items = items1;
+  float best = 0.f;
+  int bv = 0;
+  for (int v = 0; v < 4; ++v) {
+    launch_shape(v, st, 1, cA, cB, a);   // warm-up
+    float tv = 1e30f;
+    for (int rep = 0; rep < 2; ++rep) {
+      (void)hipEventRecord(T.ev[0], st);
+      launch_shape(v, st, 1, cA, cB, a);
+      (void)hipEventRecord(T.ev[1], st);
+      if (hipEventSynchronize(T.ev[1]) != hipSuccess) return 0;
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, T.ev[0], T.ev[1]);
+      tv = std::min(tv, ms);
+    }
+    if (v == 0 || tv < 0.97f * best) { best = tv; bv = v; }
+  }
+  return bv;
+}
+
+static bool stream_capturing(hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess) {
+    (void)hipGetLastError();
+    return true;
+  }
+  return cs != hipStreamCaptureStatusNone;
+}
+
 void gemm_ex(hipStream_t st, int batch, int nb1, int nb2, Dim M, Dim N, Dim K, int Mcap, int Ncap,
              Mat A, bool conjA, Mat B, bool conjB, Mat C, cplx alpha, bool accumulate, Dim lim1,
              int64_t Kcap) {
   if (Mcap <= 0 || Ncap <= 0 || batch <= 0 || nb1 <= 0 || nb2 <= 0) return;
-  const int ntn = (Ncap + XT_N - 1) / XT_N;
-  const int mtn = (Mcap + XT_M - 1) / XT_M;
   const int64_t items = (int64_t)batch * nb1 * nb2;
-  const int64_t gx = (int64_t)ntn * items;
   // split K when the output has too few tiles to fill the chip and K is long
+  // (decided on 64 x 64 tiles whatever the shape, so that every shape sums
+  // each element in the same order)
   int splits = 1;
-  const int64_t tiles = gx * mtn;
+  const int64_t tiles = (int64_t)((Ncap + 63) / 64) * items * ((Mcap + 63) / 64);
   if (Kcap >= 1024 && tiles < 256 && g_splitk.p) {
     splits = (int)std::min<int64_t>({(Kcap + 255) / 256, (512 + tiles - 1) / tiles, 64});
     const int64_t per = items * Mcap * Ncap;
     while (splits > 1 && splits * per > g_splitk.elems) --splits;
   }
-  dim3 grid((unsigned)gx, mtn, splits);
-  const int acc = accumulate ? 1 : 0;
-  unsigned long long* cnt = g_counters;
-  cplx* part = g_splitk.p;
+  GemmArgs a{nb1, nb2, M, N, K, A, B, C, alpha, accumulate ? 1 : 0, lim1, g_counters, g_splitk.p,
+             Mcap, Ncap, items};
+  int v = 0;
+  GemmTuner* T = g_tuner;
+  if (T && T->mode >= 2) {
+    v = T->mode - 2;
+  } else if (T && T->mode == 1 && splits == 1) {
+    // signature: capacities to 16 (M, N) and 64 (K), items to a power of
+    // two, conjugations and which operands are unit-stride along K / N
+    int64_t ib = 1;
+    while (ib < items) ib <<= 1;
+    const std::array<int64_t, 9> key{conjA, conjB, (Mcap + 15) / 16, (Ncap + 15) / 16,
+                                      (Kcap + 63) / 64, ib, A.cs.p ? -1 : A.cs.cst,
+                                      B.cs.p ? -1 : B.cs.cst, C.cs.p ? -1 : C.cs.cst};
+    auto it = T->choice.find(key);
+    if (it != T->choice.end()) {
+      v = it->second;
+    } else if (!stream_capturing(st)) {
+      v = tune_shape(st, *T, conjA, conjB, a);
+      T->choice[key] = v;
+    }
+  }
   const bool prof = prof_on(PROF_GEMM);
   if (prof) g_prof->begin();
-  if (!conjA && !conjB)
-    k_gemm_ex<false, false><<<grid, 256, 0, st>>>(nb1, nb2, ntn, M, N, K, A, B, C, alpha, acc, lim1,
-                                                  cnt, part, Mcap, Ncap, items);
-  else if (conjA && !conjB)
-    k_gemm_ex<true, false><<<grid, 256, 0, st>>>(nb1, nb2, ntn, M, N, K, A, B, C, alpha, acc, lim1,
-                                                 cnt, part, Mcap, Ncap, items);
-  else if (!conjA && conjB)
-    k_gemm_ex<false, true><<<grid, 256, 0, st>>>(nb1, nb2, ntn, M, N, K, A, B, C, alpha, acc, lim1,
-                                                 cnt, part, Mcap, Ncap, items);
-  else
-    k_gemm_ex<true, true><<<grid, 256, 0, st>>>(nb1, nb2, ntn, M, N, K, A, B, C, alpha, acc, lim1,
-                                                cnt, part, Mcap, Ncap, items);
+  launch_shape(v, st, splits, conjA, conjB, a);
   if (splits > 1) {
     const int64_t total = items * Mcap * Ncap;
     k_splitk_sum<<<(unsigned)((total + 255) / 256), 256, 0, st>>>(
-        nb1, nb2, M, N, C, alpha, acc, lim1, part, splits, Mcap, Ncap, items);
+        nb1, nb2, M, N, C, alpha, a.acc, lim1, g_splitk.p, splits, Mcap, Ncap, items);
   }
   if (prof) g_prof->end();
 }

@@ -22,7 +22,8 @@ ROUND_SVD, ROUND_SKETCH, ROUND_LEARNED = 0, 1, 2
 PREC_F64, PREC_F32 = 0, 1
 
 EXPORTS = ["qt_ctx_create", "qt_ctx_destroy", "qt_last_error", "qt_ctx_sync",
-           "qt_ctx_counters", "qt_ctx_profile", "qt_ctx_profile_read", "tt_hadamard",
+           "qt_ctx_counters", "qt_ctx_profile", "qt_ctx_profile_read", "qt_ctx_autotune",
+           "tt_hadamard",
            "tt_mpo_apply", "tt_add", "tt_round", "tt_dot", "tt_sketch_round", "tt_sandwich",
            "ls_iterate", "homogenize", "qt_mlp_num_params", "qt_mlp_train_step", "qt_mlp_infer",
            "qt_ranklog_enable", "qt_ranklog_get", "qt_set_predictor", "qt_learn_reset"]
@@ -84,6 +85,7 @@ def load_library(path: str = LIB_PATH):
     lib.qt_ctx_counters.argtypes = [vp, C.POINTER(C.c_int64), i32, i32]
     lib.qt_ctx_profile.argtypes = [vp, i32]
     lib.qt_ctx_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    lib.qt_ctx_autotune.argtypes = [vp, i32, C.POINTER(C.c_int32)]
     lib.tt_hadamard.argtypes = [vp, C.POINTER(TTDesc), C.POINTER(TTDesc), C.POINTER(TTDesc)]
     lib.tt_mpo_apply.argtypes = [vp, C.POINTER(MPODesc), C.POINTER(TTDesc), C.POINTER(TTDesc)]
     lib.tt_add.argtypes = [vp, dbl, dbl, C.POINTER(TTDesc), dbl, dbl, C.POINTER(TTDesc),
@@ -184,6 +186,13 @@ class Context:
     def profile(self, classes: int):
         """Start live event timing of kernel classes (bit mask; 0 stops)."""
         _check(self.lib.qt_ctx_profile(self.h, classes))
+
+    def autotune(self, mode: int = 1) -> int:
+        """GEMM tile-shape mode (0 fixed 64x64, 1 autotune, 2..5 forced shape);
+        returns the number of tuned call signatures so far."""
+        n = C.c_int32()
+        _check(self.lib.qt_ctx_autotune(self.h, mode, C.byref(n)))
+        return n.value
 
     def profile_read(self):
         """(summed kernel time in ms, number of timed launches) since the last read."""

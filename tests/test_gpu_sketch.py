@@ -225,3 +225,33 @@ def test_sketch_homogenize_laminate(q, ctx):
     assert st == q.QT_OK
     assert abs(A[0, 0] - 20.0 / 11.0) < 1e-9
     assert abs(A[1, 1] - 5.5) < 1e-9
+
+
+def test_gemm_tile_shapes_are_bitwise_equal(q):
+    # every tile shape of the structured GEMM (fixed 64 x 64, autotuned, and
+    # each forced shape) gives bitwise the same sketch-mode iteration: each
+    # output element sums its terms in one order whatever the tile
+    import torch
+
+    from paper_2512_07811_amd import operands as P
+    L, N = 4, 16
+    g = I.rng(321)
+    k = g.uniform(1.0, 4.0, size=(N, N, N))
+    prob = P.build_problem(kvox=k, k0=2.5)
+    outs = []
+    for mode in (0, 1, 2, 3, 4, 5):
+        c = q.Context(0)
+        assert c.autotune(mode) == 0
+        ops, e = P.upload(prob, [[1.0, 0.0, 0.0], [0.0, 0.0, 1.0]], max_rank=24)
+        opts = q.solve_opts(1e-8, 24, mode=q.ROUND_SKETCH, oversample=4, seed=9)
+        res = q.ls_iterate(c, ops, e, opts, 2).cpu()
+        c.sync()
+        tuned = c.autotune(mode)
+        outs.append((mode, e.data.cpu().clone(), e.ranks.cpu().clone(), res, tuned))
+        c.close()
+    _, d0, r0, s0, _ = outs[0]
+    for mode, d, r, s, tuned in outs[1:]:
+        assert torch.equal(r, r0), mode
+        assert torch.equal(d, d0), mode
+        assert torch.equal(s, s0), mode
+    assert outs[1][4] > 0          # autotune recorded the signatures it timed
