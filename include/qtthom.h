@@ -170,7 +170,9 @@ qt_status tt_add(qt_ctx ctx, double alpha_re, double alpha_im, const qt_tt* x,
  * discarded singular-value tail does not exceed eps*||x||/sqrt(n-1), capped by
  * max_rank.  On return cores 1..n-1 are right-orthogonal.
  * err_out (device [B], may be NULL): sqrt(sum of squared discarded tails)/||x||.
- * norm_out (device [B], may be NULL): ||x||_F before rounding. */
+ * norm_out (device [B], may be NULL): ||x||_F before rounding.
+ * QT_ECAPACITY (nothing launched) when a bond's SVD block, min(cap[k],
+ * p_k min(cap[k+1], max_rank)), exceeds 1024 columns. */
 qt_status tt_round(qt_ctx ctx, qt_tt* x, const qt_round_opts* opts, double* err_out,
                    double* norm_out);
 
@@ -193,7 +195,9 @@ qt_status tt_dot(qt_ctx ctx, const qt_tt* a, const qt_tt* b, double* out);
  *  xnorm2: device [B] exact ||x||^2 (e.g. from tt_sandwich).
  *  err_out: device [B] relative error sqrt(sketch^2 + truncation^2)/||x||.
  *  fail_out: device [B] int, 1 when the sketch error alone exceeds eps*||x||.
- * A must be square (p_out = p_in = y's modes). out->cap >= sketch ranks. */
+ * A must be square (p_out = p_in = y's modes). out->cap >= sketch ranks.
+ * QT_ECAPACITY (before the truncation sweep) in mode QT_ROUND_SKETCH when a
+ * bond's SVD block of `out` exceeds 1024 columns. */
 qt_status tt_sketch_round(qt_ctx ctx, const qt_mpo* A, const qt_tt* y, const qt_tt* omega,
                           const qt_round_opts* opts, const double* xnorm2, qt_tt* out,
                           double* err_out, int32_t* fail_out);
