@@ -395,9 +395,9 @@ static qt_status check_status(qt_ctx ctx) {
       QT_HIP(hipStreamSynchronize(ctx->stream));
       char msg[256];
       static const char* where[] = {"", "LDS Jacobi", "global-memory Jacobi",
-                                    "triangle given to the LDS Jacobi", "",
-                                    "", "core from the Jacobi (tall)", "core from the finalizer (wide)",
-                                    "carry from the Jacobi (wide)", "carry from the finalizer (tall)"};
+                                    "triangle given to the Jacobi", "",
+                                    "", "core from the Jacobi (tall)", "",
+                                    "left vectors from the Jacobi (wide)", ""};
       const int w = (int)d[8];
       snprintf(msg, sizeof(msg),
                "non-finite values in a rounding (%s, order %d, values %.3e %.3e, count %d)",

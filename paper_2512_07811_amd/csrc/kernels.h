@@ -83,13 +83,15 @@ void qr_blocked(hipStream_t st, int batch, int mcap, int ncap, Dim m, Dim n, con
 // l <= lmax; writes V^dagger[:l] (l x c) to core, U Sigma[:, :l] (m x l) to
 // carry, l to l_out, adds the squared discarded tail to disc2[b].  svlog (may
 // be null) receives the sorted singular values (stride svstride).
-// Truncated SVD by QR then one-sided Jacobi on R^H: R^H and W in LDS for
-// min(m, c) <= 68, R^H in LDS and W in global memory up to 100, both in global
-// memory up to 1024; returns false above that.  Scratch: Qw, Uw (max x min,
-// stride sQ), Rw, RVw (min^2, stride sR), tau, sig (stride sT).
+// Truncated SVD by QR, a second QR of R^H when A is wide, then one-sided
+// Jacobi on the conjugate transpose of the triangle without accumulating its
+// rotations: the matrix in LDS up to order 100, in global memory (Xw) up to
+// 1024; core and carry = A core^H finished by the MFMA GEMM; returns false
+// above order 1024.  Scratch: Qw, Uw (max x min, stride sQ), Rw, Xw (min^2,
+// stride sR), tau (stride sT >= min + 4).  A must not alias core.
 bool svd_trunc_fast(hipStream_t st, int batch, int mcap, int ccap, Dim m, Dim c, const cplx* A,
-                    int64_t sA, cplx* Qw, cplx* Uw, int64_t sQ, cplx* Rw, cplx* RVw, int64_t sR,
-                    double* tau, double* sig, int64_t sT, cplx* core, int64_t sCore, cplx* carry,
+                    int64_t sA, cplx* Qw, cplx* Uw, int64_t sQ, cplx* Rw, cplx* Xw, int64_t sR,
+                    double* tau, int64_t sT, cplx* core, int64_t sCore, cplx* carry,
                     int64_t sCarry, int32_t* l_out, int l_stride, const double* delta,
                     double* disc2, int lmax, int max_sweeps, int32_t* status, double* svlog,
                     int64_t svstride, unsigned long long* counters);

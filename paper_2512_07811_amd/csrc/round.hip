@@ -45,7 +45,9 @@ RoundWs round_ws_layout(const qt_tt* x, int lmax_cap) {
   w.slot = slot; w.rr = rr; w.vv = vv; w.carry = carry; w.tau = tau;
   const int B = x->batch;
   w.max_nb = std::max<int64_t>(w.max_nb, 1);
-  w.sweep_bytes = sizeof(cplx) * B * (slot + vv) + sizeof(double) * B * 2 * w.max_nb + 4 * 256;
+  // tau: nb reflector scalars, then 8 sizes of the SVD's second QR and
+  // finishing products (4 doubles)
+  w.sweep_bytes = sizeof(cplx) * B * (slot + vv) + sizeof(double) * B * (w.max_nb + 4) + 3 * 256;
   w.bytes = sizeof(cplx) * B * (3 * slot + rr + vv + carry) + sizeof(double) * B * (tau + 4) +
             sizeof(int32_t) * B * (n + 1) + 16 * 256 + w.sweep_bytes;
   if (w.qb_v > 0)
@@ -155,10 +157,9 @@ static int sweeps_global(qt_ctx ctx, int sweeps) {
 qt_status take_sweep_extra(qt_ctx ctx, int B, const RoundWs& w, SweepBufs& buf) {
   buf.U = (cplx*)ws_take(ctx, sizeof(cplx) * B * w.slot);
   buf.RV = (cplx*)ws_take(ctx, sizeof(cplx) * B * w.vv);
-  buf.tau = (double*)ws_take(ctx, sizeof(double) * B * w.max_nb);
-  buf.sig = (double*)ws_take(ctx, sizeof(double) * B * w.max_nb);
-  buf.nbmax = w.max_nb;
-  QT_CHECK(buf.U && buf.RV && buf.tau && buf.sig, QT_ENOMEM, "rounding: sweep workspace too small");
+  buf.nbmax = w.max_nb + 4;
+  buf.tau = (double*)ws_take(ctx, sizeof(double) * B * buf.nbmax);
+  QT_CHECK(buf.U && buf.RV && buf.tau, QT_ENOMEM, "rounding: sweep workspace too small");
   return QT_OK;
 }
 
@@ -178,6 +179,15 @@ qt_status right_sweep_impl(qt_ctx ctx, qt_tt* x, const int32_t* rkl, const cplx*
     QT_CHECK(nbk <= 1024, QT_ECAPACITY,
              "rounding: SVD block above 1024 columns (cap the rank or the sketch width)");
   }
+  // the SVD reads its input again after writing the core (carry = A core^H):
+  // a centre stored in x's own last core is staged into the scratch first
+  if (center == X + x->offsets[n - 1]) {
+    copy(st, B, dref(rkl + n - 1, rs), dref(rk + n, rs, x->modes[n - 1]),
+         (int64_t)x->cap[n - 1] * x->modes[n - 1] * x->cap[n], center, cstride, buf.scratch,
+         buf.slot);
+    center = buf.scratch;
+    cstride = buf.slot;
+  }
   for (int k = n - 1; k >= 1; --k) {
     const int p = x->modes[k];
     const int lmax = std::min(lmax_cap, x->cap[k]);
@@ -190,7 +200,7 @@ qt_status right_sweep_impl(qt_ctx ctx, qt_tt* x, const int32_t* rkl, const cplx*
     const int nsw = std::min(mcap, ccap) > 100 ? sweeps_glb : sweeps;
     const bool ok = svd_trunc_fast(st, B, mcap, ccap, dref(rkl + k, rs), dref(rk + k + 1, rs, p),
                                    in, sin, buf.Bsv, buf.U, buf.slot, buf.V, buf.RV, buf.vv,
-                                   buf.tau, buf.sig, buf.nbmax, X + x->offsets[k], sX, buf.C,
+                                   buf.tau, buf.nbmax, X + x->offsets[k], sX, buf.C,
                                    buf.carry, rk + k, rs, delta, disc2, lmax, nsw, ctx->status,
                                    svk, svi, ctx->counters);
     QT_CHECK(ok, QT_ECAPACITY, "rounding: SVD block above 1024 columns");

@@ -45,10 +45,9 @@ struct SweepBufs {
   cplx* V;
   cplx* C;
   int64_t slot, vv, carry;
-  cplx* U;     // reflectors (slot)
-  cplx* RV;    // kept columns of R V (vv)
-  double* tau; // nb entries
-  double* sig; // nb entries
+  cplx* U;     // reflectors, then the kept left Jacobi vectors (slot)
+  cplx* RV;    // Jacobi matrix of orders above 100 (vv)
+  double* tau; // nbmax entries: reflector scalars, then 4 for the SVD's sizes
   int64_t nbmax;
 };
 qt_status take_sweep_extra(qt_ctx ctx, int B, const RoundWs& w, SweepBufs& buf);

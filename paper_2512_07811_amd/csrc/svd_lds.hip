@@ -1,15 +1,22 @@
-// Truncated SVD for the right-to-left sweep, small sizes (min(m, c) <= 100;
-// R and V in LDS up to 68, R in LDS and V in global memory up to 100):
-//   1. B = A (m >= c) or A^H (m < c); B = Q R by the register-resident QR;
-//   2. one-sided (Hestenes) Jacobi on the columns of R^H (lower triangular),
-//      which converge in fewer sweeps than R's (the rows of a triangular
-//      factor are better separated than its columns; Drmac and Veselic,
-//      SIAM J. Matrix Anal. Appl. 29, 2008): R^H W = U Sigma, so R = W Sigma U^H
-//      (R^H and W in LDS, 16 waves, round-robin pairs, one barrier per round);
+// Truncated SVD for the right-to-left sweep, A (m x c) packed row-major:
+//   1. B = A (m >= c) or A^H (m < c); B = Q R by Householder QR;
+//   2. one-sided (Hestenes) Jacobi on the columns of X = T^H for an upper
+//      triangle T, until X W = U Sigma has orthogonal columns (W is not
+//      formed); the rows of a triangular factor are better separated than
+//      its columns, so this converges in fewer sweeps than Jacobi on T
+//      (Drmac and Veselic, SIAM J. Matrix Anal. Appl. 29, 2008):
+//        tall (A = Q R):   T = R; R = W Sigma U^H, A = (Q W) Sigma U^H, and
+//                          the right singular vectors of A are U;
+//        wide (A^H = Q R): a second QR without Q, R^H = Q2 R2, and T = R2:
+//                          R = R2^H Q2^H has the left singular vectors U of
+//                          R2^H, A = R^H Q^H = W' Sigma (Q U)^H, and the right
+//                          singular vectors of A are Q U;
 //   3. truncation (smallest l whose discarded tail <= delta, l <= lmax);
-//   4. outputs: for A = Q R:   core = U^H[:l] = ((R^H W)[:, r] / sigma_r)^H,
-//                              carry = Q W[:, :l] Sigma[:l];
-//               for A^H = Q R: core = (Q W[:, r])^H,  carry = (R^H W)[:, :l].
+//   4. core = the first l right singular vectors as rows (U^H[:l] from the
+//      converged columns, or (Q U[:, :l])^H by one GEMM), and
+//      carry = A core^H, which equals U_A Sigma[:, :l] (A V_l = U_A Sigma_l),
+//      by one GEMM on the original A: carry core = A V_l V_l^H is the
+//      orthogonal projection of A, whatever the accuracy of W.
 // Rotation: gamma = b_p^H b_q = |gamma| e^{i phi}, zeta = (beta - alpha)/(2|gamma|),
 // t = sign(zeta)/(|zeta| + sqrt(1 + zeta^2)), c = 1/sqrt(1 + t^2), s = c t,
 // [b_p, b_q] <- [b_p, b_q] [[c, s e^{i phi}], [-s e^{-i phi}, c]].
@@ -17,13 +24,14 @@
 
 namespace qt {
 
-constexpr int SL_NB = 68;            // LDS holds two SL_NB x SL_NB complex matrices
-constexpr int SL_NB_BIG = 100;       // LDS holds R only (160000 bytes), V in global memory
+constexpr int SL_NB = 68;            // orders up to 68: five rows per lane
+constexpr int SL_NB_BIG = 100;       // up to 100: X fills 160000 bytes of LDS
 constexpr double SL_EPS = 2.0 * 2.220446049250313e-16;
 constexpr double SL_NEGL = 1e-34;
 
-// Flags a non-finite output of the truncated SVD (stage 5 + 2 * out + tall:
-// out 0 core, 1 carry) with the order, kept rank and extreme kept sigmas.
+// Flags a non-finite output of the Jacobi (stage 6: the core of a tall
+// instance, 8: the left vectors of a wide one) with the order, kept rank and
+// extreme kept sigmas.
 __device__ inline void flag_out(int32_t* status, int stage, int nb, int l, double smax,
                                 double smin) {
   const int32_t old = atomicOr(status, (int32_t)ST_NONFINITE);
@@ -37,19 +45,143 @@ __device__ inline void flag_out(int32_t* status, int stage, int nb, int l, doubl
   }
 }
 
-// NBMAX: largest order; VG: V kept in global memory (Vg + b * sV, nb x nb);
-// the large variant re-reads R from LDS for the rotation to stay within the
-// register budget of 1024 threads.
-template <int NBMAX, bool VG>
+// Truncation after convergence (thread 0): sorted order perm of the column
+// norms sig, the smallest l >= 1 whose tail does not exceed delta, l <= lmax;
+// returns l, adds the discarded tail to disc2, flags non-finite sigmas.
+__device__ inline int jacobi_truncate(const double* sig, const int* perm, int nb, double dl,
+                                      int lmax, double* disc2_b, int32_t* status, double fro,
+                                      int sweeps_done, double variant) {
+  double tail2 = 0.0;
+  int l = nb;
+  for (int j = nb - 1; j >= 0; --j) {
+    const double sj = sig[perm[j]];
+    if (sqrt(tail2 + sj * sj) <= dl) { tail2 += sj * sj; l = j; }
+    else break;
+  }
+  if (l < 1) l = 1;
+  if (l > lmax) l = lmax;
+  if (l > nb) l = nb;
+  double d2 = 0.0;
+  bool finite = true;
+  for (int j = 0; j < nb; ++j) {
+    const double sj = sig[perm[j]];
+    if (!isfinite(sj)) finite = false;
+    if (j >= l) d2 += sj * sj;
+  }
+  if (!finite) {
+    const int32_t old = atomicOr(status, (int32_t)ST_NONFINITE);
+    if (!(old & ST_NONFINITE)) {
+      double* d = status_diag(status) + 5;
+      d[0] = nb;
+      d[1] = fro;
+      d[2] = -1.0;
+      d[3] = variant;
+      d[4] = sweeps_done;
+    }
+  }
+  *disc2_b += d2;
+  return l;
+}
+
+// Sum over the block (every thread gets the result); red holds 16 doubles.
+__device__ inline double block_sum(double v, double* red) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) red[wv] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int i = 0; i < nw; ++i) s += red[i];
+  return s;
+}
+
+// Kept columns whose squared norm is at or below the rotation floor were
+// never rotated, so they are not orthogonal to the others.  Their weight in
+// the matrix is below 1e-17 of its norm, so any orthonormal completion
+// serves: the sorted kept columns perm[t0..l) become, one by one, the first
+// unit vector e_j that keeps more than half of the average share (nb - r)/nb
+// after the previous columns are projected out twice (classical
+// Gram-Schmidt with reorthogonalization), normalized.  Columns perm[0..t0)
+// must have unit norm.  Whole block; h holds l complex values.
+__device__ void complete_columns(cplx* X, const int* perm, int nb, int t0, int l, cplx* h,
+                                 double* red) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
+  for (int r = t0; r < l; ++r) {
+    cplx* v = X + (int64_t)perm[r] * nb;
+    for (int j = 0; j < nb; ++j) {
+      for (int i = tid; i < nb; i += blockDim.x) v[i] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+      __syncthreads();
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int q = wv; q < r; q += nw) {
+          const cplx* u = X + (int64_t)perm[q] * nb;
+          cplx a = make_double2(0.0, 0.0);
+          for (int i = lane; i < nb; i += 64) cfma(a, cconj(u[i]), v[i]);
+          a = wave_sum(a);
+          if (lane == 0) h[q] = a;
+        }
+        __syncthreads();
+        for (int i = tid; i < nb; i += blockDim.x) {
+          cplx acc = v[i];
+          for (int q = 0; q < r; ++q) acc = csub(acc, cmul(h[q], X[(int64_t)perm[q] * nb + i]));
+          v[i] = acc;
+        }
+        __syncthreads();
+      }
+      double n2 = 0.0;
+      for (int i = tid; i < nb; i += blockDim.x) n2 += cabs2(v[i]);
+      n2 = block_sum(n2, red);
+      if (n2 >= 0.5 / nb) {
+        const double inv = 1.0 / sqrt(n2);
+        for (int i = tid; i < nb; i += blockDim.x) v[i] = cscale(v[i], inv);
+        __syncthreads();
+        break;
+      }
+    }
+  }
+}
+
+// Kept columns to unit norm in place (perm[0..t0), above the floor), the
+// completion of the rest, then the outputs: core = U^H[:l] (tall) or
+// Ul = U[:, :l] (wide).
+__device__ void jacobi_outputs(cplx* X, const double* sig, const int* perm, int nb, int l,
+                               double negl, bool tall, cplx* core, cplx* Ul, cplx* h,
+                               double* red, int32_t* status) {
+  const int tid = threadIdx.x;
+  int t0 = l;
+  for (int r = 0; r < l; ++r) {
+    const double sv = sig[perm[r]];
+    if (!(sv * sv > negl)) { t0 = r; break; }
+  }
+  for (int64_t e = tid; e < (int64_t)t0 * nb; e += blockDim.x) {
+    const int r = (int)(e / nb), i = (int)(e % nb);
+    const int c = perm[r];
+    X[(int64_t)c * nb + i] = cscale(X[(int64_t)c * nb + i], 1.0 / sig[c]);
+  }
+  __syncthreads();
+  if (t0 < l) complete_columns(X, perm, nb, t0, l, h, red);
+  bool fin = true;
+  for (int64_t e = tid; e < (int64_t)l * nb; e += blockDim.x) {
+    const int r = (int)(e / nb), i = (int)(e % nb);
+    const cplx u = X[(int64_t)perm[r] * nb + i];
+    fin = fin && isfinite(u.x) && isfinite(u.y);
+    if (tall) core[e] = cconj(u);     // row r of U^H
+    else Ul[e] = u;
+  }
+  if (!fin) flag_out(status, tall ? 6 : 8, nb, l, sig[perm[0]], sig[perm[l - 1]]);
+}
+
+// One workgroup per instance; T (nb x nb, row-major) in Rin, X = T^H in LDS
+// (NBMAX <= 100).  Outputs: tall: core =
+// U^H[:l] (l x nb, row-major); wide: Ul = U[:, :l] (column r at Ul + r * nb),
+// from which the caller forms core = (Q U[:, :l])^H.
+template <int NBMAX>
 __global__ __launch_bounds__(1024) void k_jacobi_lds(
-    Dim Md, Dim Cd, const cplx* __restrict__ Rin, int64_t sR, cplx* __restrict__ RVp, int64_t sRV,
-    double* __restrict__ sigp, int64_t sSig, cplx* __restrict__ core, int64_t sCore,
-    cplx* __restrict__ carry, int64_t sCarry, int32_t* l_out, int l_stride,
+    Dim Md, Dim Cd, const cplx* __restrict__ Rin, int64_t sR, cplx* __restrict__ Ul, int64_t sU,
+    cplx* __restrict__ core, int64_t sCore, int32_t* l_out, int l_stride,
     const double* __restrict__ delta, double* __restrict__ disc2, int lmax, int max_sweeps,
-    int32_t* status, double* svlog, int64_t svstride, unsigned long long* counters,
-    cplx* __restrict__ Vg, int64_t sV) {
+    int32_t* status, double* svlog, int64_t svstride, unsigned long long* counters) {
   __shared__ cplx Rs[NBMAX * NBMAX];
-  __shared__ cplx Vl[VG ? 1 : NBMAX * NBMAX];
+  __shared__ cplx hb[NBMAX];          // projections of the column completion
   __shared__ double sig[NBMAX];
   __shared__ int perm[NBMAX];
   __shared__ double red[16];
@@ -59,16 +191,14 @@ __global__ __launch_bounds__(1024) void k_jacobi_lds(
   const int m = dimv(Md, b), nc = dimv(Cd, b);
   const bool tall = m >= nc;
   const int nb = tall ? nc : m;
-  Rin += b * sR; RVp += b * sRV; sigp += b * sSig; core += b * sCore; carry += b * sCarry;
-  cplx* Vs = VG ? Vg + b * sV : Vl;
+  Rin += b * sR; Ul += b * sU; core += b * sCore;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
-  for (int e = tid; e < nb * nb; e += blockDim.x) {
-    const int i = e / nb, c = e % nb;       // R row-major (nb x nb)
-    Rs[e] = cconj(Rin[e]);                  // column c of R^H = conj(row c of R)
-    Vs[c * nb + i] = make_double2(i == c ? 1.0 : 0.0, 0.0);
-  }
   double fro = 0.0;
-  for (int e = tid; e < nb * nb; e += blockDim.x) fro += cabs2(Rin[e]);
+  for (int e = tid; e < nb * nb; e += blockDim.x) {
+    const cplx v = cconj(Rin[e]);         // column c of T^H = conj(row c of T)
+    Rs[e] = v;
+    fro += cabs2(v);
+  }
   fro = wave_sum(fro);
   if (lane == 0) red[wv] = fro;
   __syncthreads();
@@ -123,9 +253,12 @@ __global__ __launch_bounds__(1024) void k_jacobi_lds(
         cplx* bp = Rs + p * nb;
         cplx* bq = Rs + q * nb;
         // the pair's columns stay in registers between the dot products and
-        // the rotation (at most NBMAX / 16 rounded up rows per lane)
+        // the rotation up to order 68 (at most five rows per lane); above,
+        // the rotation reads them again from LDS (register budget of 1024
+        // threads)
         constexpr int RPL = (NBMAX + 15) / 16;
-        cplx xs[RPL], ys[RPL];
+        constexpr bool KEEP = RPL <= 5;
+        cplx xs[KEEP ? RPL : 1], ys[KEEP ? RPL : 1];
         double al = 0.0, be = 0.0;
         cplx ga = make_double2(0.0, 0.0);
 #pragma unroll
@@ -136,7 +269,7 @@ __global__ __launch_bounds__(1024) void k_jacobi_lds(
             x = bp[i];
             y = bq[i];
           }
-          if (!VG) {
+          if (KEEP) {
             xs[it] = x;
             ys[it] = y;
           }
@@ -160,26 +293,9 @@ __global__ __launch_bounds__(1024) void k_jacobi_lds(
           for (int it = 0; it < RPL; ++it) {
             const int i = g + 16 * it;
             if (i < nb) {
-              // the large variant re-reads R from LDS (registers hold V)
-              const cplx x = VG ? bp[i] : xs[it], y = VG ? bq[i] : ys[it];
+              const cplx x = KEEP ? xs[it] : bp[i], y = KEEP ? ys[it] : bq[i];
               bp[i] = csub(cscale(x, c), cmul(sec, y));
               bq[i] = cadd(cmul(se, x), cscale(y, c));
-            }
-          }
-          cplx* vp = Vs + p * nb;
-          cplx* vq = Vs + q * nb;
-#pragma unroll
-          for (int it = 0; it < RPL; ++it) {     // all loads first, then the updates
-            const int i = g + 16 * it;
-            xs[it] = i < nb ? vp[i] : make_double2(0.0, 0.0);
-            ys[it] = i < nb ? vq[i] : make_double2(0.0, 0.0);
-          }
-#pragma unroll
-          for (int it = 0; it < RPL; ++it) {
-            const int i = g + 16 * it;
-            if (i < nb) {
-              vp[i] = csub(cscale(xs[it], c), cmul(sec, ys[it]));
-              vq[i] = cadd(cmul(se, xs[it]), cscale(ys[it], c));
             }
           }
           if (g == 0) {
@@ -225,36 +341,8 @@ __global__ __launch_bounds__(1024) void k_jacobi_lds(
   }
   __syncthreads();
   if (tid == 0) {
-    const double dl = delta[b];
-    double tail2 = 0.0;
-    int l = nb;
-    for (int j = nb - 1; j >= 0; --j) {
-      const double sj = sig[perm[j]];
-      if (sqrt(tail2 + sj * sj) <= dl) { tail2 += sj * sj; l = j; }
-      else break;
-    }
-    if (l < 1) l = 1;
-    if (l > lmax) l = lmax;
-    if (l > nb) l = nb;
-    double d2 = 0.0;
-    bool finite = true;
-    for (int j = 0; j < nb; ++j) {
-      const double sj = sig[perm[j]];
-      if (!isfinite(sj)) finite = false;
-      if (j >= l) d2 += sj * sj;
-    }
-    if (!finite) {
-      const int32_t old = atomicOr(status, (int32_t)ST_NONFINITE);
-      if (!(old & ST_NONFINITE)) {
-        double* d = status_diag(status) + 5;
-        d[0] = nb;
-        d[1] = fro;
-        d[2] = -1.0;
-        d[3] = 1.0;   // LDS Jacobi
-        d[4] = sweeps_done;
-      }
-    }
-    disc2[b] += d2;
+    const int l = jacobi_truncate(sig, perm, nb, delta[b], lmax, disc2 + b, status, fro,
+                                  sweeps_done, 1.0);
     sh_l = l;
     if (l_out) l_out[(int64_t)b * l_stride] = l;
   }
@@ -262,57 +350,28 @@ __global__ __launch_bounds__(1024) void k_jacobi_lds(
   const int l = sh_l;
   if (svlog)
     for (int j = tid; j < nb; j += blockDim.x) svlog[b * svstride + j] = sig[perm[j]];
-  // W[:, perm[:l]] column-major and sorted sigma for the finalizer
-  for (int e = tid; e < l * nb; e += blockDim.x) {
-    const int r = e / nb, i = e % nb;
-    RVp[e] = Vs[perm[r] * nb + i];
-  }
-  for (int r = tid; r < l; r += blockDim.x) sigp[r] = sig[perm[r]];
-  bool fin = true;
-  if (tall) {
-    // core = U^H[:l]  (l x nc), nc = nb; U[:, r] = (R^H W)[:, r] / sigma_r
-    for (int e = tid; e < l * nb; e += blockDim.x) {
-      const int r = e / nb, c = e % nb;
-      const double sv = sig[perm[r]];
-      const cplx v = sv > 0.0 ? cscale(cconj(Rs[perm[r] * nb + c]), 1.0 / sv)
-                              : make_double2(c == r ? 1.0 : 0.0, 0.0);
-      fin = fin && isfinite(v.x) && isfinite(v.y);
-      core[e] = v;
-    }
-  } else {
-    // carry = (R^H W)[:, perm[:l]] = U Sigma  (m x l), m = nb
-    for (int e = tid; e < nb * l; e += blockDim.x) {
-      const int i = e / l, r = e % l;
-      const cplx v = Rs[perm[r] * nb + i];
-      fin = fin && isfinite(v.x) && isfinite(v.y);
-      carry[e] = v;
-    }
-  }
-  for (int e = tid; e < l * nb; e += blockDim.x) {
-    const cplx v = RVp[e];
-    fin = fin && isfinite(v.x) && isfinite(v.y);
-  }
-  if (!fin) flag_out(status, tall ? 6 : 8, nb, l, sig[perm[0]], sig[perm[l - 1]]);
+  // U[:, r] = (X W)[:, perm[r]] / sigma
+  jacobi_outputs(Rs, sig, perm, nb, l, negl, tall, core, Ul, hb, red, status);
 }
 
 
 // Global-memory variant for orders 100 < nb <= 1024 (same algorithm, schedule
-// and thresholds): R^H in the work matrix Rt, W in Vw (both column-major,
-// nb x nb per instance); each 16-lane group streams its pair's columns in
-// chunks of SG_CH rows per lane (all loads of a chunk issued before use).
-// Rio: R (row-major) on entry, W[:, perm[:l]] (column-major) on exit.
+// and thresholds): X in the work matrix Xw (column-major, nb x nb per
+// instance); each 16-lane group streams its pair's columns in chunks of SG_CH
+// rows per lane (all loads of a chunk issued before use).  Outputs as the LDS
+// variant.
 constexpr int SG_NB = 1024;
 constexpr int SG_CH = 6;
 
 __global__ __launch_bounds__(1024) void k_jacobi_glb(
-    Dim Md, Dim Cd, cplx* Rio, int64_t sR, cplx* __restrict__ Rt, int64_t sRt,
-    cplx* __restrict__ Vw, int64_t sV, double* __restrict__ sigp, int64_t sSig,
-    cplx* __restrict__ core, int64_t sCore, cplx* __restrict__ carry, int64_t sCarry,
-    int32_t* l_out, int l_stride, const double* __restrict__ delta, double* __restrict__ disc2,
-    int lmax, int max_sweeps, int32_t* status, double* svlog, int64_t svstride,
+    Dim Md, Dim Cd, const cplx* __restrict__ Rin, int64_t sR, cplx* __restrict__ Xw, int64_t sX,
+    cplx* __restrict__ Ul, int64_t sU, cplx* __restrict__ core, int64_t sCore, int32_t* l_out,
+    int l_stride, const double* __restrict__ delta, double* __restrict__ disc2, int lmax,
+    int max_sweeps, int32_t* status, double* svlog, int64_t svstride,
     unsigned long long* counters) {
   __shared__ double sig[SG_NB];
   __shared__ int perm[SG_NB];
+  __shared__ cplx hb[SG_NB];
   __shared__ double red[16];
   __shared__ int sh_rot, sh_l;
   __shared__ unsigned long long sh_worst, sh_small;
@@ -320,16 +379,14 @@ __global__ __launch_bounds__(1024) void k_jacobi_glb(
   const int m = dimv(Md, b), nc = dimv(Cd, b);
   const bool tall = m >= nc;
   const int nb = tall ? nc : m;
-  Rio += b * sR; Rt += b * sRt; Vw += b * sV; sigp += b * sSig; core += b * sCore;
-  carry += b * sCarry;
+  Rin += b * sR; Xw += b * sX; Ul += b * sU; core += b * sCore;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
   const int64_t nn = (int64_t)nb * nb;
   double fro = 0.0;
   for (int64_t e = tid; e < nn; e += blockDim.x) {
-    const cplx v = Rio[e];
+    const cplx v = cconj(Rin[e]);         // column c of T^H = conj(row c of T)
     fro += cabs2(v);
-    Rt[e] = cconj(v);                       // column c of R^H = conj(row c of R)
-    Vw[e] = make_double2((e / nb) == (e % nb) ? 1.0 : 0.0, 0.0);
+    Xw[e] = v;
   }
   fro = wave_sum(fro);
   if (lane == 0) red[wv] = fro;
@@ -375,8 +432,8 @@ __global__ __launch_bounds__(1024) void k_jacobi_glb(
           if (p >= nb || q >= nb) valid = false;
           if (p > q) { int t = p; p = q; q = t; }
         }
-        cplx* bp = Rt + (int64_t)p * nb;
-        cplx* bq = Rt + (int64_t)q * nb;
+        cplx* bp = Xw + (int64_t)p * nb;
+        cplx* bq = Xw + (int64_t)q * nb;
         double al = 0.0, be = 0.0;
         cplx ga = make_double2(0.0, 0.0);
         if (valid) {
@@ -408,25 +465,20 @@ __global__ __launch_bounds__(1024) void k_jacobi_glb(
           const double c = fast_rsq(fma(t, t, 1.0)), s = c * t;
           const cplx e = make_double2(ga.x * ig, ga.y * ig);
           const cplx se = cscale(e, s), sec = cscale(cconj(e), s);
-#pragma unroll 1
-          for (int half = 0; half < 2; ++half) {   // R^H columns, then W columns
-            cplx* cp = half == 0 ? bp : Vw + (int64_t)p * nb;
-            cplx* cq = half == 0 ? bq : Vw + (int64_t)q * nb;
-            for (int i0 = g; i0 < nb; i0 += 16 * SG_CH) {
-              cplx xs[SG_CH], ys[SG_CH];
+          for (int i0 = g; i0 < nb; i0 += 16 * SG_CH) {
+            cplx xs[SG_CH], ys[SG_CH];
 #pragma unroll
-              for (int u = 0; u < SG_CH; ++u) {
-                const int i = i0 + 16 * u;
-                xs[u] = i < nb ? cp[i] : make_double2(0.0, 0.0);
-                ys[u] = i < nb ? cq[i] : make_double2(0.0, 0.0);
-              }
+            for (int u = 0; u < SG_CH; ++u) {
+              const int i = i0 + 16 * u;
+              xs[u] = i < nb ? bp[i] : make_double2(0.0, 0.0);
+              ys[u] = i < nb ? bq[i] : make_double2(0.0, 0.0);
+            }
 #pragma unroll
-              for (int u = 0; u < SG_CH; ++u) {
-                const int i = i0 + 16 * u;
-                if (i < nb) {
-                  cp[i] = csub(cscale(xs[u], c), cmul(sec, ys[u]));
-                  cq[i] = cadd(cmul(se, xs[u]), cscale(ys[u], c));
-                }
+            for (int u = 0; u < SG_CH; ++u) {
+              const int i = i0 + 16 * u;
+              if (i < nb) {
+                bp[i] = csub(cscale(xs[u], c), cmul(sec, ys[u]));
+                bq[i] = cadd(cmul(se, xs[u]), cscale(ys[u], c));
               }
             }
           }
@@ -460,7 +512,7 @@ __global__ __launch_bounds__(1024) void k_jacobi_glb(
   }
   for (int c = wv; c < nb; c += nw) {
     double a = 0.0;
-    for (int i = lane; i < nb; i += 64) a += cabs2(Rt[(int64_t)c * nb + i]);
+    for (int i = lane; i < nb; i += 64) a += cabs2(Xw[(int64_t)c * nb + i]);
     a = wave_sum(a);
     if (lane == 0) sig[c] = sqrt(a);
   }
@@ -473,26 +525,8 @@ __global__ __launch_bounds__(1024) void k_jacobi_glb(
   }
   __syncthreads();
   if (tid == 0) {
-    const double dl = delta[b];
-    double tail2 = 0.0;
-    int l = nb;
-    for (int j = nb - 1; j >= 0; --j) {
-      const double sj = sig[perm[j]];
-      if (sqrt(tail2 + sj * sj) <= dl) { tail2 += sj * sj; l = j; }
-      else break;
-    }
-    if (l < 1) l = 1;
-    if (l > lmax) l = lmax;
-    if (l > nb) l = nb;
-    double d2 = 0.0;
-    bool finite = true;
-    for (int j = 0; j < nb; ++j) {
-      const double sj = sig[perm[j]];
-      if (!isfinite(sj)) finite = false;
-      if (j >= l) d2 += sj * sj;
-    }
-    if (!finite) flag_out(status, 2, nb, l, fro, -1.0);
-    disc2[b] += d2;
+    const int l = jacobi_truncate(sig, perm, nb, delta[b], lmax, disc2 + b, status, fro,
+                                  sweeps_done, 2.0);
     sh_l = l;
     if (l_out) l_out[(int64_t)b * l_stride] = l;
   }
@@ -500,40 +534,12 @@ __global__ __launch_bounds__(1024) void k_jacobi_glb(
   const int l = sh_l;
   if (svlog)
     for (int j = tid; j < nb; j += blockDim.x) svlog[b * svstride + j] = sig[perm[j]];
-  for (int r = tid; r < l; r += blockDim.x) sigp[r] = sig[perm[r]];
-  bool fin = true;
-  if (tall) {
-    for (int64_t e = tid; e < (int64_t)l * nb; e += blockDim.x) {
-      const int r = (int)(e / nb), c = (int)(e % nb);
-      const double sv = sig[perm[r]];
-      const cplx v = sv > 0.0 ? cscale(cconj(Rt[(int64_t)perm[r] * nb + c]), 1.0 / sv)
-                              : make_double2(c == r ? 1.0 : 0.0, 0.0);
-      fin = fin && isfinite(v.x) && isfinite(v.y);
-      core[e] = v;
-    }
-  } else {
-    for (int64_t e = tid; e < (int64_t)nb * l; e += blockDim.x) {
-      const int i = (int)(e / l), r = (int)(e % l);
-      const cplx v = Rt[(int64_t)perm[r] * nb + i];
-      fin = fin && isfinite(v.x) && isfinite(v.y);
-      carry[e] = v;
-    }
-  }
-  // W[:, perm[:l]] over R (consumed at entry) for the finishing products,
-  // scaled by sigma for the carry Q W Sigma (A = Q R)
-  for (int64_t e = tid; e < (int64_t)l * nb; e += blockDim.x) {
-    const int r = (int)(e / nb), i = (int)(e % nb);
-    const cplx w = Vw[(int64_t)perm[r] * nb + i];
-    const cplx v = tall ? cscale(w, sig[perm[r]]) : w;
-    fin = fin && isfinite(v.x) && isfinite(v.y);
-    Rio[e] = v;
-  }
-  if (!fin) flag_out(status, tall ? 6 : 8, nb, l, sig[perm[0]], sig[perm[l - 1]]);
+  jacobi_outputs(Xw, sig, perm, nb, l, negl, tall, core, Ul, hb, red, status);
 }
 
-// Sizes of the two finishing products of the global-memory variant:
-// [0..2] = (m, l, nb) for A = Q R (tall), [3..5] = (l, nc, nb) for A^H = Q R;
-// zeros for the orientation an instance does not have.
+// Sizes of the two finishing products per instance (ds ints each):
+// [0..2] = (l, nc, nb) of core = U[:, :l]^H Q^H for A^H = Q R (zeros when
+// tall); [3..5] = (m, l, nc) of carry = A core^H.
 __global__ void k_fin_dims(int batch, Dim Md, Dim Cd, const int32_t* l_in, int l_stride,
                            int32_t* fd, int ds) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
@@ -541,46 +547,29 @@ __global__ void k_fin_dims(int batch, Dim Md, Dim Cd, const int32_t* l_in, int l
   const int m = dimv(Md, b), nc = dimv(Cd, b), l = l_in[(int64_t)b * l_stride];
   const bool tall = m >= nc;
   int32_t* d = fd + (int64_t)b * ds;
-  d[0] = tall ? m : 0; d[1] = tall ? l : 0; d[2] = tall ? nc : 0;
-  d[3] = tall ? 0 : l; d[4] = tall ? 0 : nc; d[5] = tall ? 0 : m;
+  d[0] = tall ? 0 : l; d[1] = tall ? 0 : nc; d[2] = tall ? 0 : m;
+  d[3] = m; d[4] = l; d[5] = nc;
 }
 
-// Applies Q (mb x nb, row-major) to the kept columns of W: the carry
-// Q W Sigma (A = Q R) or the core rows (Q W)^H (A^H = Q R).
-__global__ __launch_bounds__(1024) void k_svd_finalize(Dim Md, Dim Cd, const cplx* __restrict__ Q,
-                                                       int64_t sQ, const cplx* __restrict__ RVp,
-                                                       int64_t sRV, const double* __restrict__ sigp,
-                                                       int64_t sSig, const int32_t* l_in,
-                                                       int l_stride, cplx* __restrict__ core,
-                                                       int64_t sCore, cplx* __restrict__ carry,
-                                                       int64_t sCarry, int32_t* status) {
+// Wide instances (A^H = Q R): R^H (packed nb x nb) into X for the second QR,
+// and its order in fd[6] (0 for tall instances, whose R is kept).
+__global__ void k_qr2_prep(Dim Md, Dim Cd, const cplx* __restrict__ R, int64_t sR,
+                           cplx* __restrict__ X, int64_t sX, int32_t* fd, int ds) {
   const int b = blockIdx.x;
   const int m = dimv(Md, b), nc = dimv(Cd, b);
-  const bool tall = m >= nc;
-  const int mb = tall ? m : nc, nb = tall ? nc : m;
-  const int l = l_in[(int64_t)b * l_stride];
-  Q += b * sQ; RVp += b * sRV; sigp += b * sSig; core += b * sCore; carry += b * sCarry;
-  for (int e = threadIdx.x; e < mb * l; e += blockDim.x) {
-    const int i = e / l, r = e % l;
-    cplx acc = make_double2(0.0, 0.0);
-    const cplx* qi = Q + (int64_t)i * nb;
-    const cplx* rv = RVp + (int64_t)r * nb;
-    for (int c = 0; c < nb; ++c) cfma(acc, qi[c], rv[c]);
-    if (tall) {
-      const cplx v = cscale(acc, sigp[r]);
-      if (!(isfinite(v.x) && isfinite(v.y))) flag_out(status, 9, nb, l, sigp[0], sigp[l - 1]);
-      carry[(int64_t)i * l + r] = v;                       // carry (m x l)
-    } else {
-      const cplx v = cconj(acc);
-      if (!(isfinite(v.x) && isfinite(v.y))) flag_out(status, 7, nb, l, sigp[0], sigp[l - 1]);
-      core[(int64_t)r * nc + i] = v;                       // core (l x nc), row r
-    }
+  const bool wide = m < nc;
+  if (threadIdx.x == 0) fd[(int64_t)b * ds + 6] = wide ? m : 0;
+  if (!wide) return;
+  R += b * sR; X += b * sX;
+  for (int64_t e = threadIdx.x; e < (int64_t)m * m; e += blockDim.x) {
+    const int64_t i = e / m, j = e % m;
+    X[e] = cconj(R[j * m + i]);
   }
 }
 
 bool svd_trunc_fast(hipStream_t st, int batch, int mcap, int ccap, Dim m, Dim c, const cplx* A,
-                    int64_t sA, cplx* Qw, cplx* Uw, int64_t sQ, cplx* Rw, cplx* RVw, int64_t sR,
-                    double* tau, double* sig, int64_t sT, cplx* core, int64_t sCore, cplx* carry,
+                    int64_t sA, cplx* Qw, cplx* Uw, int64_t sQ, cplx* Rw, cplx* Xw, int64_t sR,
+                    double* tau, int64_t sT, cplx* core, int64_t sCore, cplx* carry,
                     int64_t sCarry, int32_t* l_out, int l_stride, const double* delta,
                     double* disc2, int lmax, int max_sweeps, int32_t* status, double* svlog,
                     int64_t svstride, unsigned long long* counters) {
@@ -589,41 +578,45 @@ bool svd_trunc_fast(hipStream_t st, int batch, int mcap, int ccap, Dim m, Dim c,
   if (!qr_reg(st, batch, mbcap, nbcap, m, c, A, sA, Uw, sQ, tau, sT, Qw, sQ, Rw, sR, nullptr, 0,
               true))
     qr_mem(st, batch, mbcap, nbcap, m, c, A, sA, Uw, sQ, tau, sT, Qw, sQ, Rw, sR, nullptr, 0, true);
-  if (nbcap > SL_NB_BIG) {
-    // R^H in RVw, W in the QR scratch Uw (free after the QR), W[:, perm] back over R
-    k_jacobi_glb<<<batch, 1024, 0, st>>>(m, c, Rw, sR, RVw, sR, Uw, sQ, sig, sT, core, sCore,
-                                         carry, sCarry, l_out, l_stride, delta, disc2, lmax,
-                                         max_sweeps, status, svlog, svstride, counters);
-    // finishing products on the MFMA GEMM: carry = Q (W Sigma) for A = Q R,
-    // core = W^H Q^H for A^H = Q R; each instance's sizes are zero in the
-    // product of the other orientation
-    int32_t* fd = reinterpret_cast<int32_t*>(tau);
-    const int ds = (int)(2 * sT);
-    k_fin_dims<<<(batch + 127) / 128, 128, 0, st>>>(batch, m, c, l_out, l_stride, fd, ds);
-    const Dim tM = dref(fd + 0, ds), tN = dref(fd + 1, ds), tK = dref(fd + 2, ds);
-    const Dim wM = dref(fd + 3, ds), wN = dref(fd + 4, ds), wK = dref(fd + 5, ds);
-    const Str snb{fd + 2, ds, 1, 0}, sl{fd + 1, ds, 1, 0};
-    const Str wnb{fd + 5, ds, 1, 0}, wnc{fd + 4, ds, 1, 0};
-    const Str one{nullptr, 0, 0, 1};
-    const cplx c1 = make_double2(1.0, 0.0);
-    gemm_ex(st, batch, 1, 1, tM, tN, tK, mbcap, nbcap, mat(Qw, sQ, snb, one), false,
-            mat(Rw, sR, one, snb), false, mat(carry, sCarry, sl, one), c1, false,
-            Dim{nullptr, 0, 0, 1 << 30}, nbcap);
-    gemm_ex(st, batch, 1, 1, wM, wN, wK, nbcap, mbcap, mat(Rw, sR, wnb, one), true,
-            mat(Qw, sQ, one, wnb), true, mat(core, sCore, wnc, one), c1, false,
-            Dim{nullptr, 0, 0, 1 << 30}, nbcap);
-    return true;
-  }
+  // per-instance sizes in the last 4 doubles of each tau slice (the QRs use
+  // the first nb <= sT - 4)
+  int32_t* fd = reinterpret_cast<int32_t*>(tau + sT - 4);
+  const int ds = (int)(2 * sT);
+  // wide instances: R2 of the second QR (R^H = Q2 R2) over R, Q2 not formed
+  k_qr2_prep<<<batch, 256, 0, st>>>(m, c, Rw, sR, Xw, sR, fd, ds);
+  const Dim d2 = dref(fd + 6, ds);
+  if (!qr_reg(st, batch, nbcap, nbcap, d2, d2, Xw, sR, Uw, sQ, tau, sT, nullptr, 0, Rw, sR,
+              nullptr, 0, false))
+    qr_mem(st, batch, nbcap, nbcap, d2, d2, Xw, sR, Uw, sQ, tau, sT, nullptr, 0, Rw, sR, nullptr,
+           0, false);
+  // U[:, :l] of wide instances into the QR scratch Uw (free after the QRs)
   if (nbcap <= SL_NB)
-    k_jacobi_lds<SL_NB, false><<<batch, 1024, 0, st>>>(
-        m, c, Rw, sR, RVw, sR, sig, sT, core, sCore, carry, sCarry, l_out, l_stride, delta, disc2,
-        lmax, max_sweeps, status, svlog, svstride, counters, nullptr, 0);
-  else   // V in the QR scratch Uw (mbcap x nbcap >= nb x nb per instance), free after the QR
-    k_jacobi_lds<SL_NB_BIG, true><<<batch, 1024, 0, st>>>(
-        m, c, Rw, sR, RVw, sR, sig, sT, core, sCore, carry, sCarry, l_out, l_stride, delta, disc2,
-        lmax, max_sweeps, status, svlog, svstride, counters, Uw, sQ);
-  k_svd_finalize<<<batch, 1024, 0, st>>>(m, c, Qw, sQ, RVw, sR, sig, sT, l_out, l_stride, core,
-                                         sCore, carry, sCarry, status);
+    k_jacobi_lds<SL_NB><<<batch, 1024, 0, st>>>(m, c, Rw, sR, Uw, sQ, core, sCore, l_out,
+                                                 l_stride, delta, disc2, lmax, max_sweeps, status,
+                                                 svlog, svstride, counters);
+  else if (nbcap <= SL_NB_BIG)
+    k_jacobi_lds<SL_NB_BIG><<<batch, 1024, 0, st>>>(m, c, Rw, sR, Uw, sQ, core, sCore, l_out,
+                                                     l_stride, delta, disc2, lmax, max_sweeps,
+                                                     status, svlog, svstride, counters);
+  else
+    k_jacobi_glb<<<batch, 1024, 0, st>>>(m, c, Rw, sR, Xw, sR, Uw, sQ, core, sCore, l_out,
+                                         l_stride, delta, disc2, lmax, max_sweeps, status, svlog,
+                                         svstride, counters);
+  // finishing products on the MFMA GEMM (each instance's sizes are zero in the
+  // product of the orientation it does not have):
+  //   core  = U[:, :l]^H Q^H  (l x nc)  for A^H = Q R;
+  //   carry = A core^H        (m x l)   for every instance
+  k_fin_dims<<<(batch + 127) / 128, 128, 0, st>>>(batch, m, c, l_out, l_stride, fd, ds);
+  const Str one{nullptr, 0, 0, 1};
+  const Str s_nc{fd + 1, ds, 1, 0}, s_nb{fd + 2, ds, 1, 0};
+  const Str s_l{fd + 4, ds, 1, 0}, s_k{fd + 5, ds, 1, 0};
+  const cplx c1 = make_double2(1.0, 0.0);
+  gemm_ex(st, batch, 1, 1, dref(fd + 0, ds), dref(fd + 1, ds), dref(fd + 2, ds), nbcap, mbcap,
+          mat(Uw, sQ, s_nb, one), true, mat(Qw, sQ, one, s_nb), true,
+          mat(core, sCore, s_nc, one), c1, false, Dim{nullptr, 0, 0, 1 << 30}, nbcap);
+  gemm_ex(st, batch, 1, 1, dref(fd + 3, ds), dref(fd + 4, ds), dref(fd + 5, ds), mcap, nbcap,
+          mat(A, sA, s_k, one), false, mat(core, sCore, one, s_k), true,
+          mat(carry, sCarry, s_l, one), c1, false, Dim{nullptr, 0, 0, 1 << 30}, ccap);
   return true;
 }
 
