@@ -95,6 +95,37 @@ __device__ inline double block_sum(double v, double* red) {
   return s;
 }
 
+// Maximum / minimum over the block (every thread gets the result).
+__device__ inline double block_max(double v, double* red) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  __syncthreads();
+  if (lane == 0) red[wv] = v;
+  __syncthreads();
+  double s = red[0];
+  for (int i = 1; i < nw; ++i) s = fmax(s, red[i]);
+  return s;
+}
+__device__ inline double block_min(double v, double* red) {
+  return -block_max(-v, red);
+}
+
+// Sweep-cap diagnostics (thread 0): order, Frobenius norm^2, largest
+// |gamma| / sqrt(alpha beta) / tol and smallest rotated column norm^2 /
+// Frobenius^2 of the last sweep, sweeps done.
+__device__ inline void flag_sweep_cap(int32_t* status, int nb, double fro, double worst2,
+                                      double small2, double jtol, int sweeps_done) {
+  const int32_t old = atomicOr(status, (int32_t)ST_JACOBI_CAP);
+  if (!(old & ST_JACOBI_CAP)) {
+    double* d = status_diag(status);
+    d[0] = nb;
+    d[1] = fro;
+    d[2] = sqrt(worst2) / jtol;
+    d[3] = small2 / fro;
+    d[4] = sweeps_done;
+  }
+}
+
 // Kept columns whose squared norm is at or below the rotation floor were
 // never rotated, so they are not orthogonal to the others.  Their weight in
 // the matrix is below 1e-17 of its norm, so any orthonormal completion
@@ -185,8 +216,7 @@ __global__ __launch_bounds__(1024) void k_jacobi_lds(
   __shared__ double sig[NBMAX];
   __shared__ int perm[NBMAX];
   __shared__ double red[16];
-  __shared__ int sh_rot, sh_l;
-  __shared__ unsigned long long sh_worst, sh_small;   // bit patterns of positive doubles
+  __shared__ int sh_l;
   const int b = blockIdx.x;
   const int m = dimv(Md, b), nc = dimv(Cd, b);
   const bool tall = m >= nc;
@@ -222,14 +252,15 @@ __global__ __launch_bounds__(1024) void k_jacobi_lds(
   bool converged = nb < 2;
   int sweeps_done = 0;
   // each 16-lane row group owns one pair per round; sums reduce over the group by DPP
+  // per lane over the current sweep: any rotation, largest gamma^2 / (alpha
+  // beta) and smallest rotated column norm^2 (diagnostics of the sweep cap);
+  // convergence is one block-wide OR per sweep
+  double worst2 = 0.0, small2 = 0.0;
   for (int sweep = 0; sweep < max_sweeps && !converged; ++sweep) {
     ++sweeps_done;
-    if (tid == 0) {
-      sh_rot = 0;
-      sh_worst = 0ull;
-      sh_small = (unsigned long long)__double_as_longlong(1.0);
-    }
-    __syncthreads();
+    int any_rot = 0;
+    worst2 = 0.0;
+    small2 = fro;
     for (int r = 0; r < nbp - 1; ++r) {
       for (int pi0 = 0; pi0 < nbp / 2; pi0 += ngrp) {
         // waves whose four groups all lie beyond the last pair of this round
@@ -298,29 +329,18 @@ __global__ __launch_bounds__(1024) void k_jacobi_lds(
               bq[i] = cadd(cmul(se, x), cscale(y, c));
             }
           }
-          if (g == 0) {
-            sh_rot = 1;
-            atomicMax(&sh_worst, (unsigned long long)__double_as_longlong(
-                                     sqrt(g2 / (al * be)) / jtol));
-            atomicMin(&sh_small, (unsigned long long)__double_as_longlong(fmin(al, be) / fro));
-          }
+          any_rot = 1;
+          worst2 = fmax(worst2, g2 * fast_rcp(al * be));
+          small2 = fmin(small2, fmin(al, be));
         }
       }
       __syncthreads();
     }
-    converged = (sh_rot == 0);
-    __syncthreads();
+    converged = !__syncthreads_or(any_rot);
   }
-  if (!converged && tid == 0) {
-    const int32_t old = atomicOr(status, (int32_t)ST_JACOBI_CAP);
-    if (!(old & ST_JACOBI_CAP)) {
-      double* d = status_diag(status);
-      d[0] = nb;
-      d[1] = fro;
-      d[2] = __longlong_as_double((long long)sh_worst);
-      d[3] = __longlong_as_double((long long)sh_small);
-      d[4] = sweeps_done;
-    }
+  if (!converged) {   // block-uniform
+    const double w2 = block_max(worst2, red), s2 = block_min(small2, red);
+    if (tid == 0) flag_sweep_cap(status, nb, fro, w2, s2, jtol, sweeps_done);
   }
   if (tid == 0 && counters) {
     atomicAdd(counters + CNT_SVD_CALLS, 1ull);
@@ -373,8 +393,7 @@ __global__ __launch_bounds__(1024) void k_jacobi_glb(
   __shared__ int perm[SG_NB];
   __shared__ cplx hb[SG_NB];
   __shared__ double red[16];
-  __shared__ int sh_rot, sh_l;
-  __shared__ unsigned long long sh_worst, sh_small;
+  __shared__ int sh_l;
   const int b = blockIdx.x;
   const int m = dimv(Md, b), nc = dimv(Cd, b);
   const bool tall = m >= nc;
@@ -406,14 +425,15 @@ __global__ __launch_bounds__(1024) void k_jacobi_glb(
   const int g = tid & 15, grp = tid >> 4, ngrp = blockDim.x >> 4;
   bool converged = nb < 2;
   int sweeps_done = 0;
+  // per lane over the current sweep: any rotation, largest gamma^2 / (alpha
+  // beta) and smallest rotated column norm^2 (diagnostics of the sweep cap);
+  // convergence is one block-wide OR per sweep
+  double worst2 = 0.0, small2 = 0.0;
   for (int sweep = 0; sweep < max_sweeps && !converged; ++sweep) {
     ++sweeps_done;
-    if (tid == 0) {
-      sh_rot = 0;
-      sh_worst = 0ull;
-      sh_small = (unsigned long long)__double_as_longlong(1.0);
-    }
-    __syncthreads();
+    int any_rot = 0;
+    worst2 = 0.0;
+    small2 = fro;
     for (int r = 0; r < nbp - 1; ++r) {
       for (int pi0 = 0; pi0 < nbp / 2; pi0 += ngrp) {
         if (pi0 + 4 * wv >= nbp / 2) continue;   // wave-uniform: no pair for this wave
@@ -482,29 +502,18 @@ __global__ __launch_bounds__(1024) void k_jacobi_glb(
               }
             }
           }
-          if (g == 0) {
-            sh_rot = 1;
-            atomicMax(&sh_worst, (unsigned long long)__double_as_longlong(
-                                     sqrt(g2 / (al * be)) / jtol));
-            atomicMin(&sh_small, (unsigned long long)__double_as_longlong(fmin(al, be) / fro));
-          }
+          any_rot = 1;
+          worst2 = fmax(worst2, g2 * fast_rcp(al * be));
+          small2 = fmin(small2, fmin(al, be));
         }
       }
       __syncthreads();
     }
-    converged = (sh_rot == 0);
-    __syncthreads();
+    converged = !__syncthreads_or(any_rot);
   }
-  if (!converged && tid == 0) {
-    const int32_t old = atomicOr(status, (int32_t)ST_JACOBI_CAP);
-    if (!(old & ST_JACOBI_CAP)) {
-      double* d = status_diag(status);
-      d[0] = nb;
-      d[1] = fro;
-      d[2] = __longlong_as_double((long long)sh_worst);
-      d[3] = __longlong_as_double((long long)sh_small);
-      d[4] = sweeps_done;
-    }
+  if (!converged) {   // block-uniform
+    const double w2 = block_max(worst2, red), s2 = block_min(small2, red);
+    if (tid == 0) flag_sweep_cap(status, nb, fro, w2, s2, jtol, sweeps_done);
   }
   if (tid == 0 && counters) {
     atomicAdd(counters + CNT_SVD_CALLS, 1ull);
