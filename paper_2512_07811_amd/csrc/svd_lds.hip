@@ -129,67 +129,80 @@ __device__ inline void flag_sweep_cap(int32_t* status, int nb, double fro, doubl
 // Kept columns whose squared norm is at or below the rotation floor were
 // never rotated, so they are not orthogonal to the others.  Their weight in
 // the matrix is below 1e-17 of its norm, so any orthonormal completion
-// serves: the sorted kept columns perm[t0..l) become, one by one, the first
-// unit vector e_j that keeps more than half of the average share (nb - r)/nb
-// after the previous columns are projected out twice (classical
-// Gram-Schmidt with reorthogonalization), normalized.  Columns perm[0..t0)
-// must have unit norm.  Whole block; h holds l complex values.
+// serves: the sorted kept columns perm[t0..l) become, one by one, the unit
+// vector e_j with the largest weight w_j = 1 - sum_q |U[j, q]|^2 outside the
+// current span (at least (nb - r) / nb), with the previous columns projected
+// out twice (classical Gram-Schmidt with reorthogonalization), normalized.
+// Columns perm[0..t0) must have unit norm.  Whole block; h holds l complex
+// values, w (nb doubles) is scratch.
 __device__ void complete_columns(cplx* X, const int* perm, int nb, int t0, int l, cplx* h,
-                                 double* red) {
+                                 double* red, double* w) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
+  for (int j = tid; j < nb; j += blockDim.x) {
+    double a = 1.0;
+    for (int q = 0; q < t0; ++q) a -= cabs2(X[(int64_t)perm[q] * nb + j]);
+    w[j] = a;
+  }
+  __syncthreads();
   for (int r = t0; r < l; ++r) {
+    double best = -1.0;
+    for (int j = tid; j < nb; j += blockDim.x) best = fmax(best, w[j]);
+    best = block_max(best, red);
+    double jb = (double)nb;
+    for (int j = tid; j < nb; j += blockDim.x)
+      if (w[j] == best) jb = fmin(jb, (double)j);
+    const int js = (int)block_min(jb, red);
     cplx* v = X + (int64_t)perm[r] * nb;
-    for (int j = 0; j < nb; ++j) {
-      for (int i = tid; i < nb; i += blockDim.x) v[i] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+    for (int i = tid; i < nb; i += blockDim.x) v[i] = make_double2(i == js ? 1.0 : 0.0, 0.0);
+    __syncthreads();
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int q = wv; q < r; q += nw) {
+        const cplx* u = X + (int64_t)perm[q] * nb;
+        cplx a = make_double2(0.0, 0.0);
+        for (int i = lane; i < nb; i += 64) cfma(a, cconj(u[i]), v[i]);
+        a = wave_sum(a);
+        if (lane == 0) h[q] = a;
+      }
       __syncthreads();
-      for (int pass = 0; pass < 2; ++pass) {
-        for (int q = wv; q < r; q += nw) {
-          const cplx* u = X + (int64_t)perm[q] * nb;
-          cplx a = make_double2(0.0, 0.0);
-          for (int i = lane; i < nb; i += 64) cfma(a, cconj(u[i]), v[i]);
-          a = wave_sum(a);
-          if (lane == 0) h[q] = a;
-        }
-        __syncthreads();
-        for (int i = tid; i < nb; i += blockDim.x) {
-          cplx acc = v[i];
-          for (int q = 0; q < r; ++q) acc = csub(acc, cmul(h[q], X[(int64_t)perm[q] * nb + i]));
-          v[i] = acc;
-        }
-        __syncthreads();
+      for (int i = tid; i < nb; i += blockDim.x) {
+        cplx acc = v[i];
+        for (int q = 0; q < r; ++q) acc = csub(acc, cmul(h[q], X[(int64_t)perm[q] * nb + i]));
+        v[i] = acc;
       }
-      double n2 = 0.0;
-      for (int i = tid; i < nb; i += blockDim.x) n2 += cabs2(v[i]);
-      n2 = block_sum(n2, red);
-      if (n2 >= 0.5 / nb) {
-        const double inv = 1.0 / sqrt(n2);
-        for (int i = tid; i < nb; i += blockDim.x) v[i] = cscale(v[i], inv);
-        __syncthreads();
-        break;
-      }
+      __syncthreads();
     }
+    double n2 = 0.0;
+    for (int i = tid; i < nb; i += blockDim.x) n2 += cabs2(v[i]);
+    const double inv = 1.0 / sqrt(block_sum(n2, red));
+    for (int i = tid; i < nb; i += blockDim.x) {
+      const cplx u = cscale(v[i], inv);
+      v[i] = u;
+      w[i] -= cabs2(u);
+    }
+    __syncthreads();
   }
 }
 
 // Kept columns to unit norm in place (perm[0..t0), above the floor), the
 // completion of the rest, then the outputs: core = U^H[:l] (tall) or
-// Ul = U[:, :l] (wide).
-__device__ void jacobi_outputs(cplx* X, const double* sig, const int* perm, int nb, int l,
-                               double negl, bool tall, cplx* core, cplx* Ul, cplx* h,
-                               double* red, int32_t* status) {
+// Ul = U[:, :l] (wide).  sig is scratch after the normalization.
+__device__ void jacobi_outputs(cplx* X, double* sig, const int* perm, int nb, int l, double negl,
+                               bool tall, cplx* core, cplx* Ul, cplx* h, double* red,
+                               int32_t* status) {
   const int tid = threadIdx.x;
   int t0 = l;
   for (int r = 0; r < l; ++r) {
     const double sv = sig[perm[r]];
     if (!(sv * sv > negl)) { t0 = r; break; }
   }
+  const double s_first = sig[perm[0]], s_last = sig[perm[l - 1]];
   for (int64_t e = tid; e < (int64_t)t0 * nb; e += blockDim.x) {
     const int r = (int)(e / nb), i = (int)(e % nb);
     const int c = perm[r];
     X[(int64_t)c * nb + i] = cscale(X[(int64_t)c * nb + i], 1.0 / sig[c]);
   }
   __syncthreads();
-  if (t0 < l) complete_columns(X, perm, nb, t0, l, h, red);
+  if (t0 < l) complete_columns(X, perm, nb, t0, l, h, red, sig);
   bool fin = true;
   for (int64_t e = tid; e < (int64_t)l * nb; e += blockDim.x) {
     const int r = (int)(e / nb), i = (int)(e % nb);
@@ -198,7 +211,7 @@ __device__ void jacobi_outputs(cplx* X, const double* sig, const int* perm, int 
     if (tall) core[e] = cconj(u);     // row r of U^H
     else Ul[e] = u;
   }
-  if (!fin) flag_out(status, tall ? 6 : 8, nb, l, sig[perm[0]], sig[perm[l - 1]]);
+  if (!fin) flag_out(status, tall ? 6 : 8, nb, l, s_first, s_last);
 }
 
 // One workgroup per instance; T (nb x nb, row-major) in Rin, X = T^H in LDS
