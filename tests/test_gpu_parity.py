@@ -106,6 +106,36 @@ def test_round_matches_oracle(q, ctx, eps, rmax):
             assert np.allclose(G, np.eye(G.shape[0]), atol=1e-12)
 
 
+@pytest.mark.parametrize("eps", [0.0, 1e-8])
+def test_round_mixed_orientation_and_subfloor_columns(q, ctx, eps):
+    # one batch whose right sweep meets wide SVD blocks (A^H = QR, then the
+    # second QR of R^H) and tall ones (A = QR), with ragged ranks, and an
+    # instance with a component 1e-100 below the Jacobi's rotation floor:
+    # those columns are never rotated, so at eps = 0 they are kept through an
+    # orthonormal completion (same ranks as the oracle, orthonormal cores),
+    # at eps > 0 they are truncated
+    modes = [3] + [2] * 9
+    xa = I.graded_tt(modes, [1, 3, 6, 12, 16, 16, 12, 6, 3, 2, 1], decay=0.5, seed=71)
+    xb = I.graded_tt(modes, [1, 3, 6, 12, 24, 12, 4, 8, 4, 2, 1], decay=0.5, seed=72)
+    a = I.random_tt(modes, [1, 2, 4, 4, 4, 4, 4, 4, 4, 2, 1], seed=73)
+    b = I.random_tt(modes, [1, 2, 3, 3, 3, 3, 3, 3, 3, 2, 1], seed=74)
+    xc = T.add(a, T.scale(b, 1e-100))
+    xs = [xa, xb, xc]
+    X = q.DeviceTT.from_cores(xs)
+    err, nrm = q.tt_round(ctx, X, eps, 0)
+    ctx.sync()
+    out = X.to_cores()
+    nrm = nrm.cpu().numpy()
+    for i in range(3):
+        ref, info = T.round_tt(xs[i], eps, None, return_info=True)
+        assert T.ranks(out[i]) == T.ranks(ref)
+        assert rel(T.full(out[i]), T.full(ref)) < 1e-10
+        assert abs(nrm[i] - info["norm"]) < 1e-13 * info["norm"]
+        for c in out[i][1:]:
+            G = T.right_gram(c)
+            assert np.allclose(G, np.eye(G.shape[0]), atol=1e-12)
+
+
 @pytest.mark.parametrize("eps", [0.0, 1e-9])
 def test_round_large_ranks_matches_oracle(q, ctx, eps):
     # bond ranks up to 100: the right sweep's SVD orders exceed the LDS Jacobi
