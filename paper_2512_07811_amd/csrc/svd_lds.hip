@@ -395,7 +395,25 @@ __global__ __launch_bounds__(1024) void k_jacobi_lds(
 // variant.
 constexpr int SG_NB = 1024;
 constexpr int SG_CH = 6;
+constexpr int SG_RPL = 8;            // register variant: orders up to 32 * SG_RPL = 256
 
+// Sum over a group of GL = 16 or 32 lanes (every lane of the group gets it).
+template <int GL>
+__device__ inline double group_sum(double v) {
+  v = row16_sum(v);
+  if (GL == 32) v += __shfl_xor(v, 16, 64);
+  return v;
+}
+template <int GL>
+__device__ inline cplx group_sum(cplx v) {
+  return make_double2(group_sum<GL>(v.x), group_sum<GL>(v.y));
+}
+
+// RPL = 0: 16-lane groups stream their pair's columns from X in chunks, once
+// for the dot products and once for the rotation.  RPL > 0 (orders up to
+// 32 RPL): 32-lane groups keep the pair's columns in registers between the
+// dot products and the rotation, one load and one store per element.
+template <int RPL>
 __global__ __launch_bounds__(1024) void k_jacobi_glb(
     Dim Md, Dim Cd, const cplx* __restrict__ Rin, int64_t sR, cplx* __restrict__ Xw, int64_t sX,
     cplx* __restrict__ Ul, int64_t sU, cplx* __restrict__ core, int64_t sCore, int32_t* l_out,
@@ -435,7 +453,8 @@ __global__ __launch_bounds__(1024) void k_jacobi_glb(
   const double negl = SL_NEGL * fro;
   const double jtol = SL_EPS * (double)nb, jtol2 = jtol * jtol;
   const int nbp = (nb + 1) & ~1;
-  const int g = tid & 15, grp = tid >> 4, ngrp = blockDim.x >> 4;
+  constexpr int GL = RPL > 0 ? 32 : 16;   // lanes per pair
+  const int g = tid % GL, grp = tid / GL, ngrp = blockDim.x / GL;
   bool converged = nb < 2;
   int sweeps_done = 0;
   // per lane over the current sweep: any rotation, largest gamma^2 / (alpha
@@ -449,7 +468,8 @@ __global__ __launch_bounds__(1024) void k_jacobi_glb(
     small2 = fro;
     for (int r = 0; r < nbp - 1; ++r) {
       for (int pi0 = 0; pi0 < nbp / 2; pi0 += ngrp) {
-        if (pi0 + 4 * wv >= nbp / 2) continue;   // wave-uniform: no pair for this wave
+        // wave-uniform: no pair for this wave
+        if (pi0 + (64 / GL) * wv >= nbp / 2) continue;
         const int pi = pi0 + grp;
         int p = 0, q = 0;
         bool valid = pi < nbp / 2;
@@ -469,7 +489,21 @@ __global__ __launch_bounds__(1024) void k_jacobi_glb(
         cplx* bq = Xw + (int64_t)q * nb;
         double al = 0.0, be = 0.0;
         cplx ga = make_double2(0.0, 0.0);
-        if (valid) {
+        cplx xr[RPL > 0 ? RPL : 1], yr[RPL > 0 ? RPL : 1];
+        if constexpr (RPL > 0) {
+#pragma unroll
+          for (int it = 0; it < RPL; ++it) {
+            const int i = g + GL * it;
+            xr[it] = (valid && i < nb) ? bp[i] : make_double2(0.0, 0.0);
+            yr[it] = (valid && i < nb) ? bq[i] : make_double2(0.0, 0.0);
+          }
+#pragma unroll
+          for (int it = 0; it < RPL; ++it) {
+            al += cabs2(xr[it]);
+            be += cabs2(yr[it]);
+            cfma(ga, cconj(xr[it]), yr[it]);
+          }
+        } else if (valid) {
           for (int i0 = g; i0 < nb; i0 += 16 * SG_CH) {
             cplx xs[SG_CH], ys[SG_CH];
 #pragma unroll
@@ -486,7 +520,7 @@ __global__ __launch_bounds__(1024) void k_jacobi_glb(
             }
           }
         }
-        al = row16_sum(al); be = row16_sum(be); ga = row16_sum(ga);
+        al = group_sum<GL>(al); be = group_sum<GL>(be); ga = group_sum<GL>(ga);
         const double g2 = cabs2(ga);
         const bool rot = valid && al > negl && be > negl && g2 > 0.0 && g2 > jtol2 * al * be;
         if (rot) {
@@ -498,6 +532,16 @@ __global__ __launch_bounds__(1024) void k_jacobi_glb(
           const double c = fast_rsq(fma(t, t, 1.0)), s = c * t;
           const cplx e = make_double2(ga.x * ig, ga.y * ig);
           const cplx se = cscale(e, s), sec = cscale(cconj(e), s);
+          if constexpr (RPL > 0) {
+#pragma unroll
+            for (int it = 0; it < RPL; ++it) {
+              const int i = g + GL * it;
+              if (i < nb) {
+                bp[i] = csub(cscale(xr[it], c), cmul(sec, yr[it]));
+                bq[i] = cadd(cmul(se, xr[it]), cscale(yr[it], c));
+              }
+            }
+          } else
           for (int i0 = g; i0 < nb; i0 += 16 * SG_CH) {
             cplx xs[SG_CH], ys[SG_CH];
 #pragma unroll
@@ -620,10 +664,14 @@ bool svd_trunc_fast(hipStream_t st, int batch, int mcap, int ccap, Dim m, Dim c,
     k_jacobi_lds<SL_NB_BIG><<<batch, 1024, 0, st>>>(m, c, Rw, sR, Uw, sQ, core, sCore, l_out,
                                                      l_stride, delta, disc2, lmax, max_sweeps,
                                                      status, svlog, svstride, counters);
+  else if (nbcap <= 32 * SG_RPL)
+    k_jacobi_glb<SG_RPL><<<batch, 1024, 0, st>>>(m, c, Rw, sR, Xw, sR, Uw, sQ, core, sCore, l_out,
+                                                 l_stride, delta, disc2, lmax, max_sweeps, status,
+                                                 svlog, svstride, counters);
   else
-    k_jacobi_glb<<<batch, 1024, 0, st>>>(m, c, Rw, sR, Xw, sR, Uw, sQ, core, sCore, l_out,
-                                         l_stride, delta, disc2, lmax, max_sweeps, status, svlog,
-                                         svstride, counters);
+    k_jacobi_glb<0><<<batch, 1024, 0, st>>>(m, c, Rw, sR, Xw, sR, Uw, sQ, core, sCore, l_out,
+                                            l_stride, delta, disc2, lmax, max_sweeps, status,
+                                            svlog, svstride, counters);
   // finishing products on the MFMA GEMM (each instance's sizes are zero in the
   // product of the orientation it does not have):
   //   core  = U[:, :l]^H Q^H  (l x nc)  for A^H = Q R;
