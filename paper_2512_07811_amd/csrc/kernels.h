@@ -58,6 +58,9 @@ bool qr_lds_fits(int mcap, int ncap);
 // formation on the MFMA GEMM) for unfoldings beyond one workgroup's LDS.
 // Same contract as qr (Q may be null: R and s_out only).  Mw is the m x n work
 // matrix (column-major, leading dimension mcap, stride sM >= mcap * ncap).
+// orient: factor A^H where an instance's A is wide, as qr_reg does (mcap and
+// ncap are then the capacities of the factored matrix, rows >= columns, and
+// ws.dims must hold batch x 3 ints).
 struct QrBlkWs {
   cplx* V;            // reflectors, mcap x (panels * 32) per instance
   int64_t v_stride;
@@ -69,6 +72,7 @@ struct QrBlkWs {
   double* tau;        // panels * 32 per instance
   int64_t tau_stride;
   int32_t* s_dev;     // batch
+  int32_t* dims;      // batch x 3, for oriented factorizations (may be null otherwise)
 };
 bool qr_blocked_wanted(int mcap, int ncap);
 // element counts per instance of V, T and one W buffer; returns V + T + 2 W
@@ -76,7 +80,7 @@ size_t qr_blocked_ws_elems(int mcap, int ncap, int64_t* v_elems, int64_t* t_elem
                            int64_t* w_elems);
 void qr_blocked(hipStream_t st, int batch, int mcap, int ncap, Dim m, Dim n, const cplx* A,
                 int64_t sA, cplx* Mw, int64_t sM, const QrBlkWs& ws, cplx* Q, int64_t sQ,
-                cplx* R, int64_t sR, int32_t* s_out, int s_stride);
+                cplx* R, int64_t sR, int32_t* s_out, int s_stride, bool orient = false);
 
 // Truncated SVD of the packed m x c matrix A by one-sided (Hestenes) Jacobi:
 // keeps the smallest l >= 1 whose discarded tail does not exceed delta[b],
@@ -88,10 +92,12 @@ void qr_blocked(hipStream_t st, int batch, int mcap, int ncap, Dim m, Dim n, con
 // rotations: the matrix in LDS up to order 100, in global memory (Xw) up to
 // 1024; core and carry = A core^H finished by the MFMA GEMM; returns false
 // above order 1024.  Scratch: Qw, Uw (max x min, stride sQ), Rw, Xw (min^2,
-// stride sR), tau (stride sT >= min + 4).  A must not alias core.
+// stride sR), tau (stride sT >= min + 4); qb (may be null): blocked-QR
+// workspace for blocks where qr_blocked_wanted(max, min), whose QRs then run
+// blocked.  A must not alias core.
 bool svd_trunc_fast(hipStream_t st, int batch, int mcap, int ccap, Dim m, Dim c, const cplx* A,
                     int64_t sA, cplx* Qw, cplx* Uw, int64_t sQ, cplx* Rw, cplx* Xw, int64_t sR,
-                    double* tau, int64_t sT, cplx* core, int64_t sCore, cplx* carry,
+                    double* tau, int64_t sT, const QrBlkWs* qb, cplx* core, int64_t sCore, cplx* carry,
                     int64_t sCarry, int32_t* l_out, int l_stride, const double* delta,
                     double* disc2, int lmax, int max_sweeps, int32_t* status, double* svlog,
                     int64_t svstride, unsigned long long* counters);

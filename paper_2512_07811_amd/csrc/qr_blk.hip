@@ -36,7 +36,10 @@ __device__ inline double qb_block_sum(double v, double* sh) {
 }
 
 // M (column-major, ld) <- A (row-major m x n); s_dev[b] = min(m, n).
+// trans (may be null; stride 3 per instance): factor B = A^H for that
+// instance, whose column c is row c of A, conjugated.
 __global__ __launch_bounds__(256) void k_qrb_load(int tiles_r, int tiles_c, Dim Md, Dim Nd,
+                                                  const int32_t* trans,
                                                   const cplx* __restrict__ A, int64_t sA,
                                                   cplx* __restrict__ M, int64_t sM, int ld,
                                                   int32_t* s_dev) {
@@ -45,11 +48,19 @@ __global__ __launch_bounds__(256) void k_qrb_load(int tiles_r, int tiles_c, Dim 
   const int m = dimv(Md, b), n = dimv(Nd, b);
   if (t == 0 && threadIdx.x == 0) s_dev[b] = min(m, n);
   const int r0 = (t / tiles_c) * QB_TILE, c0 = (t % tiles_c) * QB_TILE;
-  if (r0 >= m || c0 >= n) return;
-  __shared__ cplx tile[QB_TILE][QB_TILE + 1];
   A += b * sA;
   M += b * sM;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  if (trans && trans[(int64_t)b * 3 + 2]) {   // B (n x m) = A^H, no transpose through LDS
+    if (r0 >= n || c0 >= m) return;
+    for (int c = ty; c < QB_TILE; c += 8) {
+      const int cc = c0 + c, i = r0 + tx;
+      if (cc < m && i < n) M[(int64_t)cc * ld + i] = cconj(A[(int64_t)cc * n + i]);
+    }
+    return;
+  }
+  if (r0 >= m || c0 >= n) return;
+  __shared__ cplx tile[QB_TILE][QB_TILE + 1];
   for (int r = ty; r < QB_TILE; r += 8) {
     const int i = r0 + r, c = c0 + tx;
     tile[r][tx] = (i < m && c < n) ? A[(int64_t)i * n + c] : czero();
@@ -285,9 +296,24 @@ bool qr_blocked_wanted(int mcap, int ncap) {
          std::min(mcap, ncap) >= 8 * QB_NB;
 }
 
-void qr_blocked(hipStream_t st, int batch, int mcap, int ncap, Dim m, Dim n, const cplx* A,
+// Sizes of the factored matrix per instance when oriented: rows max(m, n),
+// columns min(m, n), and whether it is A^H.
+__global__ void k_qrb_dims(int batch, Dim Md, Dim Nd, int32_t* dims) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= batch) return;
+  const int m = dimv(Md, b), n = dimv(Nd, b);
+  dims[(int64_t)b * 3 + 0] = max(m, n);
+  dims[(int64_t)b * 3 + 1] = min(m, n);
+  dims[(int64_t)b * 3 + 2] = m < n ? 1 : 0;
+}
+
+void qr_blocked(hipStream_t st, int batch, int mcap, int ncap, Dim m0, Dim n0, const cplx* A,
                 int64_t sA, cplx* Mw, int64_t sM, const QrBlkWs& ws, cplx* Q, int64_t sQ,
-                cplx* R, int64_t sR, int32_t* s_out, int s_stride) {
+                cplx* R, int64_t sR, int32_t* s_out, int s_stride, bool orient) {
+  // oriented: mcap, ncap are the capacities of the factored matrix (rows
+  // >= columns) and m, n below its sizes per instance
+  if (orient) k_qrb_dims<<<(batch + 127) / 128, 128, 0, st>>>(batch, m0, n0, ws.dims);
+  const Dim m = orient ? dref(ws.dims, 3) : m0, n = orient ? dref(ws.dims + 1, 3) : n0;
   // live timing: the QR class covers this file's kernels; the products time
   // themselves as the GEMM class (regions do not nest)
   const bool prof = prof_on(PROF_QR);
@@ -304,7 +330,8 @@ void qr_blocked(hipStream_t st, int batch, int mcap, int ncap, Dim m, Dim n, con
   {
     const int tr = (mcap + QB_TILE - 1) / QB_TILE, tc = (ncap + QB_TILE - 1) / QB_TILE;
     pb();
-    k_qrb_load<<<batch * tr * tc, 256, 0, st>>>(tr, tc, m, n, A, sA, Mw, sM, ld, ws.s_dev);
+    k_qrb_load<<<batch * tr * tc, 256, 0, st>>>(tr, tc, m0, n0, orient ? ws.dims : nullptr, A,
+                                                sA, Mw, sM, ld, ws.s_dev);
     pe();
   }
   const Dim sd = dref(ws.s_dev, 1);

@@ -9,6 +9,7 @@ struct RoundWs {
   int64_t slot = 1, rr = 1, vv = 1, carry = 1, tau = 1, max_nb = 0;
   // blocked left-sweep QR (elements per instance; 0 when no core needs it)
   int64_t qb_v = 0, qb_t = 0, qb_w = 0, qb_tau = 0;
+  int64_t sb_v = 0, sb_t = 0, sb_w = 0, sb_tau = 0;   // blocked QRs of the SVD blocks
   size_t bytes = 0;
   size_t sweep_bytes = 0;   // extra for the fast SVD (reflectors, R V, tau, sigma)
 };

@@ -33,6 +33,15 @@ RoundWs round_ws_layout(const qt_tt* x, int lmax_cap) {
     carry = std::max<int64_t>(carry, (int64_t)x->cap[k] * std::min(x->cap[k], lmax_cap));
     tau = std::max<int64_t>(tau, x->cap[k + 1]);
     w.max_nb = std::max<int64_t>(w.max_nb, nb);
+    const int64_t mbk = std::max<int64_t>(x->cap[k], (int64_t)x->modes[k] * lnext);
+    if (k >= 1 && nb <= 1024 && qr_blocked_wanted((int)mbk, (int)nb)) {
+      int64_t v, t, wq;
+      qr_blocked_ws_elems((int)mbk, (int)nb, &v, &t, &wq);
+      w.sb_v = std::max(w.sb_v, v);
+      w.sb_t = std::max(w.sb_t, t);
+      w.sb_w = std::max(w.sb_w, wq);
+      w.sb_tau = std::max(w.sb_tau, t / 32);
+    }
     if (k < n - 1 && qr_blocked_wanted(x->cap[k] * x->modes[k], x->cap[k + 1])) {
       int64_t v, t, wq;
       qr_blocked_ws_elems(x->cap[k] * x->modes[k], x->cap[k + 1], &v, &t, &wq);
@@ -48,6 +57,9 @@ RoundWs round_ws_layout(const qt_tt* x, int lmax_cap) {
   // tau: nb reflector scalars, then 8 sizes of the SVD's second QR and
   // finishing products (4 doubles)
   w.sweep_bytes = sizeof(cplx) * B * (slot + vv) + sizeof(double) * B * (w.max_nb + 4) + 3 * 256;
+  if (w.sb_v > 0)
+    w.sweep_bytes += sizeof(cplx) * B * (w.sb_v + w.sb_t + 2 * w.sb_w) +
+                     sizeof(double) * B * w.sb_tau + sizeof(int32_t) * B * 4 + 7 * 256;
   w.bytes = sizeof(cplx) * B * (3 * slot + rr + vv + carry) + sizeof(double) * B * (tau + 4) +
             sizeof(int32_t) * B * (n + 1) + 16 * 256 + w.sweep_bytes;
   if (w.qb_v > 0)
@@ -160,6 +172,23 @@ qt_status take_sweep_extra(qt_ctx ctx, int B, const RoundWs& w, SweepBufs& buf) 
   buf.nbmax = w.max_nb + 4;
   buf.tau = (double*)ws_take(ctx, sizeof(double) * B * buf.nbmax);
   QT_CHECK(buf.U && buf.RV && buf.tau, QT_ENOMEM, "rounding: sweep workspace too small");
+  buf.qb = QrBlkWs{};
+  if (w.sb_v > 0) {
+    QrBlkWs& q = buf.qb;
+    q.V = (cplx*)ws_take(ctx, sizeof(cplx) * B * w.sb_v);
+    q.v_stride = w.sb_v;
+    q.T = (cplx*)ws_take(ctx, sizeof(cplx) * B * w.sb_t);
+    q.t_stride = w.sb_t;
+    q.W1 = (cplx*)ws_take(ctx, sizeof(cplx) * B * w.sb_w);
+    q.W2 = (cplx*)ws_take(ctx, sizeof(cplx) * B * w.sb_w);
+    q.w_stride = w.sb_w;
+    q.tau = (double*)ws_take(ctx, sizeof(double) * B * w.sb_tau);
+    q.tau_stride = w.sb_tau;
+    q.s_dev = (int32_t*)ws_take(ctx, sizeof(int32_t) * B);
+    q.dims = (int32_t*)ws_take(ctx, sizeof(int32_t) * B * 3);
+    QT_CHECK(q.V && q.T && q.W1 && q.W2 && q.tau && q.s_dev && q.dims, QT_ENOMEM,
+             "rounding: blocked QR workspace of the SVD too small");
+  }
   return QT_OK;
 }
 
@@ -200,7 +229,8 @@ qt_status right_sweep_impl(qt_ctx ctx, qt_tt* x, const int32_t* rkl, const cplx*
     const int nsw = std::min(mcap, ccap) > 100 ? sweeps_glb : sweeps;
     const bool ok = svd_trunc_fast(st, B, mcap, ccap, dref(rkl + k, rs), dref(rk + k + 1, rs, p),
                                    in, sin, buf.Bsv, buf.U, buf.slot, buf.V, buf.RV, buf.vv,
-                                   buf.tau, buf.nbmax, X + x->offsets[k], sX, buf.C,
+                                   buf.tau, buf.nbmax, buf.qb.V ? &buf.qb : nullptr,
+                                   X + x->offsets[k], sX, buf.C,
                                    buf.carry, rk + k, rs, delta, disc2, lmax, nsw, ctx->status,
                                    svk, svi, ctx->counters);
     QT_CHECK(ok, QT_ECAPACITY, "rounding: SVD block above 1024 columns");

@@ -49,6 +49,7 @@ struct SweepBufs {
   cplx* RV;    // Jacobi matrix of orders above 100 (vv)
   double* tau; // nbmax entries: reflector scalars, then 4 for the SVD's sizes
   int64_t nbmax;
+  QrBlkWs qb;  // blocked QRs of large SVD blocks (V null when none)
 };
 qt_status take_sweep_extra(qt_ctx ctx, int B, const RoundWs& w, SweepBufs& buf);
 qt_status right_sweep_impl(qt_ctx ctx, qt_tt* x, const int32_t* rkl, const cplx* center,

@@ -635,14 +635,21 @@ __global__ void k_qr2_prep(Dim Md, Dim Cd, const cplx* __restrict__ R, int64_t s
 
 bool svd_trunc_fast(hipStream_t st, int batch, int mcap, int ccap, Dim m, Dim c, const cplx* A,
                     int64_t sA, cplx* Qw, cplx* Uw, int64_t sQ, cplx* Rw, cplx* Xw, int64_t sR,
-                    double* tau, int64_t sT, cplx* core, int64_t sCore, cplx* carry,
-                    int64_t sCarry, int32_t* l_out, int l_stride, const double* delta,
-                    double* disc2, int lmax, int max_sweeps, int32_t* status, double* svlog,
-                    int64_t svstride, unsigned long long* counters) {
+                    double* tau, int64_t sT, const QrBlkWs* qb, cplx* core, int64_t sCore,
+                    cplx* carry, int64_t sCarry, int32_t* l_out, int l_stride,
+                    const double* delta, double* disc2, int lmax, int max_sweeps,
+                    int32_t* status, double* svlog, int64_t svstride,
+                    unsigned long long* counters) {
   const int mbcap = std::max(mcap, ccap), nbcap = std::min(mcap, ccap);
   if (nbcap > SG_NB) return false;
-  if (!qr_reg(st, batch, mbcap, nbcap, m, c, A, sA, Uw, sQ, tau, sT, Qw, sQ, Rw, sR, nullptr, 0,
-              true))
+  // blocks beyond one workgroup's LDS with >= 256 columns: panel + GEMM QRs
+  // (work matrix in the QR scratch Uw)
+  const bool blocked = qb && qr_blocked_wanted(mbcap, nbcap);
+  if (blocked)
+    qr_blocked(st, batch, mbcap, nbcap, m, c, A, sA, Uw, sQ, *qb, Qw, sQ, Rw, sR, nullptr, 0,
+               true);
+  else if (!qr_reg(st, batch, mbcap, nbcap, m, c, A, sA, Uw, sQ, tau, sT, Qw, sQ, Rw, sR,
+                   nullptr, 0, true))
     qr_mem(st, batch, mbcap, nbcap, m, c, A, sA, Uw, sQ, tau, sT, Qw, sQ, Rw, sR, nullptr, 0, true);
   // per-instance sizes in the last 4 doubles of each tau slice (the QRs use
   // the first nb <= sT - 4)
@@ -651,8 +658,11 @@ bool svd_trunc_fast(hipStream_t st, int batch, int mcap, int ccap, Dim m, Dim c,
   // wide instances: R2 of the second QR (R^H = Q2 R2) over R, Q2 not formed
   k_qr2_prep<<<batch, 256, 0, st>>>(m, c, Rw, sR, Xw, sR, fd, ds);
   const Dim d2 = dref(fd + 6, ds);
-  if (!qr_reg(st, batch, nbcap, nbcap, d2, d2, Xw, sR, Uw, sQ, tau, sT, nullptr, 0, Rw, sR,
-              nullptr, 0, false))
+  if (blocked && qr_blocked_wanted(nbcap, nbcap))
+    qr_blocked(st, batch, nbcap, nbcap, d2, d2, Xw, sR, Uw, sQ, *qb, nullptr, 0, Rw, sR, nullptr,
+               0, false);
+  else if (!qr_reg(st, batch, nbcap, nbcap, d2, d2, Xw, sR, Uw, sQ, tau, sT, nullptr, 0, Rw, sR,
+                   nullptr, 0, false))
     qr_mem(st, batch, nbcap, nbcap, d2, d2, Xw, sR, Uw, sQ, tau, sT, nullptr, 0, Rw, sR, nullptr,
            0, false);
   // U[:, :l] of wide instances into the QR scratch Uw (free after the QRs)
