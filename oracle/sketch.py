@@ -85,11 +85,15 @@ def truncate_right(cores, delta, rmax=None):
     return cores, {"disc": disc, "ranks": kept, "svals": svals}
 
 
+NOISE_FLOOR = 1e-14
+
+
 def sketch_round(x, omega, eps, rmax=None, xnorm=None):
     """RTO followed by SVD truncation with the remaining error budget.
 
     sketch error e_s^2 = ||x||^2 - ||x~||^2 (exact for the projection); the
-    truncation threshold per bond is sqrt((eps^2 ||x||^2 - e_s^2)/(n-1)).
+    truncation threshold per bond is sqrt((eps^2 ||x||^2 - e_s^2)/(n-1)), and
+    at least NOISE_FLOOR ||x|| when eps > 0.
     Returns (cores, info) with info['ok'] = (e_s <= eps ||x||).
     """
     n = len(x)
@@ -101,6 +105,10 @@ def sketch_round(x, omega, eps, rmax=None, xnorm=None):
     budget = eps ** 2 * xnorm ** 2 - es2
     ok = budget >= 0.0
     delta = math.sqrt(max(budget, 0.0) / (n - 1)) if n > 1 else 0.0
+    if eps > 0.0 and n > 1:
+        # noise floor: for eps > 0 no direction below 1e-14 ||x|| is kept, also
+        # when the sketch error alone exceeds the budget
+        delta = max(delta, NOISE_FLOOR * xnorm)
     z, info = truncate_right(y, delta, rmax)
     info.update({"sketch_err": math.sqrt(es2), "xnorm": xnorm, "ynorm": ynorm, "ok": ok,
                  "delta": delta})

@@ -12,6 +12,10 @@
 namespace qt {
 
 // delta[b] = sqrt(max(eps^2 ||x||^2 - e_s^2, 0)/(n-1)); e_s^2 = max(||x||^2 - ||x~||^2, 0)
+// Relative floor of the truncation threshold for eps > 0: singular values of
+// rounding noise (about 1e-16 of the norm each) never survive a truncation.
+constexpr double QT_NOISE_FLOOR = 1e-14;
+
 __global__ void k_budget(int batch, int nbonds, double eps, const double* xn2, const double* yn2,
                          double* delta, double* disc2, double* es2, int32_t* fail,
                          unsigned long long* counters) {
@@ -19,7 +23,11 @@ __global__ void k_budget(int batch, int nbonds, double eps, const double* xn2, c
   if (b >= batch) return;
   double e2 = fmax(xn2[b] - yn2[b], 0.0);
   double bud = eps * eps * xn2[b] - e2;
-  delta[b] = nbonds > 0 ? sqrt(fmax(bud, 0.0) / nbonds) : 0.0;
+  double dl = nbonds > 0 ? sqrt(fmax(bud, 0.0) / nbonds) : 0.0;
+  // eps > 0: no bond keeps directions below the rounding-noise floor, also
+  // when the projection alone exhausts the budget (the rank cap binds)
+  if (eps > 0.0 && nbonds > 0) dl = fmax(dl, QT_NOISE_FLOOR * sqrt(xn2[b]));
+  delta[b] = dl;
   disc2[b] = 0.0;
   es2[b] = e2;
   if (fail) fail[b] = bud < 0.0 ? 1 : 0;

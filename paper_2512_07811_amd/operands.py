@@ -183,6 +183,91 @@ def green_tt(L, k0, eps=1e-10):
     return [ctrl.astype(np.complex128)] + [c.astype(np.complex128) for c in cores[1:]]
 
 
+def _inv_expsum(smax, tol):
+    """Exponents t_m and weights w_m with 1/s ~ sum_m w_m exp(-t_m s) on [1, smax]
+    to relative error below tol: the trapezoidal rule on 1/s = int exp(-s e^u + u) du,
+    step pi^2 / (2 log(4/tol)) from the width of the strip where the integrand is
+    analytic, range cut where each tail falls below tol."""
+    h = math.pi ** 2 / (2.0 * math.log(4.0 / tol))
+    u = np.arange(math.log(tol / smax) - 1.0, math.log(math.log(4.0 / tol) + 2.0) + h, h)
+    return np.exp(u), h * np.exp(u)
+
+
+def _split_modes(cores, split, eps):
+    """Rounding of a train in which core k (mode 2**split[k], or any mode when
+    split[k] == 0) becomes split[k] cores of mode 2, most significant bit first;
+    every discarded tail is within eps * ||x|| / sqrt(number of bonds)."""
+    cs = [np.array(c) for c in cores]
+    n = len(cs)
+    for k in range(n - 1, 0, -1):
+        r, p, r2 = cs[k].shape
+        Q, R = np.linalg.qr(cs[k].reshape(r, p * r2).T)
+        cs[k] = Q.T.reshape(Q.shape[1], p, r2)
+        cs[k - 1] = np.tensordot(cs[k - 1], R.T, axes=(2, 0))
+    bonds = sum(max(m, 1) for m in split) - 1
+    delta = eps * np.linalg.norm(cs[0]) / math.sqrt(max(bonds, 1))
+    out = []
+    for k in range(n):
+        r, p, r2 = cs[k].shape
+        pm = [2] * split[k] if split[k] > 0 else [p]
+        rest = cs[k].reshape(r, -1)
+        for j, q in enumerate(pm):
+            rows = rest.reshape(r * q, -1)
+            if k == n - 1 and j == len(pm) - 1:
+                out.append(rows.reshape(r, q, r2))
+                break
+            U, sv, Vt = _svd_wide(rows)
+            l = _keep(sv, delta)
+            out.append(U[:, :l].reshape(r, q, l))
+            rest = sv[:l, None] * Vt[:l]
+            r = l
+        if k < n - 1:
+            cs[k + 1] = np.tensordot(rest, cs[k + 1], axes=(1, 0))
+    return out
+
+
+def green_tt_expsum(L, k0, eps=1e-10):
+    """The operator of green_tt without its dense 9 N^3 array (grids beyond 256^3).
+
+    Gamma_ab(q) = q_a q_b / (k0 |q|^2) with 1/|q|^2 as an exponential sum, so
+    that every term is a product of one function per axis (the momentum order
+    of green_momentum_dense).  Gamma(0) = 0 through the factor q_a q_b, and a
+    Nyquist frequency on any axis zeroes every term through a per-axis
+    indicator.  Each component's sum is compressed at the level of the three
+    axis groups, the nine components are stacked behind the component core,
+    and the axis cores are split into their L bits."""
+    N = 2 ** L
+    f = signed_freq(N)[bit_reversal(L)]
+    keep = (f != -N // 2).astype(np.float64)
+    t, w = _inv_expsum(3.0 * (N // 2) ** 2, eps * 1e-3)
+    E = np.exp(-np.outer(f * f, t)) * keep[:, None]
+    P = [E, E * f[:, None], E * (f * f)[:, None]]        # q_d^0, q_d^1, q_d^2 in each term
+    M = len(t)
+    comps = []
+    for a in range(3):
+        for b in range(3):
+            pw = [(a == d) + (b == d) for d in range(3)]
+            X = (P[pw[0]] * (w / k0)[None, :])[None, :, :]
+            Y = np.zeros((M, N, M))
+            Y[np.arange(M), :, np.arange(M)] = P[pw[1]].T
+            Z = P[pw[2]].T[:, :, None]
+            comps.append(compress([X, Y, Z], eps * 1e-3))
+    R1 = np.cumsum([0] + [c[0].shape[2] for c in comps])
+    R2 = np.cumsum([0] + [c[1].shape[2] for c in comps])
+    ctrl = np.eye(9).reshape(1, 9, 9)
+    X = np.zeros((9, N, R1[-1]))
+    Y = np.zeros((R1[-1], N, R2[-1]))
+    Z = np.zeros((R2[-1], N, 1))
+    for c, (cx, cy, cz) in enumerate(comps):
+        X[c, :, R1[c]:R1[c + 1]] = cx[0]
+        Y[R1[c]:R1[c + 1], :, R2[c]:R2[c + 1]] = cy
+        Z[R2[c]:R2[c + 1]] = cz
+    big = compress([ctrl, X, Y, Z], eps * 1e-2)
+    cores = compress(_split_modes(big, [0, L, L, L], eps * 1e-1), eps)
+    ctl = cores[0].reshape(1, 3, 3, cores[0].shape[2])
+    return [ctl.astype(np.complex128)] + [c.astype(np.complex128) for c in cores[1:]]
+
+
 # ------------------------------------------------------- material, loads
 
 def material_tt(kvox, shift=0.0, eps=1e-10):
@@ -244,7 +329,9 @@ def build_problem(kvox=None, k0=None, L=None, section=None, op_eps=1e-10, sfft_e
         S, Sinv, G = shared["S"], shared["Sinv"], shared["G"]
     else:
         S, Sinv = sfft_3d(L, sfft_eps)
-        G = green_tt(L, k0, op_eps)
+        # the dense Green array has 9 N^3 entries: beyond 256^3 the
+        # exponential-sum build (same operator, same ranks)
+        G = green_tt(L, k0, op_eps) if L <= 8 else green_tt_expsum(L, k0, op_eps)
     return {"L": L, "k0": float(k0), "kp": kp, "k2": k2, "k_sel": ksel, "S": S, "Sinv": Sinv,
             "G": G}
 

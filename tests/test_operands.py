@@ -30,6 +30,23 @@ def test_green_tt_matches_oracle_definition():
     assert np.max(np.abs(diag.reshape(3, 3, N, N, N) - Gref)) < 1e-11
 
 
+@pytest.mark.parametrize("L", [3, 4, 5])
+def test_green_expsum_matches_oracle_definition(L):
+    # the exponential-sum build (grids beyond 256^3) against the oracle's dense
+    # Green array: same operator to the build tolerance, Gamma(0) = 0 and the
+    # Nyquist planes zero, same ranks as the dense TT-SVD
+    G = P.green_tt_expsum(L, 3.5, 1e-10)
+    ctrl = G[0].reshape(9, -1)
+    x = ctrl
+    for c in G[1:]:
+        r, p, r2 = c.shape
+        x = (x @ c.reshape(r, p * r2)).reshape(-1, r2)
+    ref = O.green_momentum(L, 3.5)
+    got = x.reshape(ref.shape)
+    assert np.max(np.abs(got - ref)) <= 1e-9 * np.max(np.abs(ref))
+    assert [c.shape[-1] for c in G] == [c.shape[-1] for c in P.green_tt(L, 3.5, 1e-10)]
+
+
 def test_material_tt_bits_and_z_invariance():
     L = 4
     sec = I.cylinders_section(L, seed=3, count=2, r_min=2, r_max=3, k_in=5.0)

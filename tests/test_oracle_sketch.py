@@ -75,3 +75,20 @@ def test_sketch_round_meets_tolerance_with_oversampling(eps):
     _, ref = T.round_tt(x, eps, return_info=True)
     for k in range(1, len(m)):
         assert abs(info["ranks"][k] - ref["ranks"][k]) <= 1
+
+
+def test_sketch_round_noise_floor_when_over_budget():
+    # bond 3's sketch width (3) is below its rank (4), so at eps = 1e-12 the
+    # projection alone exhausts the budget; bond 4's width (6) exceeds its
+    # rank (2): the floor 1e-14 ||x|| keeps that bond at its rank, where a
+    # zero threshold keeps the sketch's noise directions as well
+    modes = [2] * 6
+    x = I.random_tt(modes, [1, 2, 4, 8, 2, 2, 1], seed=5)
+    om = I.gaussian_sketch(modes, [1, 2, 4, 3, 6, 2, 1], seed=6)
+    z, info = SK.sketch_round(x, om, 1e-12)
+    assert not info["ok"]
+    assert info["delta"] == pytest.approx(SK.NOISE_FLOOR * info["xnorm"], rel=1e-12)
+    assert T.ranks(z)[4] == 2
+    z0, info0 = SK.truncate_right(SK.rto(x, om), 0.0)
+    assert T.ranks(z0)[4] > 2
+    assert np.linalg.norm(T.full(z) - T.full(z0)) <= 1e-13 * info["xnorm"]
