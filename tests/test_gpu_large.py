@@ -1,0 +1,59 @@
+"""Full-size check of the 1024^3 fibre cell (16 z-parallel cylinders, 31 cores,
+field rank cap 128), in the launch configuration of `bench.py --config cyl1024`
+(product-aware rounding, oversample 4): the first iterate from E against the
+dense Moulinec-Suquet iterate of the exact 2D reduction of this z-invariant
+cell (oracle), lifted to 3D as a train with all-ones z cores.  The cap binds
+hard here (the exact iterate's best rank-128 train is 4 % off), so the bound
+is a small multiple of that best-approximation error: a wrong operator, bit
+order or Green build is off by O(1)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import ms
+from oracle import tt as T
+from paper_2512_07811_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def test_cylinders_1024_first_iterate_matches_dense_2d_reduction():
+    from paper_2512_07811_amd import operands as P
+    from paper_2512_07811_amd import qtt as q
+    L, k0, rmax = 10, 25.5, 128
+    sec = I.cylinders_section(L, 4)
+    prob = P.build_problem(section=sec, k0=k0)
+    ctx = q.Context(0)
+    try:
+        ops, e = P.upload(prob, [[1.0, 0.0, 0.0]], rmax)
+        e = q.DeviceTT.from_cores([P.mean_field(np.array([1.0, 0.0, 0.0]), L)], e.cap)
+        opts = q.solve_opts(1e-6, rmax, mode=q.ROUND_SKETCH, oversample=4, seed=17)
+        q.ls_iterate(ctx, ops, e, opts, 1)
+        ctx.sync()
+        assert max(e.rank_array()[0]) <= rmax
+        # exact first iterate on the 1024^2 section, components (x, y, z = 0)
+        e0 = np.zeros((2,) + sec.shape)
+        e0[0] = 1.0
+        e1 = ms.ms_step(e0, sec, k0, [1.0, 0.0])
+        comp = np.stack([e1[0], e1[1], np.zeros_like(e1[0])])
+        ref = T.tt_svd(comp.reshape(-1), [3] + [2] * (2 * L), 1e-13)
+        ref = [c.astype(np.complex128) for c in ref] + \
+              [np.ones((1, 2, 1), dtype=np.complex128) for _ in range(L)]
+        _, best = T.round_tt(ref, 0.0, rmax, return_info=True)
+        R = q.DeviceTT.from_cores([ref])
+        aa = q.tt_dot(ctx, e, e).cpu().numpy()[0].real
+        bb = q.tt_dot(ctx, R, R).cpu().numpy()[0].real
+        ab = q.tt_dot(ctx, e, R).cpu().numpy()[0]
+        ctx.sync()
+        nrm = math.sqrt(bb)
+        assert abs(nrm - best["norm"]) <= 1e-10 * nrm
+        dist = math.sqrt(max(aa + bb - 2.0 * ab.real, 0.0)) / nrm
+        print(f"1024^3 first iterate: distance {dist:.4f}, best rank-{rmax} error {best['err']:.4f}")
+        assert dist <= 4.0 * best["err"]
+        # the mean of the iterate is E (Gamma(0) = 0) up to the rounding
+        M = q.DeviceTT.from_cores([P.mean_field(np.array([1.0, 0.0, 0.0]), L)])
+        mean_x = q.tt_dot(ctx, M, e).cpu().numpy()[0].real / 2.0 ** (3 * L)
+        assert abs(mean_x - 1.0) <= 4.0 * best["err"]
+    finally:
+        ctx.close()
