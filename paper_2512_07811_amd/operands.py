@@ -226,7 +226,7 @@ def _split_modes(cores, split, eps):
     return out
 
 
-def green_tt_expsum(L, k0, eps=1e-10):
+def green_tt_expsum(L, k0, eps=1e-10, log=None):
     """The operator of green_tt without its dense 9 N^3 array (grids beyond 256^3).
 
     Gamma_ab(q) = q_a q_b / (k0 |q|^2) with 1/|q|^2 as an exponential sum, so
@@ -252,6 +252,8 @@ def green_tt_expsum(L, k0, eps=1e-10):
             Y[np.arange(M), :, np.arange(M)] = P[pw[1]].T
             Z = P[pw[2]].T[:, :, None]
             comps.append(compress([X, Y, Z], eps * 1e-3))
+            if log:
+                log(f"Green component {3 * a + b + 1}/9")
     R1 = np.cumsum([0] + [c[0].shape[2] for c in comps])
     R2 = np.cumsum([0] + [c[1].shape[2] for c in comps])
     ctrl = np.eye(9).reshape(1, 9, 9)
@@ -263,6 +265,8 @@ def green_tt_expsum(L, k0, eps=1e-10):
         Y[R1[c]:R1[c + 1], :, R2[c]:R2[c + 1]] = cy
         Z[R2[c]:R2[c + 1]] = cz
     big = compress([ctrl, X, Y, Z], eps * 1e-2)
+    if log:
+        log("Green axis-group train")
     cores = compress(_split_modes(big, [0, L, L, L], eps * 1e-1), eps)
     ctl = cores[0].reshape(1, 3, 3, cores[0].shape[2])
     return [ctl.astype(np.complex128)] + [c.astype(np.complex128) for c in cores[1:]]
@@ -285,6 +289,22 @@ def material_tt_z_invariant(section, shift=0.0, eps=1e-10):
     return sp + [np.ones((1, 2, 1)) for _ in range(L)]
 
 
+def material_tt_periodic(cell, L, shift=0.0, eps=1e-10):
+    """Spatial train of (k - shift) on a 2^L grid tiled by a periodic cell of
+    side 2^pL: k depends on the low pL bits of each axis only, so each axis
+    group is L - pL free top bits (identity on the bond, mode 2) followed by
+    the cell's own cores for that axis."""
+    M = cell.shape[0]
+    pL = int(round(math.log2(M)))
+    sp = ttsvd(np.asarray(cell, dtype=np.float64) - shift, [2] * (3 * pL), eps)
+    out = []
+    for d in range(3):
+        r = sp[d * pL].shape[0]
+        free = np.repeat(np.eye(r)[:, None, :], 2, axis=1)
+        out += [free.copy() for _ in range(L - pL)] + sp[d * pL:(d + 1) * pL]
+    return out
+
+
 def with_component_core(spatial, control):
     """Prepend a (1, 3, 1) component core to a spatial train (complex cores)."""
     return [np.asarray(control, dtype=np.complex128).reshape(1, 3, 1)] + \
@@ -305,22 +325,32 @@ def mean_field(E, L):
 
 
 def build_problem(kvox=None, k0=None, L=None, section=None, op_eps=1e-10, sfft_eps=1e-13,
-                  shared=None):
-    """All host trains of one cell problem (k given as N^3 voxels or a z-invariant section).
+                  shared=None, cell=None, log=None):
+    """All host trains of one cell problem (k given as N^3 voxels, a z-invariant
+    section, or a periodic cell tiling a 2^L grid).
 
     shared: the "S", "Sinv" and "G" entries of an earlier problem with the same L and
-    k0, reused instead of rebuilt (they do not depend on the microstructure)."""
+    k0, reused instead of rebuilt (they do not depend on the microstructure).
+    log: optional callable taking a progress message."""
+    say = log or (lambda msg: None)
     if kvox is not None:
         sp_k = material_tt(kvox, 0.0, op_eps)
         sp_kp = material_tt(kvox, k0, op_eps)
         sp_k2 = material_tt((np.asarray(kvox, dtype=np.float64) - k0) ** 2, 0.0, op_eps * 1e-2)
         L = int(round(math.log2(kvox.shape[0])))
+    elif cell is not None:
+        # a 2^L grid tiled by a periodic cell (L given)
+        sp_k = material_tt_periodic(cell, L, 0.0, op_eps)
+        sp_kp = material_tt_periodic(cell, L, k0, op_eps)
+        sp_k2 = material_tt_periodic((np.asarray(cell, dtype=np.float64) - k0) ** 2, L, 0.0,
+                                     op_eps * 1e-2)
     else:
         sp_k = material_tt_z_invariant(section, 0.0, op_eps)
         sp_kp = material_tt_z_invariant(section, k0, op_eps)
         sp_k2 = material_tt_z_invariant((np.asarray(section, dtype=np.float64) - k0) ** 2, 0.0,
                                         op_eps * 1e-2)
         L = int(round(math.log2(section.shape[0])))
+    say(f"material trains, k' rank {max(c.shape[0] for c in sp_kp)}")
     kp = with_component_core(sp_kp, np.ones(3))
     ksel = [with_component_core(sp_k, np.eye(3)[c]) for c in range(3)]
     # (k')^2 for the exact norm ||k' e||^2 = <e, diag((k')^2) e>
@@ -329,9 +359,11 @@ def build_problem(kvox=None, k0=None, L=None, section=None, op_eps=1e-10, sfft_e
         S, Sinv, G = shared["S"], shared["Sinv"], shared["G"]
     else:
         S, Sinv = sfft_3d(L, sfft_eps)
+        say("SFFT operator")
         # the dense Green array has 9 N^3 entries: beyond 256^3 the
         # exponential-sum build (same operator, same ranks)
-        G = green_tt(L, k0, op_eps) if L <= 8 else green_tt_expsum(L, k0, op_eps)
+        G = green_tt(L, k0, op_eps) if L <= 8 else green_tt_expsum(L, k0, op_eps, log=say)
+        say(f"Green operator, rank {max(c.shape[0] for c in G)}")
     return {"L": L, "k0": float(k0), "kp": kp, "k2": k2, "k_sel": ksel, "S": S, "Sinv": Sinv,
             "G": G}
 

@@ -72,3 +72,17 @@ def test_sfft_of_mean_field_is_zero_frequency_delta():
     want = np.zeros((3, N ** 3), dtype=complex)
     want[:, 0] = E * N ** 1.5
     assert np.max(np.abs(full - want)) < 1e-12 * N ** 1.5
+
+
+def test_periodic_material_equals_tiled_array():
+    # a 2^5 grid tiled by a 2^3 cell: free top bits (identity on the bond)
+    # followed by the cell's cores, per axis; compared with the train of the
+    # tiled array itself
+    cell = I.sphere_lattice_cell(3, rel_radius=0.3, k_in=20.0, k_out=1.0)
+    L = 5
+    tiled = np.tile(cell, (4, 4, 4))
+    per = P.material_tt_periodic(cell, L, 10.5, 1e-12)
+    ref = P.material_tt(tiled, 10.5, 1e-12)
+    assert len(per) == 3 * L
+    assert np.max(np.abs(T.full(per) - T.full(ref))) < 1e-10
+    assert max(c.shape[2] for c in per) <= max(c.shape[2] for c in ref)
