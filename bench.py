@@ -45,10 +45,6 @@ CONFIGS = {
     # 1024^2 section, and the Green operator by its exponential-sum form
     "cyl1024": dict(L=10, geom="cylinders", seed=4, k0=25.5, eps=1e-6, rmax=128,
                     loads=[[1.0, 0.0, 0.0]]),
-    # 4096^3 simple-cubic lattice of 8^3 spheres (radius 0.3 of the 512-voxel
-    # spacing), k = 20 in k = 1, load e_x: k' from the 512^3 period cell
-    "lattice4096": dict(L=12, geom="lattice", period_L=9, k0=10.5, eps=1e-5, rmax=256,
-                        loads=[[1.0, 0.0, 0.0]]),
 }
 
 
@@ -69,8 +65,6 @@ def voxels(cfg, inst=0):
         return I.laminate(cfg["L"])
     if cfg["geom"] == "cylinders":      # the (N, N) section of a z-invariant cell
         return I.cylinders_section(cfg["L"], cfg["seed"])
-    if cfg["geom"] == "lattice":        # one period of a periodic cell
-        return I.sphere_lattice_cell(cfg["period_L"], rel_radius=0.3, k_in=20.0, k_out=1.0)
     raise ValueError(cfg["geom"])
 
 
@@ -111,8 +105,6 @@ def cpu_baseline(cfg, kvox, budget_s=20.0):
             "sample": f"{its} dense Moulinec-Suquet iterations (Algorithm 1, numpy pocketfft, "
                       f"one thread) on the same {kvox.shape[0]}^{d} microstructure and load"
                       + (" (the exact 2D reduction of the z-invariant cell)" if d == 2 else "")
-                      + (" (one period: the exact reduction of the periodic cell)"
-                         if cfg.get("geom") == "lattice" else "")
                       + "; the naive TT oracle cannot form this workload's product ranks"}
 
 
@@ -256,12 +248,6 @@ def main():
         fields = [E for _ in probs for E in cfg["loads"]]
     elif cfg["geom"] == "cylinders":
         prob = P.build_problem(section=voxels(cfg), k0=cfg["k0"])
-        probs = [prob]
-        fields = list(cfg["loads"])
-    elif cfg["geom"] == "lattice":
-        prob = P.build_problem(cell=voxels(cfg), L=cfg["L"], k0=cfg["k0"],
-                               log=lambda m: print(f"[bench] set-up: {m}", file=sys.stderr,
-                                                   flush=True))
         probs = [prob]
         fields = list(cfg["loads"])
     else:
