@@ -209,8 +209,10 @@ def main():
                     help="run only the tt_round micro-benchmark and print its JSON")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; the multi-GPU layout is described "
-                                   "in DESIGN.md and not launched", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "one GPU only: independent solves would shard across GPUs "
+                                   "with no exchange, and one large train by core blocks with "
+                                   "point-to-point sends of the carried factor; neither is "
+                                   "launched", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import numpy as np
