@@ -8,6 +8,8 @@
 namespace qt {
 
 constexpr int XT_K = 16;
+// the panel index maps below (idx >> 4, idx & 15) take 16-deep K panels
+static_assert(XT_K == 16, "k_gemm_ex's panel index maps assume XT_K == 16");
 constexpr int XT_PAD = 16;   // LDS row pitch 80 doubles: 16-lane groups of one read land 32 banks apart
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
