@@ -255,3 +255,30 @@ def test_gemm_tile_shapes_are_bitwise_equal(q):
         assert torch.equal(d, d0), mode
         assert torch.equal(s, s0), mode
     assert outs[1][4] > 0          # autotune recorded the signatures it timed
+
+
+def test_sketch_svd_round_noise_floor_when_over_budget(q, ctx):
+    # x = 1 * y with y of ranks (2, 4, 8, 2, 2): bond 3's sketch width (3) is
+    # below its rank (8), so at eps = 1e-12 the projection alone exhausts the
+    # budget (fail flag set); bond 4's width (4) exceeds its rank (2), and the
+    # noise floor keeps it at rank 2 on the device as in the oracle
+    import torch
+    modes = [3] + [2] * 5
+    dcores = [np.ones((1, p, 1)) for p in modes]
+    y = I.random_tt(modes, [1, 2, 4, 8, 2, 2, 1], seed=95)
+    ells = [1, 2, 4, 3, 4, 2, 1]
+    om = I.gaussian_sketch(modes, ells, seed=96)
+    Ad = q.DeviceMPO.from_cores(dcores, [1] * len(modes))
+    Om = q.DeviceTT.from_cores([om], ells)
+    Y = q.DeviceTT.from_cores([y])
+    out = q.DeviceTT.empty(modes, ells, 1)
+    xn = math.sqrt(np.real(T.dot(y, y)))
+    xn2 = torch.tensor([xn * xn], dtype=torch.float64, device="cuda")
+    err, fail = q.tt_sketch_round(ctx, Ad, Y, xn2, out, omega=Om, eps=1e-12, mode=q.ROUND_SKETCH)
+    got = out.to_cores()[0]
+    assert fail.cpu().numpy()[0] == 1
+    ref, info = SK.sketch_round(y, om, 1e-12, xnorm=xn)
+    assert not info["ok"]
+    assert T.ranks(ref)[4] == 2
+    assert T.ranks(got) == T.ranks(ref)
+    assert rel(T.full(got), T.full(ref)) < 1e-10
