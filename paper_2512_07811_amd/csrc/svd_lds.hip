@@ -265,9 +265,10 @@ __global__ __launch_bounds__(1024) void k_jacobi_lds(
   bool converged = nb < 2;
   int sweeps_done = 0;
   // each 16-lane row group owns one pair per round; sums reduce over the group by DPP
-  // per lane over the current sweep: any rotation, largest gamma^2 / (alpha
-  // beta) and smallest rotated column norm^2 (diagnostics of the sweep cap);
-  // convergence is one block-wide OR per sweep
+  // per lane: any rotation in the current sweep; in the last allowed sweep
+  // also the largest gamma^2 / (alpha beta) and the smallest rotated column
+  // norm^2 (diagnostics of the sweep cap); convergence is one block-wide OR
+  // per sweep
   double worst2 = 0.0, small2 = 0.0;
   for (int sweep = 0; sweep < max_sweeps && !converged; ++sweep) {
     ++sweeps_done;
@@ -343,8 +344,10 @@ __global__ __launch_bounds__(1024) void k_jacobi_lds(
             }
           }
           any_rot = 1;
-          worst2 = fmax(worst2, g2 * fast_rcp(al * be));
-          small2 = fmin(small2, fmin(al, be));
+          if (sweep + 1 == max_sweeps) {   // read only when the cap is reached
+            worst2 = fmax(worst2, g2 * fast_rcp(al * be));
+            small2 = fmin(small2, fmin(al, be));
+          }
         }
       }
       __syncthreads();
@@ -457,9 +460,10 @@ __global__ __launch_bounds__(1024) void k_jacobi_glb(
   const int g = tid % GL, grp = tid / GL, ngrp = blockDim.x / GL;
   bool converged = nb < 2;
   int sweeps_done = 0;
-  // per lane over the current sweep: any rotation, largest gamma^2 / (alpha
-  // beta) and smallest rotated column norm^2 (diagnostics of the sweep cap);
-  // convergence is one block-wide OR per sweep
+  // per lane: any rotation in the current sweep; in the last allowed sweep
+  // also the largest gamma^2 / (alpha beta) and the smallest rotated column
+  // norm^2 (diagnostics of the sweep cap); convergence is one block-wide OR
+  // per sweep
   double worst2 = 0.0, small2 = 0.0;
   for (int sweep = 0; sweep < max_sweeps && !converged; ++sweep) {
     ++sweeps_done;
@@ -560,8 +564,10 @@ __global__ __launch_bounds__(1024) void k_jacobi_glb(
             }
           }
           any_rot = 1;
-          worst2 = fmax(worst2, g2 * fast_rcp(al * be));
-          small2 = fmin(small2, fmin(al, be));
+          if (sweep + 1 == max_sweeps) {   // read only when the cap is reached
+            worst2 = fmax(worst2, g2 * fast_rcp(al * be));
+            small2 = fmin(small2, fmin(al, be));
+          }
         }
       }
       __syncthreads();

@@ -107,3 +107,24 @@ def test_round_component_below_double_square_range(q, ctx, eps):
     assert T.ranks(out) == T.ranks(ref)
     assert np.linalg.norm(full_out - T.full(ref)) <= 1e-14 * np.linalg.norm(T.full(ref))
     assert abs(nrm.cpu().numpy()[0] - info["norm"]) <= 1e-14 * info["norm"]
+
+
+def test_jacobi_sweep_cap_reports_diagnostics(q):
+    # a one-sweep cap on SVD blocks of order 16 cannot converge: the rounding
+    # returns QT_ENUMERIC with the order, the last sweep's worst off-diagonal
+    # (above the tolerance) and the sweep count; the kernels exit normally
+    c = q.Context(0)
+    try:
+        modes = [3] + [2] * 9
+        x = I.random_tt(modes, [1, 3, 6, 12, 16, 16, 16, 12, 6, 3, 1], seed=123)
+        X = q.DeviceTT.from_cores([x])
+        with pytest.raises(q.QtError) as ei:
+            q.tt_round(c, X, 0.0, 0, jacobi_max_sweeps=1)
+            c.sync()
+        assert ei.value.status == -5
+        msg = str(ei.value)
+        assert "sweep cap" in msg and ", 1 sweeps)" in msg
+        worst = float(msg.split("worst off-diagonal ")[1].split(" ")[0])
+        assert worst > 1.0
+    finally:
+        c.close()
