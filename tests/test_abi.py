@@ -35,3 +35,38 @@ def test_library_exports_every_declared_symbol():
 def test_binding_lists_every_export():
     from paper_2512_07811_amd import qtt
     assert set(qtt.EXPORTS) >= set(declared_functions())
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    from paper_2512_07811_amd import qtt
+    monkeypatch.setattr(qtt, "_lib", None)
+    with pytest.raises(ImportError, match="missing"):
+        qtt.load_library(str(tmp_path / "libqtthom.so"))
+
+
+def test_binding_refuses_to_run_without_a_device():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a HIP device is present")
+    from paper_2512_07811_amd import qtt
+    with pytest.raises(RuntimeError, match="HIP device"):
+        qtt._torch()
+
+
+# an import of the oracle package, a path into it, or an attribute of it
+USES_ORACLE = r"^\s*(from|import)\s+oracle\b|oracle/|\boracle\.[A-Za-z_]|import_module\(\s*['\"]oracle"
+
+
+def test_product_sources_never_reach_the_oracle():
+    """Nothing in the package (Python, HIP, C headers) imports, links or opens oracle/."""
+    pkg = os.path.join(ROOT, "paper_2512_07811_amd")
+    hits = []
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                src = open(os.path.join(dirpath, f)).read()
+                if re.search(USES_ORACLE, src, flags=re.M):
+                    hits.append(f)
+    if re.search(USES_ORACLE, open(HEADER).read(), flags=re.M):
+        hits.append("qtthom.h")
+    assert hits == []
