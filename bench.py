@@ -199,6 +199,10 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 512 MiB device copy first (HBM counter calibration)")
     ap.add_argument("--oversample", type=int, default=4)
+    ap.add_argument("--sketch-seed", type=int, default=17,
+                    help="Philox seed of the sketch Gaussians")
+    ap.add_argument("--quantile", type=float, default=0.9,
+                    help="learned mode: the predicted rank is the class at this quantile")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--round-ranks", default="16,32,64,128",
@@ -274,10 +278,10 @@ def main():
     else:
         ops, e = P.upload(prob, cfg["loads"], cfg["rmax"])
     mode = {"learned": qtt.ROUND_LEARNED, "sketch": qtt.ROUND_SKETCH, "svd": qtt.ROUND_SVD}[args.mode]
-    opts = qtt.solve_opts(cfg["eps"], cfg["rmax"], mode=mode, oversample=args.oversample, seed=17,
+    opts = qtt.solve_opts(cfg["eps"], cfg["rmax"], mode=mode, oversample=args.oversample, seed=args.sketch_seed,
                           graph=args.graph)
     sk_opts = qtt.solve_opts(cfg["eps"], cfg["rmax"], mode=qtt.ROUND_SKETCH,
-                             oversample=args.oversample, seed=17)
+                             oversample=args.oversample, seed=args.sketch_seed)
     e = qtt.DeviceTT.from_cores([P.mean_field(np.asarray(E), ops.L) for E in fields], e.cap)
     train_info = None
     if args.mode == "learned":
@@ -289,7 +293,7 @@ def main():
         qtt.ranklog_enable(ctx, 0, learned.N_CLS)
         pred = learned.RankPredictor(ctx, seed=5)
         hist = pred.train(X, Y, epochs=args.epochs)
-        pred.install()
+        pred.install(quantile=args.quantile)
         train_info = {"samples": int(X.shape[0]), "epochs": args.epochs,
                       "loss_first": float(hist[0]), "loss_last": float(hist[-1]),
                       "log_and_train_s": time.perf_counter() - t0}
@@ -361,7 +365,9 @@ def main():
         "config": {"workload": args.config, "L": cfg["L"], "grid": f"{2 ** cfg['L']}^3",
                    "instances": len(probs),
                    "rounding": args.mode, "eps": cfg["eps"], "max_rank": cfg["rmax"],
-                   "oversample": args.oversample, "graph": bool(args.graph and args.mode == "sketch"),
+                   "oversample": args.oversample,
+                   "quantile": args.quantile if args.mode == "learned" else None,
+                   "graph": bool(args.graph and args.mode == "sketch"),
                    "batch": B, "parallelism": "single GPU"},
     }
     dom = max(split, key=lambda k: split[k][0])
