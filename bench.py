@@ -201,6 +201,9 @@ def main():
     ap.add_argument("--oversample", type=int, default=4)
     ap.add_argument("--sketch-seed", type=int, default=17,
                     help="Philox seed of the sketch Gaussians")
+    ap.add_argument("--accept", type=float, default=1.0,
+                    help="learned mode: where the step's last SVD-truncated error e_s exceeds "
+                         "eps (rank cap), keep a rounding iff its error <= accept * e_s")
     ap.add_argument("--quantile", type=float, default=0.9,
                     help="learned mode: the predicted rank is the class at this quantile")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -293,7 +296,7 @@ def main():
         qtt.ranklog_enable(ctx, 0, learned.N_CLS)
         pred = learned.RankPredictor(ctx, seed=5)
         hist = pred.train(X, Y, epochs=args.epochs)
-        pred.install(quantile=args.quantile)
+        pred.install(quantile=args.quantile, accept_factor=args.accept)
         train_info = {"samples": int(X.shape[0]), "epochs": args.epochs,
                       "loss_first": float(hist[0]), "loss_last": float(hist[-1]),
                       "log_and_train_s": time.perf_counter() - t0}
@@ -367,6 +370,7 @@ def main():
                    "rounding": args.mode, "eps": cfg["eps"], "max_rank": cfg["rmax"],
                    "oversample": args.oversample,
                    "quantile": args.quantile if args.mode == "learned" else None,
+                   "accept": args.accept if args.mode == "learned" else None,
                    "graph": bool(args.graph and args.mode == "sketch"),
                    "batch": B, "parallelism": "single GPU"},
     }

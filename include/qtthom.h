@@ -264,12 +264,14 @@ qt_status homogenize(qt_ctx ctx, const qt_operands* ops, const qt_tt* k_sel, qt_
  * r_c = c * r_0 (Sec. 5.1) are combined with a small FP32 MLP that predicts
  * each bond's rank from the previous iteration's sketched spectrum, so that the
  * product-aware rounding can skip its SVD truncation sweep.  The exact
- * a-posteriori error decides: above accept * max(eps, e_s), where e_s is the
- * error of the last SVD-truncated rounding of the same step (e_s > eps only
- * where the rank cap binds), the step is redone with the SVD-truncated sketch
- * rounding (fallback, counted).  With accept <= 1 every rounding is as
- * accurate as the SVD truncation would be (to the drift of e_s between its
- * refreshes, which happen at every fallback).
+ * a-posteriori error decides: above eps, or above max(eps, accept * e_s) when
+ * e_s > eps, where e_s is the error of the last SVD-truncated rounding of the
+ * same step (e_s > eps only where the rank cap binds), the step is redone with
+ * the SVD-truncated sketch rounding (fallback, counted).  The tolerance eps
+ * always holds; accept only scales the comparison with the SVD truncation
+ * where the cap binds.  With
+ * accept <= 1 every rounding is as accurate as the SVD truncation would be (to
+ * the drift of e_s between its refreshes, which happen at every fallback).
  * ------------------------------------------------------------------------- */
 
 /* Number of floats in the MLP parameter vector for n_in inputs and n_cls
@@ -317,7 +319,8 @@ qt_status qt_ranklog_get(qt_ctx ctx, float* features, int32_t* labels, int32_t m
 /* Installs the predictor for QT_ROUND_LEARNED (params: device, borrowed; must
  * stay valid while used).  quantile in (0, 1]: class choice (see qt_mlp_infer);
  * accept_factor in (0, 2]: a learned rounding is kept iff its relative error
- * is at most accept_factor * max(eps, e_s) (<= 0: 1).  Errors: QT_EINVAL for
+ * is at most eps, or at most max(eps, accept_factor * e_s) where e_s > eps
+ * (<= 0: 1).  Errors: QT_EINVAL for
  * other values, n_cls outside [2, 32] or quantile outside (0, 1]. */
 qt_status qt_set_predictor(qt_ctx ctx, const float* params, int32_t n_cls, float quantile,
                            float accept_factor);

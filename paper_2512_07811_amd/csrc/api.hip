@@ -544,9 +544,10 @@ static qt_tt view_caps(const qt_tt& t, const std::vector<int32_t>& caps) {
 // One product-aware rounding step s of the iteration.  Learned path: fixed
 // ranks predicted by the MLP from the previous iteration's features; accepted
 // when the exact a-posteriori error sqrt(||x||^2 - ||x~||^2)/||x|| is at most
-// accept * max(eps, e_s), e_s = the error of the last SVD-truncated rounding
-// of this step (above eps only where the rank cap binds), otherwise redone
-// with the SVD-truncated sketch (fallback).
+// eps, or, where the last SVD-truncated rounding of this step could not meet
+// eps (its error e_s > eps: the rank cap binds), at most max(eps, accept * e_s);
+// otherwise redone with the SVD-truncated sketch (fallback).  The factor never
+// relaxes eps.
 static qt_status round_step(qt_ctx ctx, int step, const qt_mpo* A, const qt_tt* y,
                             const std::vector<int32_t>& ell_plan, const qt_round_opts& base,
                             const double* xn2, qt_tt* out, double* err_dev, uint64_t iter_id,
@@ -576,8 +577,9 @@ static qt_status round_step(qt_ctx ctx, int step, const qt_mpo* A, const qt_tt* 
     QT_HIP(hipMemcpyAsync(&err, err_dev, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     QT_HIP(hipStreamSynchronize(ctx->stream));
     ++L->learned_roundings;
-    const double ref = std::max(base.eps, L->ref_err[step]);
-    if (!(err <= (double)L->accept * ref)) {
+    const double es = L->ref_err[step];
+    const double ref = es > base.eps ? std::max(base.eps, (double)L->accept * es) : base.eps;
+    if (!(err <= ref)) {
       ++L->fallbacks;
       ell = ell_plan;
       so.mode = QT_ROUND_SKETCH;

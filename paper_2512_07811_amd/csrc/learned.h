@@ -21,7 +21,9 @@ struct LearnCtx {
   const float* params = nullptr;
   int pred_cls = 0;
   float quantile = 0.9f;
-  float accept = 1.0f;  // accepted iff error <= accept * max(eps, ref_err[step])
+  // a learned rounding is kept iff error <= eps, or, where ref_err[step] > eps
+  // (rank cap), iff error <= max(eps, accept * ref_err[step])
+  float accept = 1.0f;
   long long fallbacks = 0;
   long long learned_roundings = 0;
   // rank log (training data)

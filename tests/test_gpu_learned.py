@@ -243,6 +243,39 @@ def test_learned_homogenize_matches_svd_path_and_dense_oracle(q, cell, trained):
     assert abs(A[0, 0] - Ad[0, 0]) < 1e-5 * Ad[0, 0]
 
 
+def test_accept_factor_never_relaxes_eps(q, cell):
+    # at eps 1e-3 the sketch of width rank cap + oversampling covers every
+    # product of this cell, so each SVD-truncated rounding meets eps and a
+    # factor above 1 must not loosen the acceptance: a network that always
+    # answers rank 8 keeps and rejects the same roundings with accept 1 and 2
+    import torch
+
+    from paper_2512_07811_amd import learned
+    layers = f32_layers(31)
+    layers[7] = np.array([50.0] + [-50.0] * (C - 1), dtype=np.float32)
+    layers[6] = np.zeros_like(layers[6])
+    params = torch.from_numpy(learned.flat_params(layers)).cuda()
+    opts = q.solve_opts(1e-3, RMAX, tol=TOL, max_iter=12, mode=q.ROUND_LEARNED, oversample=4,
+                        seed=3)
+    runs = []
+    for accept in (1.0, 2.0):
+        c = q.Context(0)
+        try:
+            q.set_predictor(c, params, C, 0.9, accept)
+            ops, e = fresh_field(q, cell, [1.0, 0.0, 0.0])
+            A, its, res, st = q.homogenize(c, ops, e, opts)
+            runs.append((A, its, res, c.counters()))
+        finally:
+            c.close()
+    (A1, its1, res1, cnt1), (A2, its2, res2, cnt2) = runs
+    assert cnt1["learned_roundings"] > 0
+    assert cnt1["learned_fallbacks"] == cnt2["learned_fallbacks"]
+    assert cnt1["learned_roundings"] == cnt2["learned_roundings"]
+    assert np.array_equal(its1, its2)
+    assert np.array_equal(res1, res2)
+    assert A1[0, 0] == A2[0, 0]
+
+
 def test_forced_underprediction_falls_back(q, cell):
     # a network that always answers class 0 (rank 8) under-predicts the field
     # ranks: the a-posteriori check rejects those roundings and the SVD path runs
