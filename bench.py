@@ -11,7 +11,8 @@ tolerance 1e-6, field rank cap 64, learned-rank rounding: the rank predictor is
 trained on the device from the rank log of SVD-truncated iterations run before
 the timed window (part of the warm-up), then the timed window runs the learned
 path; the same window is re-run with the SVD-truncated product-aware rounding
-from the same field for the ablation figures.
+from the same field for the ablation figures, and once more on the learned path
+with the relaxed acceptance at capped steps (accept factor 1.25).
 
 Prints one JSON line (see the keys below).
 """
@@ -53,6 +54,9 @@ CONFIGS = {
 # commands is profiles/k_gemm_ex_sphere256_hbm_traffic.md.  Reported only for
 # the workload and mode it was measured on.
 GEMM_TRAFFIC = {("sphere256", "learned"): 26.69e6}
+
+# accept factor of the ablation's relaxed learned window
+RELAXED_ACCEPT = 1.25
 
 
 def voxels(cfg, inst=0):
@@ -356,6 +360,26 @@ def main():
                     "gemm_flops_ratio": cnt["gemm_flops"] / max(cnt_sk["gemm_flops"], 1),
                     "svd_calls_learned": cnt["svd_calls"], "svd_calls_sketch": cnt_sk["svd_calls"],
                     "max_residual_rel_diff": float(np.max(np.abs(r_l - r_s) / r_s))}
+        if args.accept == 1.0:
+            # the same window again with the relaxed acceptance at capped steps
+            # (a learned error within 25 % of the SVD-truncated one is kept; eps
+            # still holds elsewhere); the predictor state carries over from the
+            # windows above
+            pred.install(quantile=args.quantile, accept_factor=RELAXED_ACCEPT)
+            e.data.copy_(snap[0])
+            e.ranks.copy_(snap[1])
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            qtt.ls_iterate(ctx, ops, e, opts, args.steps)
+            ctx.sync()
+            torch.cuda.synchronize()
+            dt_rx = time.perf_counter() - t2
+            cnt_rx = ctx.counters(reset=True)
+            pred.install(quantile=args.quantile, accept_factor=args.accept)
+            ablation.update({"relaxed_accept": RELAXED_ACCEPT,
+                             "relaxed_accept_iters_per_s": args.steps * len(fields) / dt_rx,
+                             "relaxed_accept_fallbacks": cnt_rx["learned_fallbacks"],
+                             "relaxed_accept_roundings": cnt_rx["learned_roundings"]})
     B = len(fields)
     value = args.steps * B / dt
     print(f"[bench] {args.steps} steps in {dt:.3f}s; residuals {res.cpu().numpy()[:, 0].tolist()}",
