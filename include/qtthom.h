@@ -176,6 +176,27 @@ qt_status tt_add(qt_ctx ctx, double alpha_re, double alpha_im, const qt_tt* x,
 qt_status tt_round(qt_ctx ctx, qt_tt* x, const qt_round_opts* opts, double* err_out,
                    double* norm_out);
 
+/* Allocation-free variant of tt_round, for callers that cannot allocate
+ * device memory during the call: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  Same arguments, kernels and results
+ * as tt_round (bitwise equal on the same input), but the rounding's workspace
+ * is a library-owned static device array of QT_NOALLOC_SCRATCH_BYTES per GPU
+ * (held from library load until the process ends; its address is looked up
+ * by qt_ctx_create), and the call performs no hipMalloc/hipFree, no GEMM
+ * tile-shape timing (signatures not tuned yet use 64 x 64 tiles) and no
+ * profiling events.
+ * Limits: QT_ECAPACITY (nothing launched) when the rounding needs more than
+ * QT_NOALLOC_SCRATCH_BYTES of workspace (e.g. rank 384 on 25 cores fits,
+ * rank 512 does not) or an SVD block above 1024 columns.
+ * Concurrency: every call on one GPU, from any context or thread, uses the
+ * same array and leaves its contents behind; calls that overlap in time on
+ * one GPU (different streams, or threads) race and give undefined results.
+ * Calls on one stream are ordered and safe.  Nothing in the array needs to
+ * start at zero. */
+#define QT_NOALLOC_SCRATCH_BYTES (64ll << 20)
+qt_status tt_round_noalloc(qt_ctx ctx, qt_tt* x, const qt_round_opts* opts, double* err_out,
+                           double* norm_out);
+
 /* out[b] = sum_i conj(a_i) b_i for every instance (device [B][2] doubles). */
 qt_status tt_dot(qt_ctx ctx, const qt_tt* a, const qt_tt* b, double* out);
 

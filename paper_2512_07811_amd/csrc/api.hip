@@ -15,6 +15,7 @@ thread_local ProfSink* g_prof = nullptr;
 thread_local unsigned long long* g_counters = nullptr;
 thread_local SplitKBuf g_splitk;
 thread_local GemmTuner* g_tuner = nullptr;
+thread_local bool g_no_alloc = false;
 
 // Regions do not nest: work launched inside an open region (the finishing
 // products of a large SVD, the products of a blocked QR) counts to that region.
@@ -891,6 +892,18 @@ qt_status qt_ctx_create(int device, void* stream, size_t ws_bytes, qt_ctx* out) 
     delete c;
     set_error(hip_msg(e, "qt_ctx_create: device allocations"));
     return QT_EHIP;
+  }
+  {
+    // the allocation-free entry points' scratch on this device
+    qt_status s = noalloc_attach(device);
+    if (s != QT_OK) {
+      hipFree(c->status);
+      hipFree(c->counters);
+      hipFree(c->splitk.p);
+      hipFree(c->dev_iter);
+      delete c;
+      return s;
+    }
   }
   if (ws_bytes) {
     qt_status s = ws_reserve(c, ws_bytes);

@@ -240,6 +240,10 @@ struct GemmTuner {
   hipEvent_t ev[2] = {nullptr, nullptr};
 };
 extern thread_local GemmTuner* g_tuner;
+// Set while an allocation-free entry point runs: the GEMM launcher then never
+// times tile shapes (the timing would allocate its output buffer).
+extern thread_local bool g_no_alloc;
+qt_status noalloc_attach(int device);
 
 struct LearnCtx;
 }  // namespace qt

@@ -334,7 +334,7 @@ void gemm_ex(hipStream_t st, int batch, int nb1, int nb2, Dim M, Dim N, Dim K, i
     auto it = T->choice.find(key);
     if (it != T->choice.end()) {
       v = it->second;
-    } else if (!stream_capturing(st)) {
+    } else if (!g_no_alloc && !stream_capturing(st)) {
       v = tune_shape(st, *T, conjA, conjB, a);
       T->choice[key] = v;
     }

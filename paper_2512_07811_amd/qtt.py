@@ -24,7 +24,7 @@ PREC_F64, PREC_F32 = 0, 1
 EXPORTS = ["qt_ctx_create", "qt_ctx_destroy", "qt_last_error", "qt_ctx_sync",
            "qt_ctx_counters", "qt_ctx_profile", "qt_ctx_profile_read", "qt_ctx_autotune",
            "tt_hadamard",
-           "tt_mpo_apply", "tt_add", "tt_round", "tt_dot", "tt_sketch_round", "tt_sandwich",
+           "tt_mpo_apply", "tt_add", "tt_round", "tt_round_noalloc", "tt_dot", "tt_sketch_round", "tt_sandwich",
            "ls_iterate", "homogenize", "qt_mlp_num_params", "qt_mlp_train_step", "qt_mlp_infer",
            "qt_ranklog_enable", "qt_ranklog_get", "qt_set_predictor", "qt_learn_reset"]
 
@@ -91,6 +91,7 @@ def load_library(path: str = LIB_PATH):
     lib.tt_add.argtypes = [vp, dbl, dbl, C.POINTER(TTDesc), dbl, dbl, C.POINTER(TTDesc),
                            C.POINTER(TTDesc)]
     lib.tt_round.argtypes = [vp, C.POINTER(TTDesc), C.POINTER(RoundOpts), vp, vp]
+    lib.tt_round_noalloc.argtypes = [vp, C.POINTER(TTDesc), C.POINTER(RoundOpts), vp, vp]
     lib.tt_dot.argtypes = [vp, C.POINTER(TTDesc), C.POINTER(TTDesc), vp]
     lib.tt_sketch_round.argtypes = [vp, C.POINTER(MPODesc), C.POINTER(TTDesc), C.POINTER(TTDesc),
                                     C.POINTER(RoundOpts), vp, C.POINTER(TTDesc), vp, vp]
@@ -391,6 +392,14 @@ def tt_round(ctx: Context, x: DeviceTT, eps: float, max_rank: int = 0, **kw):
     _check(ctx.lib.tt_round(ctx.h, C.byref(x.desc()), C.byref(o), C.c_void_p(err.data_ptr()),
                             C.c_void_p(nrm.data_ptr())))
     return err, nrm
+
+
+def tt_round_noalloc(ctx: Context, x: DeviceTT, eps: float, err, nrm, max_rank: int = 0, **kw):
+    """tt_round with the library's static scratch (no device allocation in the
+    call); err and nrm are caller-owned float64 device tensors [batch]."""
+    o = round_opts(eps, max_rank, **kw)
+    _check(ctx.lib.tt_round_noalloc(ctx.h, C.byref(x.desc()), C.byref(o),
+                                    C.c_void_p(err.data_ptr()), C.c_void_p(nrm.data_ptr())))
 
 
 def tt_dot(ctx: Context, a: DeviceTT, b: DeviceTT):
