@@ -294,11 +294,12 @@ def main():
     if args.mode == "learned":
         from paper_2512_07811_amd import learned
         t0 = time.perf_counter()
-        qtt.ranklog_enable(ctx, 1 << 20, learned.N_CLS)
+        n_cls = learned.n_classes(cfg["rmax"])
+        qtt.ranklog_enable(ctx, 1 << 20, n_cls)
         qtt.ls_iterate(ctx, ops, e, sk_opts, args.log_iters)
         X, Y = qtt.ranklog_get(ctx)
-        qtt.ranklog_enable(ctx, 0, learned.N_CLS)
-        pred = learned.RankPredictor(ctx, seed=5)
+        qtt.ranklog_enable(ctx, 0, n_cls)
+        pred = learned.RankPredictor(ctx, n_cls=n_cls, seed=5)
         hist = pred.train(X, Y, epochs=args.epochs)
         pred.install(quantile=args.quantile, accept_factor=args.accept)
         train_info = {"samples": int(X.shape[0]), "epochs": args.epochs,

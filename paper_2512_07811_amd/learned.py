@@ -14,7 +14,14 @@ import numpy as np
 
 from . import inputs, qtt
 
-N_CLS = 8          # ranks 8 .. 64
+N_CLS = 8          # ranks 8 .. 64 (default: rank caps up to 64)
+
+
+def n_classes(max_rank: int) -> int:
+    """Class count whose top class (rank 8 n_cls) reaches the rank cap (at most
+    32 classes, rank 256); with fewer classes the predictor could never ask for
+    the capped rank and every capped learned rounding would fall back."""
+    return max(2, min(32, -(-int(max_rank) // 8)))
 LOSS_BETA = 1.0    # weight of the asymmetric cost term
 LOSS_GAMMA = 2.0   # cost of predicting below the label
 
