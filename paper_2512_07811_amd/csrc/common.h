@@ -162,6 +162,39 @@ __device__ inline cplx row16_sum(cplx v) {
   return v;
 }
 
+// Householder reflector of a column x (head al = x_j, tail sum of squares
+// sig2): beta = -e^{i arg al} ||x||, iu0 = 1 / (al - beta), t = 1 + |al| / ||x||,
+// so that u = x / (al - beta) (u_j = 1) and H = I - t u u^H maps x to beta e_j.
+// When ||x||^2 < 2^-900 the caller passes al and sig2 of the column scaled by
+// sc = 2^600 (an exact power of two): squares and reciprocals of the unscaled
+// values would leave the double range; u and t do not depend on the scale,
+// beta and iu0 are returned for the unscaled column.
+constexpr double QR_TINY = 0x1p-900, QR_SCALE = 0x1p+600;
+__device__ inline void house_coef(cplx al, double sig2, double sc, double& t, cplx& beta,
+                                  cplx& iu0) {
+  // sc is 1 or QR_SCALE: its reciprocal without a division on the critical path
+  const double isc = sc == 1.0 ? 1.0 : 1.0 / QR_SCALE;
+  const double a2 = cabs2(al), x2 = a2 + sig2;
+  if (x2 == 0.0) {
+    t = 0.0; beta = cscale(al, isc); iu0 = make_double2(0.0, 0.0);
+    return;
+  }
+  const double ixn = fast_rsq(x2), xn = x2 * ixn;
+  double aa = 0.0;
+  cplx ph = make_double2(1.0, 0.0);
+  if (a2 > 0.0) {
+    const double ia = fast_rsq(a2);
+    aa = a2 * ia;
+    ph = make_double2(al.x * ia, al.y * ia);
+  }
+  const cplx bs = make_double2(-ph.x * xn, -ph.y * xn);
+  const cplx u0 = csub(al, bs);
+  const double id = fast_rcp(cabs2(u0)) * sc;
+  iu0 = make_double2(u0.x * id, -u0.y * id);
+  beta = cscale(bs, isc);
+  t = 1.0 + aa * ixn;
+}
+
 // Error reporting ---------------------------------------------------------
 void set_error(const std::string& msg);
 std::string hip_msg(hipError_t e, const char* what);

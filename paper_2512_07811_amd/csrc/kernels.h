@@ -54,22 +54,24 @@ void qr_auto(hipStream_t st, int batch, int mcap, int ncap, Dim m, Dim n, const 
 bool qr_reg_fits(int mcap, int ncap);
 bool qr_lds_fits(int mcap, int ncap);
 
-// Blocked Householder QR (panels of 32 columns, trailing updates and Q
-// formation on the MFMA GEMM) for unfoldings beyond one workgroup's LDS.
+// Blocked Householder QR (panels of 64, 32 or 16 columns factored in
+// registers by one workgroup, or 32-column panels in global memory above 576
+// rows; trailing updates and Q formation on the MFMA GEMM) for unfoldings
+// beyond one workgroup's registers and LDS.
 // Same contract as qr (Q may be null: R and s_out only).  Mw is the m x n work
 // matrix (column-major, leading dimension mcap, stride sM >= mcap * ncap).
 // orient: factor A^H where an instance's A is wide, as qr_reg does (mcap and
 // ncap are then the capacities of the factored matrix, rows >= columns, and
 // ws.dims must hold batch x 3 ints).
 struct QrBlkWs {
-  cplx* V;            // reflectors, mcap x (panels * 32) per instance
+  cplx* V;            // reflectors, mcap x (panels * NB) per instance
   int64_t v_stride;
-  cplx* T;            // panels x 32 x 32 per instance
+  cplx* T;            // panels x NB x NB per instance
   int64_t t_stride;
-  cplx* W1;           // 32 x ncap per instance
+  cplx* W1;           // NB x ncap per instance
   cplx* W2;
   int64_t w_stride;
-  double* tau;        // panels * 32 per instance
+  double* tau;        // panels * NB per instance (qr_blocked_tau_elems)
   int64_t tau_stride;
   int32_t* s_dev;     // batch
   int32_t* dims;      // batch x 3, for oriented factorizations (may be null otherwise)
@@ -78,6 +80,8 @@ bool qr_blocked_wanted(int mcap, int ncap);
 // element counts per instance of V, T and one W buffer; returns V + T + 2 W
 size_t qr_blocked_ws_elems(int mcap, int ncap, int64_t* v_elems, int64_t* t_elems,
                            int64_t* w_elems);
+// reflector scalars per instance (QrBlkWs::tau_stride)
+int64_t qr_blocked_tau_elems(int mcap, int ncap);
 void qr_blocked(hipStream_t st, int batch, int mcap, int ncap, Dim m, Dim n, const cplx* A,
                 int64_t sA, cplx* Mw, int64_t sM, const QrBlkWs& ws, cplx* Q, int64_t sQ,
                 cplx* R, int64_t sR, int32_t* s_out, int s_stride, bool orient = false);

@@ -278,22 +278,256 @@ __global__ __launch_bounds__(QB_T) void k_qrb_panel(int j0, Dim Md, Dim Nd, cplx
   for (int e = tid; e < QB_NB * QB_NB; e += QB_T) T[e] = Ts[e / QB_NB][e % QB_NB];
 }
 
+// Sum over a group of GL = 8, 16 or 32 consecutive lanes; every lane of the
+// group gets the same bits (each step adds two values that the partner lane
+// adds in the other order): quad_perm [1,0,3,2], [2,3,0,1], then
+// row_half_mirror (lanes i and 7 - i of each 8-lane half), then for 16 lanes
+// row_mirror, then for 32 lanes a swap of the two 16-lane halves.
+template <int GL>
+__device__ inline double grp_sum(double v) {
+  static_assert(GL == 8 || GL == 16 || GL == 32, "group of 8, 16 or 32 lanes");
+  if (GL == 16) return row16_sum(v);
+  if (GL == 32) {   // the two 16-lane halves add each other's sums (commutes)
+    v = row16_sum(v);
+    return v + __shfl_xor(v, 16, 64);
+  }
+#define QP_DPP_STEP(ctrl)                                                           \
+  {                                                                                 \
+    int lo = __double2loint(v), hi = __double2hiint(v);                             \
+    int l2 = __builtin_amdgcn_update_dpp(0, lo, ctrl, 0xF, 0xF, false);             \
+    int h2 = __builtin_amdgcn_update_dpp(0, hi, ctrl, 0xF, 0xF, false);             \
+    v += __hiloint2double(h2, l2);                                                  \
+  }
+  QP_DPP_STEP(0xB1)
+  QP_DPP_STEP(0x4E)
+  QP_DPP_STEP(0x141)
+#undef QP_DPP_STEP
+  return v;
+}
+template <int GL>
+__device__ inline cplx grp_sum(cplx v) {
+  v.x = grp_sum<GL>(v.x);
+  v.y = grp_sum<GL>(v.y);
+  return v;
+}
+
+// Register-resident panel factorization: NB = NT / GL columns
+// [j0, j0 + NB) of M (rows j0..m-1, m - j0 <= GL RPL).  Group c of GL lanes
+// holds panel column c, lane l its rows j0 + l + GL r, for the whole panel.
+// Step jj: the owner of column jj forms its reflector (the same Householder
+// coefficients as the one-workgroup QRs), keeps beta and the reflector below
+// the diagonal in its registers and publishes the reflector in LDS; after
+// one barrier every later column applies it (group sums), and every earlier
+// column c forms z_c = u_c^H u_jj, from which the next step builds T's
+// column jj: T[a][jj] = -t_jj sum_{c=a}^{jj-1} T[a][c] z_c, T[jj][jj] = t_jj.
+// One barrier per column; reflector and z buffers alternate between steps.
+// Writes the panel back (R on and above the diagonal), V (explicit, zero
+// above the diagonal, one on it, zero columns past the last reflector) and T.
+constexpr int QP_CH = 6;
+template <int NT, int GL, int RPL>
+__global__ __launch_bounds__(NT) void k_qrp_panel(int j0, Dim Md, Dim Nd, cplx* __restrict__ M,
+                                                    int64_t sM, int ld, cplx* __restrict__ V,
+                                                    int64_t sV, double* __restrict__ tau,
+                                                    int64_t sTau, cplx* __restrict__ T,
+                                                    int64_t sT) {
+  constexpr int NB = NT / GL;
+  constexpr int MP = GL * RPL;
+  const int b = blockIdx.x;
+  const int m = dimv(Md, b), n = dimv(Nd, b), s = min(m, n);
+  if (j0 >= s) return;
+  const int nbw = min(NB, s - j0), ncol = min(NB, n - j0);
+  M += b * sM;
+  V += b * sV;
+  tau += b * sTau;
+  T += b * sT + (int64_t)(j0 / NB) * NB * NB;
+  __shared__ cplx ush[2][MP];
+  __shared__ cplx zsh[2][NB];
+  __shared__ double tl[NB];
+  __shared__ cplx Ts[NB][NB];
+  const int tid = threadIdx.x, grp = tid / GL, l = tid % GL;
+  for (int e = tid; e < NB * NB; e += NT) Ts[e / NB][e % NB] = czero();
+  const int c = j0 + grp;
+  const bool have = grp < ncol;
+  cplx a[RPL];
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) {
+    const int i = j0 + l + GL * r;
+    a[r] = (have && i < m) ? M[(int64_t)c * ld + i] : czero();
+  }
+  for (int jj = 0; jj < nbw; ++jj) {
+    const int j = j0 + jj, buf = jj & 1;
+    if (grp == jj) {
+      double sig2 = 0.0;
+      cplx al = czero();
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) {
+        const int i = j0 + l + GL * r;
+        if (i > j && i < m) sig2 += cabs2(a[r]);
+        if (i == j) al = a[r];
+      }
+      sig2 = grp_sum<GL>(sig2);
+      al = grp_sum<GL>(al);   // one lane contributes
+      double t;
+      cplx beta, iu0;
+      {
+        double sc = 1.0, s2 = sig2;
+        const double x2 = cabs2(al) + sig2;
+        if (x2 > 0.0 && x2 < QR_TINY) {   // uniform over the group
+          sc = QR_SCALE;
+          s2 = 0.0;
+#pragma unroll
+          for (int r = 0; r < RPL; ++r) {
+            const int i = j0 + l + GL * r;
+            if (i > j && i < m) s2 += cabs2(cscale(a[r], sc));
+          }
+          s2 = grp_sum<GL>(s2);
+        }
+        house_coef(cscale(al, sc), s2, sc, t, beta, iu0);
+      }
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) {
+        const int i = j0 + l + GL * r;
+        cplx u;
+        if (i < j || i >= m) u = czero();
+        else if (i == j) u = make_double2(1.0, 0.0);
+        else u = cmul(a[r], iu0);
+        ush[buf][l + GL * r] = u;
+        if (i == j) a[r] = beta;
+        else if (i > j) a[r] = u;
+      }
+      if (l == 0) {
+        tl[jj] = t;
+        tau[j] = t;
+      }
+    }
+    __syncthreads();
+    const double t = tl[jj];
+    // T column jj - 1 from the previous step's z (published by the barrier)
+    if (jj >= 1 && tid < jj) {
+      const int q = jj - 1;
+      if (tid == q) {
+        Ts[q][q] = make_double2(tl[q], 0.0);
+      } else {
+        cplx acc = czero();
+        for (int cc = tid; cc < q; ++cc) cfma(acc, Ts[tid][cc], zsh[q & 1][cc]);
+        Ts[tid][q] = cscale(acc, -tl[q]);
+      }
+    }
+    const cplx* u = ush[buf];
+    // the reflector is read from LDS in chunks of QP_CH rows (the empty asm
+    // statements keep the compiler from loading all of it at once: the
+    // registers hold the column)
+    if (grp > jj && have && t != 0.0) {
+      cplx w = czero();
+#pragma unroll
+      for (int r0 = 0; r0 < RPL; r0 += QP_CH) {
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int r = r0; r < r0 + QP_CH && r < RPL; ++r) cfma(w, cconj(u[l + GL * r]), a[r]);
+      }
+      w = grp_sum<GL>(w);
+      const cplx f = cscale(w, -t);
+#pragma unroll
+      for (int r0 = 0; r0 < RPL; r0 += QP_CH) {
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int r = r0; r < r0 + QP_CH && r < RPL; ++r) cfma(a[r], u[l + GL * r], f);
+      }
+    } else if (grp < jj) {
+      // rows i >= j > c: a holds this column's reflector there
+      cplx z = czero();
+#pragma unroll
+      for (int r0 = 0; r0 < RPL; r0 += QP_CH) {
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int r = r0; r < r0 + QP_CH && r < RPL; ++r) {
+          const int i = j0 + l + GL * r;
+          if (i >= j) cfma(z, cconj(a[r]), u[l + GL * r]);
+        }
+      }
+      z = grp_sum<GL>(z);
+      if (l == 0) zsh[buf][grp] = z;
+    }
+  }
+  __syncthreads();
+  {
+    const int q = nbw - 1;
+    if (tid == q) {
+      Ts[q][q] = make_double2(tl[q], 0.0);
+    } else if (tid < q) {
+      cplx acc = czero();
+      for (int cc = tid; cc < q; ++cc) cfma(acc, Ts[tid][cc], zsh[q & 1][cc]);
+      Ts[tid][q] = cscale(acc, -tl[q]);
+    }
+  }
+  // the panel back (R part) and the explicit reflectors
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) {
+    const int i = j0 + l + GL * r;
+    if (i >= m) continue;
+    if (have) M[(int64_t)c * ld + i] = (grp < nbw && i > c) ? czero() : a[r];
+    cplx v;
+    if (grp >= nbw || i < c) v = czero();
+    else if (i == c) v = make_double2(1.0, 0.0);
+    else v = a[r];
+    V[(int64_t)c * ld + i] = v;
+  }
+  __syncthreads();
+  for (int e = tid; e < NB * NB; e += NT) T[e] = Ts[e / NB][e % NB];
+}
+
+// Panel width and kernel of the blocked QR for a column capacity of mcap
+// rows (512 threads, so that a lane may hold up to 24 complex rows without
+// spilling): 64 columns in 8-lane groups up to 192 rows, 32 columns in
+// 16-lane groups up to 384, 16 columns in 32-lane groups up to 576, else the
+// 32-column global-memory panel.
+static int qrb_nb(int mcap) {
+  if (mcap <= 8 * 24) return 64;
+  if (mcap <= 16 * 24) return 32;
+  if (mcap <= 32 * 18) return 16;
+  return QB_NB;
+}
+
+static void qrb_panel(hipStream_t st, int batch, int mcap, int j0, Dim m, Dim n, cplx* Mw,
+                      int64_t sM, int ld, const QrBlkWs& ws) {
+#define QP_LAUNCH(GL, RPL)                                                                  \
+  k_qrp_panel<512, GL, RPL><<<batch, 512, 0, st>>>(j0, m, n, Mw, sM, ld, ws.V, ws.v_stride, \
+                                                   ws.tau, ws.tau_stride, ws.T, ws.t_stride)
+  if (mcap <= 8 * 12) QP_LAUNCH(8, 12);
+  else if (mcap <= 8 * 24) QP_LAUNCH(8, 24);
+  else if (mcap <= 16 * 24) QP_LAUNCH(16, 24);
+  else if (mcap <= 32 * 18) QP_LAUNCH(32, 18);
+  else
+    k_qrb_panel<<<batch, QB_T, 0, st>>>(j0, m, n, Mw, sM, ld, ws.V, ws.v_stride, ws.tau,
+                                        ws.tau_stride, ws.T, ws.t_stride);
+#undef QP_LAUNCH
+}
+
+int64_t qr_blocked_tau_elems(int mcap, int ncap) {
+  const int NB = qrb_nb(mcap);
+  return (int64_t)((std::min(mcap, ncap) + NB - 1) / NB) * NB;
+}
+
 size_t qr_blocked_ws_elems(int mcap, int ncap, int64_t* v_elems, int64_t* t_elems,
                            int64_t* w_elems) {
   const int scap = std::min(mcap, ncap);
-  const int P = (scap + QB_NB - 1) / QB_NB;
-  *v_elems = (int64_t)mcap * P * QB_NB;
-  *t_elems = (int64_t)P * QB_NB * QB_NB;
-  *w_elems = (int64_t)QB_NB * ncap;
+  const int NB = qrb_nb(mcap);
+  const int P = (scap + NB - 1) / NB;
+  *v_elems = (int64_t)mcap * P * NB;
+  *t_elems = (int64_t)P * NB * NB;
+  *w_elems = (int64_t)NB * ncap;
   return (size_t)(*v_elems + *t_elems + 2 * *w_elems);
 }
 
-// The one-workgroup global-memory QR is faster up to a few panels (measured:
-// 256 x 128 unfoldings are slower blocked); from 8 panels on the trailing
-// products dominate and the blocked form wins (4x at 1024 x 512).
+// Matrices beyond registers and LDS: up to 576 rows the register-resident
+// panels (one barrier per column) make the blocked form faster than the
+// one-workgroup global-memory QR, whose every column step streams the trailing
+// matrix through one CU; above 576 rows the global-memory panel is slow per
+// column and the blocked form wins from 8 panels on (4x at 1024 x 512).
 bool qr_blocked_wanted(int mcap, int ncap) {
-  return !qr_reg_fits(mcap, ncap) && !qr_lds_fits(mcap, ncap) &&
-         std::min(mcap, ncap) >= 8 * QB_NB;
+  if (qr_reg_fits(mcap, ncap) || qr_lds_fits(mcap, ncap)) return false;
+  if (mcap <= 32 * 18) return true;   // register-resident panels
+  return std::min(mcap, ncap) >= 8 * QB_NB;
 }
 
 // Sizes of the factored matrix per instance when oriented: rows max(m, n),
@@ -321,7 +555,8 @@ void qr_blocked(hipStream_t st, int batch, int mcap, int ncap, Dim m0, Dim n0, c
   auto pe = [&]() { if (prof) g_prof->end(); };
   const int ld = mcap;
   const int scap = std::min(mcap, ncap);
-  const int P = (scap + QB_NB - 1) / QB_NB;
+  const int NB = qrb_nb(mcap);
+  const int P = (scap + NB - 1) / NB;
   const int64_t sV = ws.v_stride, sT = ws.t_stride, sW = ws.w_stride;
   const int ldw = ncap;
   const cplx one = make_double2(1.0, 0.0), mone = make_double2(-1.0, 0.0);
@@ -336,28 +571,27 @@ void qr_blocked(hipStream_t st, int batch, int mcap, int ncap, Dim m0, Dim n0, c
   }
   const Dim sd = dref(ws.s_dev, 1);
   for (int p = 0; p < P; ++p) {
-    const int j0 = p * QB_NB;
+    const int j0 = p * NB;
     pb();
-    k_qrb_panel<<<batch, QB_T, 0, st>>>(j0, m, n, Mw, sM, ld, ws.V, sV, ws.tau, ws.tau_stride,
-                                        ws.T, sT);
+    qrb_panel(st, batch, mcap, j0, m, n, Mw, sM, ld, ws);
     pe();
-    const int ncap_t = ncap - j0 - QB_NB;
+    const int ncap_t = ncap - j0 - NB;
     if (ncap_t <= 0) continue;
-    const Dim nt = shift(n, j0 + QB_NB), mt = shift(m, j0);
+    const Dim nt = shift(n, j0 + NB), mt = shift(m, j0);
     // W1 (NB x n') = V^H A_trail
-    gemm_ex(st, batch, 1, 1, dconst(QB_NB), nt, mt, QB_NB, ncap_t,
+    gemm_ex(st, batch, 1, 1, dconst(NB), nt, mt, NB, ncap_t,
             mat(ws.V + (int64_t)j0 * ld + j0, sV, cs(ld), cs(1)), true,
-            mat(Mw + (int64_t)(j0 + QB_NB) * ld + j0, sM, cs(1), cs(ld)), false,
+            mat(Mw + (int64_t)(j0 + NB) * ld + j0, sM, cs(1), cs(ld)), false,
             mat(ws.W1, sW, cs(ldw), cs(1)), one, false, Dim{nullptr, 0, 0, 1 << 30}, mcap - j0);
     // W2 = T^H W1
-    gemm_ex(st, batch, 1, 1, dconst(QB_NB), nt, dconst(QB_NB), QB_NB, ncap_t,
-            mat(ws.T + (int64_t)p * QB_NB * QB_NB, sT, cs(1), cs(QB_NB)), true,
+    gemm_ex(st, batch, 1, 1, dconst(NB), nt, dconst(NB), NB, ncap_t,
+            mat(ws.T + (int64_t)p * NB * NB, sT, cs(1), cs(NB)), true,
             mat(ws.W1, sW, cs(ldw), cs(1)), false, mat(ws.W2, sW, cs(ldw), cs(1)), one, false);
     // A_trail^T -= W2^T V^T  (the transposed form writes M along its columns)
-    gemm_ex(st, batch, 1, 1, nt, mt, dconst(QB_NB), ncap_t, mcap - j0,
+    gemm_ex(st, batch, 1, 1, nt, mt, dconst(NB), ncap_t, mcap - j0,
             mat(ws.W2, sW, cs(1), cs(ldw)), false,
             mat(ws.V + (int64_t)j0 * ld + j0, sV, cs(ld), cs(1)), false,
-            mat(Mw + (int64_t)(j0 + QB_NB) * ld + j0, sM, cs(ld), cs(1)), mone, true);
+            mat(Mw + (int64_t)(j0 + NB) * ld + j0, sM, cs(ld), cs(1)), mone, true);
   }
   {
     const int tr = (scap + QB_TILE - 1) / QB_TILE, tc = (ncap + QB_TILE - 1) / QB_TILE;
@@ -372,20 +606,20 @@ void qr_blocked(hipStream_t st, int batch, int mcap, int ncap, Dim m0, Dim n0, c
     k_qrb_qinit<<<batch * per, 256, 0, st>>>(per, cap_elems, m, n, Mw, sM, ld);
     pe();
     for (int p = P - 1; p >= 0; --p) {
-      const int j0 = p * QB_NB;
+      const int j0 = p * NB;
       const int scap_t = scap - j0;
       const Dim st_ = shift(sd, j0), mt = shift(m, j0);
       // W1 (NB x (s - j0)) = V^H Q[j0:, j0:]
-      gemm_ex(st, batch, 1, 1, dconst(QB_NB), st_, mt, QB_NB, scap_t,
+      gemm_ex(st, batch, 1, 1, dconst(NB), st_, mt, NB, scap_t,
               mat(ws.V + (int64_t)j0 * ld + j0, sV, cs(ld), cs(1)), true,
               mat(Mw + (int64_t)j0 * ld + j0, sM, cs(1), cs(ld)), false,
               mat(ws.W1, sW, cs(ldw), cs(1)), one, false, Dim{nullptr, 0, 0, 1 << 30}, mcap - j0);
       // W2 = T W1
-      gemm_ex(st, batch, 1, 1, dconst(QB_NB), st_, dconst(QB_NB), QB_NB, scap_t,
-              mat(ws.T + (int64_t)p * QB_NB * QB_NB, sT, cs(QB_NB), cs(1)), false,
+      gemm_ex(st, batch, 1, 1, dconst(NB), st_, dconst(NB), NB, scap_t,
+              mat(ws.T + (int64_t)p * NB * NB, sT, cs(NB), cs(1)), false,
               mat(ws.W1, sW, cs(ldw), cs(1)), false, mat(ws.W2, sW, cs(ldw), cs(1)), one, false);
       // Q[j0:, j0:]^T -= W2^T V^T
-      gemm_ex(st, batch, 1, 1, st_, mt, dconst(QB_NB), scap_t, mcap - j0,
+      gemm_ex(st, batch, 1, 1, st_, mt, dconst(NB), scap_t, mcap - j0,
               mat(ws.W2, sW, cs(1), cs(ldw)), false,
               mat(ws.V + (int64_t)j0 * ld + j0, sV, cs(ld), cs(1)), false,
               mat(Mw + (int64_t)j0 * ld + j0, sM, cs(ld), cs(1)), mone, true);

@@ -35,12 +35,17 @@ RoundWs round_ws_layout(const qt_tt* x, int lmax_cap) {
     w.max_nb = std::max<int64_t>(w.max_nb, nb);
     const int64_t mbk = std::max<int64_t>(x->cap[k], (int64_t)x->modes[k] * lnext);
     if (k >= 1 && nb <= 1024 && qr_blocked_wanted((int)mbk, (int)nb)) {
-      int64_t v, t, wq;
-      qr_blocked_ws_elems((int)mbk, (int)nb, &v, &t, &wq);
-      w.sb_v = std::max(w.sb_v, v);
-      w.sb_t = std::max(w.sb_t, t);
-      w.sb_w = std::max(w.sb_w, wq);
-      w.sb_tau = std::max(w.sb_tau, t / 32);
+      // the SVD's first QR (mbk x nb) and second QR (nb x nb): the panel
+      // width depends on the rows, so either may need more
+      for (const int64_t rows : {mbk, nb}) {
+        if (rows == nb && !qr_blocked_wanted((int)nb, (int)nb)) continue;
+        int64_t v, t, wq;
+        qr_blocked_ws_elems((int)rows, (int)nb, &v, &t, &wq);
+        w.sb_v = std::max(w.sb_v, v);
+        w.sb_t = std::max(w.sb_t, t);
+        w.sb_w = std::max(w.sb_w, wq);
+        w.sb_tau = std::max(w.sb_tau, qr_blocked_tau_elems((int)rows, (int)nb));
+      }
     }
     if (k < n - 1 && qr_blocked_wanted(x->cap[k] * x->modes[k], x->cap[k + 1])) {
       int64_t v, t, wq;
@@ -48,7 +53,7 @@ RoundWs round_ws_layout(const qt_tt* x, int lmax_cap) {
       w.qb_v = std::max(w.qb_v, v);
       w.qb_t = std::max(w.qb_t, t);
       w.qb_w = std::max(w.qb_w, wq);
-      w.qb_tau = std::max(w.qb_tau, t / 32);
+      w.qb_tau = std::max(w.qb_tau, qr_blocked_tau_elems(x->cap[k] * x->modes[k], x->cap[k + 1]));
     }
   }
   w.slot = slot; w.rr = rr; w.vv = vv; w.carry = carry; w.tau = tau;

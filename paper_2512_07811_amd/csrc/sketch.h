@@ -9,6 +9,8 @@ namespace qt {
 struct SketchWs {
   std::vector<int64_t> Woff;
   int64_t Wtot = 1, T1 = 1, T2 = 1, M = 1, T3 = 1, Z = 1, Y = 1, R = 1, tau = 1;
+  // blocked QRs of the sketches Y_k beyond registers and LDS (0: none)
+  int64_t qb_v = 0, qb_t = 0, qb_w = 0, qb_tau = 0;
   size_t bytes = 0;
 };
 SketchWs sketch_ws_layout(const qt_mpo* A, const qt_tt* y, const std::vector<int32_t>& ell);

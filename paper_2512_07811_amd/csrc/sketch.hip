@@ -127,10 +127,21 @@ SketchWs sketch_ws_layout(const qt_mpo* A, const qt_tt* y, const std::vector<int
     mx(w.Y, (int64_t)ell[k] * p * ell[k + 1]);
     mx(w.R, (int64_t)ell[k + 1] * ell[k + 1]);
     mx(w.tau, ell[k + 1]);
+    if (k < n - 1 && qr_blocked_wanted((int)(ell[k] * p), ell[k + 1])) {
+      int64_t v, t, wq;
+      qr_blocked_ws_elems((int)(ell[k] * p), ell[k + 1], &v, &t, &wq);
+      mx(w.qb_v, v);
+      mx(w.qb_t, t);
+      mx(w.qb_w, wq);
+      mx(w.qb_tau, qr_blocked_tau_elems((int)(ell[k] * p), ell[k + 1]));
+    }
   }
   const int B = y->batch;
   w.bytes = sizeof(cplx) * B * (w.Wtot + w.T1 + w.T2 + w.M + w.T3 + w.Z + 2 * w.Y + w.R) +
             sizeof(double) * B * (w.tau + 2) + 16 * 256;
+  if (w.qb_v > 0)
+    w.bytes += sizeof(cplx) * B * (w.qb_v + w.qb_t + 2 * w.qb_w) +
+               sizeof(double) * B * w.qb_tau + sizeof(int32_t) * B + 8 * 256;
   return w;
 }
 
@@ -167,6 +178,21 @@ qt_status sketch_impl(qt_ctx ctx, const qt_mpo* A, const qt_tt* y, const cplx* o
   double* tau = (double*)ws_take(ctx, sizeof(double) * B * w.tau);
   QT_CHECK(Wall && T1 && T2 && Mb && T3 && Zb && Yb && Wq && Rb && tau, QT_ENOMEM,
            "sketch: workspace too small");
+  QrBlkWs qb{};
+  if (w.qb_v > 0) {
+    qb.V = (cplx*)ws_take(ctx, sizeof(cplx) * B * w.qb_v);
+    qb.v_stride = w.qb_v;
+    qb.T = (cplx*)ws_take(ctx, sizeof(cplx) * B * w.qb_t);
+    qb.t_stride = w.qb_t;
+    qb.W1 = (cplx*)ws_take(ctx, sizeof(cplx) * B * w.qb_w);
+    qb.W2 = (cplx*)ws_take(ctx, sizeof(cplx) * B * w.qb_w);
+    qb.w_stride = w.qb_w;
+    qb.tau = (double*)ws_take(ctx, sizeof(double) * B * w.qb_tau);
+    qb.tau_stride = w.qb_tau;
+    qb.s_dev = (int32_t*)ws_take(ctx, sizeof(int32_t) * B);
+    QT_CHECK(qb.V && qb.T && qb.W1 && qb.W2 && qb.tau && qb.s_dev, QT_ENOMEM,
+             "sketch: blocked QR workspace too small");
+  }
   const int rs = n + 1;
   int32_t* ry = y->ranks;
   int32_t* ro = out->ranks;
@@ -261,8 +287,12 @@ qt_status sketch_impl(qt_ctx ctx, const qt_mpo* A, const qt_tt* y, const cplx* o
             mat(Wall + w.Woff[k + 1], iW, sc(lk1), sc(1)), false, mat(Yb, iY, sc(lk1), sc(1)),
             one, false, dconst(1 << 30), (int64_t)rd1 * y->cap[k + 1]);
     // Q_k = qr(Y_k) -> out core k, new rank s' -> ro[k+1]
-    qr_auto(st, B, lk * p, lk1, dref(ro + k, rs, p), dconst(lk1), Yb, iY, Wq, iY, tau, w.tau,
-            Od + out->offsets[k], out->inst_stride, Rb, w.R, ro + k + 1, rs);
+    if (qb.V && qr_blocked_wanted(lk * p, lk1))
+      qr_blocked(st, B, lk * p, lk1, dref(ro + k, rs, p), dconst(lk1), Yb, iY, Wq, iY, qb,
+                 Od + out->offsets[k], out->inst_stride, Rb, w.R, ro + k + 1, rs);
+    else
+      qr_auto(st, B, lk * p, lk1, dref(ro + k, rs, p), dconst(lk1), Yb, iY, Wq, iY, tau, w.tau,
+              Od + out->offsets[k], out->inst_stride, Rb, w.R, ro + k + 1, rs);
     if (rdiag) k_rdiag<<<1, 128, 0, st>>>(Rb, lk1, ro + k + 1, rdiag + (int64_t)(k + 1) * RD_MAX);
     // M_k = Q_k^H Z   (s' x R_{k+1})
     gemm_ex(st, B, 1, 1, dref(ro + k + 1, rs), dref(ry + k + 1, rs, rd1), dref(ro + k, rs, p), lk1,
