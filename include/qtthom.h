@@ -210,11 +210,15 @@ qt_status tt_dot(qt_ctx ctx, const qt_tt* a, const qt_tt* b, double* out);
  *         l_k); NULL draws Philox4x32-10 Gaussians from opts->seed with
  *         l_k = min(natural rank, r_A r_y capacity, max_rank + oversample).
  *  opts->mode QT_ROUND_SKETCH: then a right-to-left truncated-SVD sweep with
- *         the remaining budget eps^2||x||^2 - (||x||^2 - ||x~||^2) split over
- *         the n-1 bonds (capped by max_rank);
+ *         the remaining budget eps||x|| - e_s, e_s = (||x||^2 - ||x~||^2)^(1/2),
+ *         split over the n-1 bonds, threshold (eps||x|| - e_s)/sqrt(n-1)
+ *         (capped by max_rank; the truncation error is not orthogonal to the
+ *         projection error, so the two add linearly);
  *         QT_ROUND_LEARNED: keep the sketch ranks (fixed-rank rounding).
  *  xnorm2: device [B] exact ||x||^2 (e.g. from tt_sandwich).
- *  err_out: device [B] relative error sqrt(sketch^2 + truncation^2)/||x||.
+ *  err_out: device [B] (e_s + sqrt(sum of discarded tails^2))/||x||: the exact
+ *         relative error in QT_ROUND_LEARNED mode, an upper bound of it in
+ *         QT_ROUND_SKETCH mode (equal when nothing is truncated).
  *  fail_out: device [B] int, 1 when the sketch error alone exceeds eps*||x||.
  * A must be square (p_out = p_in = y's modes). out->cap >= sketch ranks.
  * QT_ECAPACITY (before the truncation sweep) in mode QT_ROUND_SKETCH when a

@@ -91,10 +91,15 @@ NOISE_FLOOR = 1e-14
 def sketch_round(x, omega, eps, rmax=None, xnorm=None):
     """RTO followed by SVD truncation with the remaining error budget.
 
-    sketch error e_s^2 = ||x||^2 - ||x~||^2 (exact for the projection); the
-    truncation threshold per bond is sqrt((eps^2 ||x||^2 - e_s^2)/(n-1)), and
-    at least NOISE_FLOOR ||x|| when eps > 0.
-    Returns (cores, info) with info['ok'] = (e_s <= eps ||x||).
+    sketch error e_s^2 = ||x||^2 - ||x~||^2 (exact for the projection).  The
+    truncation of interior bonds moves the left interfaces of the result out of
+    the sketch's span, so the projection error x - x~ and the truncation error
+    are not orthogonal: the budget is split linearly (triangle inequality),
+    ||x - z|| <= e_s + sqrt(sum of discarded tails^2) <= eps ||x||, with the
+    per-bond threshold (eps ||x|| - e_s)/sqrt(n-1), and at least
+    NOISE_FLOOR ||x|| when eps > 0.
+    Returns (cores, info) with info['ok'] = (e_s <= eps ||x||) and
+    info['err_bound'] = (e_s + sqrt(sum tails^2)) / ||x||.
     """
     n = len(x)
     if xnorm is None:
@@ -102,14 +107,16 @@ def sketch_round(x, omega, eps, rmax=None, xnorm=None):
     y = rto(x, omega)
     ynorm = float(np.linalg.norm(y[-1]))
     es2 = max(xnorm ** 2 - ynorm ** 2, 0.0)
-    budget = eps ** 2 * xnorm ** 2 - es2
+    es = math.sqrt(es2)
+    budget = eps * xnorm - es
     ok = budget >= 0.0
-    delta = math.sqrt(max(budget, 0.0) / (n - 1)) if n > 1 else 0.0
+    delta = max(budget, 0.0) / math.sqrt(n - 1) if n > 1 else 0.0
     if eps > 0.0 and n > 1:
         # noise floor: for eps > 0 no direction below 1e-14 ||x|| is kept, also
         # when the sketch error alone exceeds the budget
         delta = max(delta, NOISE_FLOOR * xnorm)
     z, info = truncate_right(y, delta, rmax)
-    info.update({"sketch_err": math.sqrt(es2), "xnorm": xnorm, "ynorm": ynorm, "ok": ok,
-                 "delta": delta})
+    trunc = math.sqrt(float(np.sum(np.asarray(info["disc"]) ** 2)))
+    info.update({"sketch_err": es, "xnorm": xnorm, "ynorm": ynorm, "ok": ok,
+                 "delta": delta, "err_bound": (es + trunc) / xnorm if xnorm > 0 else 0.0})
     return z, info

@@ -570,8 +570,11 @@ static qt_status round_step(qt_ctx ctx, int step, const qt_mpo* A, const qt_tt* 
     so.mode = QT_ROUND_LEARNED;
     sketch_mode = false;
   }
+  // the SVD-truncated rounding's error as the learned path's reference: the
+  // quadrature estimate (the reported bound adds the two parts linearly)
+  double* est_dev = err_dev + y->batch;
   QT_TRY(sround_impl(ctx, A, y, nullptr, nullptr, ell, &so, xn2, out, err_dev, nullptr,
-                     iter_id * 4 + step, nullptr, 0, 0, rd));
+                     iter_id * 4 + step, nullptr, 0, 0, rd, est_dev));
   ctx->ws_top = mark;
   if (use_learned) {
     double err = 0.0;
@@ -586,7 +589,7 @@ static qt_status round_step(qt_ctx ctx, int step, const qt_mpo* A, const qt_tt* 
       so.mode = QT_ROUND_SKETCH;
       sketch_mode = true;
       QT_TRY(sround_impl(ctx, A, y, nullptr, nullptr, ell, &so, xn2, out, err_dev, nullptr,
-                         iter_id * 4 + step + (1ull << 40), nullptr, 0, 0, rd));
+                         iter_id * 4 + step + (1ull << 40), nullptr, 0, 0, rd, est_dev));
       ctx->ws_top = mark;
     }
   }
@@ -597,7 +600,7 @@ static qt_status round_step(qt_ctx ctx, int step, const qt_mpo* A, const qt_tt* 
   if (sketch_mode && logging) learn_log(ctx, step, out->ranks);
   if (sketch_mode && learned) {
     double err = 0.0;
-    QT_HIP(hipMemcpyAsync(&err, err_dev, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    QT_HIP(hipMemcpyAsync(&err, est_dev, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     QT_HIP(hipStreamSynchronize(ctx->stream));
     L->ref_err[step] = err;
   }
@@ -762,7 +765,7 @@ static qt_status solver_setup(qt_ctx ctx, const qt_operands* ops, qt_tt* e,
   }
   ctx->ws_top = 0;
   QT_TRY(ws_reserve(ctx, bytesA + bytesB + ws + extra + sizeof(int32_t) * B * (n + 1) * 2 +
-                             sizeof(double) * B * 4 + 8 * 256));
+                             sizeof(double) * B * 5 + 8 * 256));
   S.bufA = (char*)ws_take(ctx, bytesA);
   S.bufB = (char*)ws_take(ctx, bytesB);
   S.rA = (int32_t*)ws_take(ctx, sizeof(int32_t) * B * (n + 1));
@@ -770,7 +773,7 @@ static qt_status solver_setup(qt_ctx ctx, const qt_operands* ops, qt_tt* e,
   S.dnorm = (double*)ws_take(ctx, sizeof(double) * B);
   S.dinv = (double*)ws_take(ctx, sizeof(double) * B);
   S.xn2 = (double*)ws_take(ctx, sizeof(double) * B);
-  S.err = (double*)ws_take(ctx, sizeof(double) * B);
+  S.err = (double*)ws_take(ctx, sizeof(double) * 2 * B);   // bound, then estimate
   QT_CHECK(S.bufA && S.bufB && S.rA && S.rB && S.dnorm && S.dinv && S.xn2 && S.err, QT_ENOMEM,
            "iteration workspace");
   std::vector<double> inv(B);

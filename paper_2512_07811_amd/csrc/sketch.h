@@ -71,11 +71,12 @@ SRoundWs sround_ws_layout(const qt_mpo* A, const qt_tt* y, const qt_tt* out,
 // Product-aware rounding of A (*) y into out (mode QT_ROUND_SKETCH or
 // QT_ROUND_LEARNED).  xn2: device ||A y||^2 per instance.  omega_in null ->
 // Gaussian cores drawn from (o->seed, stream_id).  fail[b] = 1 when the
-// sketch alone already exceeds eps*||x||.
+// sketch alone already exceeds eps*||x||.  err_out: the rigorous error bound;
+// err_est (optional): the quadrature estimate (see k_sketch_err).
 qt_status sround_impl(qt_ctx ctx, const qt_mpo* A, const qt_tt* y, const cplx* omega_in,
                       const std::vector<int64_t>* om_off_in, const std::vector<int32_t>& ell,
                       const qt_round_opts* o, const double* xn2, qt_tt* out, double* err_out,
                       int32_t* fail, uint64_t stream_id, double* svlog, int64_t svb,
-                      int64_t svi, double* rdiag = nullptr);
+                      int64_t svi, double* rdiag = nullptr, double* err_est = nullptr);
 
 }  // namespace qt

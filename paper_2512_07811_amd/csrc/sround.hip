@@ -11,7 +11,12 @@
 
 namespace qt {
 
-// delta[b] = sqrt(max(eps^2 ||x||^2 - e_s^2, 0)/(n-1)); e_s^2 = max(||x||^2 - ||x~||^2, 0)
+// e_s^2 = max(||x||^2 - ||x~||^2, 0) (exact for the orthogonal projection of the
+// sketch).  The truncation of interior bonds moves the result's left
+// interfaces out of the sketch's span, so its error is not orthogonal to the
+// projection error: the budget is split linearly (triangle inequality),
+// delta[b] = max(eps ||x|| - e_s, 0)/sqrt(n-1), so that
+// ||x - z|| <= e_s + sqrt(sum of discarded tails^2) <= eps ||x||.
 // Relative floor of the truncation threshold for eps > 0: singular values of
 // rounding noise (about 1e-16 of the norm each) never survive a truncation.
 constexpr double QT_NOISE_FLOOR = 1e-14;
@@ -22,8 +27,8 @@ __global__ void k_budget(int batch, int nbonds, double eps, const double* xn2, c
   int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= batch) return;
   double e2 = fmax(xn2[b] - yn2[b], 0.0);
-  double bud = eps * eps * xn2[b] - e2;
-  double dl = nbonds > 0 ? sqrt(fmax(bud, 0.0) / nbonds) : 0.0;
+  double bud = eps * sqrt(fmax(xn2[b], 0.0)) - sqrt(e2);
+  double dl = nbonds > 0 ? fmax(bud, 0.0) / sqrt((double)nbonds) : 0.0;
   // eps > 0: no bond keeps directions below the rounding-noise floor, also
   // when the projection alone exhausts the budget (the rank cap binds)
   if (eps > 0.0 && nbonds > 0) dl = fmax(dl, QT_NOISE_FLOOR * sqrt(xn2[b]));
@@ -34,12 +39,19 @@ __global__ void k_budget(int batch, int nbonds, double eps, const double* xn2, c
   if (bud < 0.0 && counters) atomicAdd(counters + CNT_SKETCH_FAIL, 1ull);
 }
 
+// Reported error: (e_s + sqrt(discarded tails^2)) / ||x||, a rigorous upper
+// bound of ||x - z|| / ||x|| (exact when nothing is truncated after the sketch);
+// est (optional): sqrt(e_s^2 + tails^2) / ||x||, the estimate that treats the
+// two errors as orthogonal (within a few per cent of the true error in the
+// capped tests), used where two roundings' errors are compared.
 __global__ void k_sketch_err(int batch, const double* xn2, const double* es2, const double* disc2,
-                             double* err) {
+                             double* err, double* est) {
   int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= batch) return;
   double x = xn2[b];
-  err[b] = x > 0.0 ? sqrt((es2[b] + (disc2 ? disc2[b] : 0.0)) / x) : 0.0;
+  const double d2 = disc2 ? disc2[b] : 0.0;
+  if (err) err[b] = x > 0.0 ? (sqrt(es2[b]) + sqrt(d2)) / sqrt(x) : 0.0;
+  if (est) est[b] = x > 0.0 ? sqrt((es2[b] + d2) / x) : 0.0;
 }
 
 std::vector<int32_t> sketch_ranks(const qt_mpo* A, const qt_tt* y, int rmax, int oversample) {
@@ -81,7 +93,7 @@ qt_status sround_impl(qt_ctx ctx, const qt_mpo* A, const qt_tt* y, const cplx* o
                       const std::vector<int64_t>* om_off_in, const std::vector<int32_t>& ell,
                       const qt_round_opts* o, const double* xn2, qt_tt* out, double* err_out,
                       int32_t* fail, uint64_t stream_id, double* svlog, int64_t svb,
-                      int64_t svi, double* rdiag) {
+                      int64_t svi, double* rdiag, double* err_est) {
   const int n = y->n, B = y->batch;
   hipStream_t st = ctx->stream;
   const int lmax_cap = o->max_rank > 0 ? o->max_rank : (1 << 30);
@@ -116,9 +128,11 @@ qt_status sround_impl(qt_ctx ctx, const qt_mpo* A, const qt_tt* y, const cplx* o
     const int sweeps = o->jacobi_max_sweeps > 0 ? o->jacobi_max_sweeps : ctx->jacobi_default;
     QT_TRY(right_sweep_impl(ctx, out, rkl, (const cplx*)out->data + out->offsets[n - 1],
                             out->inst_stride, buf, delta, disc2, lmax_cap, sweeps, svlog, svb, svi));
-    if (err_out) k_sketch_err<<<(B + 127) / 128, 128, 0, st>>>(B, xn2, es2, disc2, err_out);
+    if (err_out || err_est)
+      k_sketch_err<<<(B + 127) / 128, 128, 0, st>>>(B, xn2, es2, disc2, err_out, err_est);
   } else {
-    if (err_out) k_sketch_err<<<(B + 127) / 128, 128, 0, st>>>(B, xn2, es2, nullptr, err_out);
+    if (err_out || err_est)
+      k_sketch_err<<<(B + 127) / 128, 128, 0, st>>>(B, xn2, es2, nullptr, err_out, err_est);
   }
   QT_HIP(hipGetLastError());
   return QT_OK;

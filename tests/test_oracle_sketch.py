@@ -92,3 +92,38 @@ def test_sketch_round_noise_floor_when_over_budget():
     z0, info0 = SK.truncate_right(SK.rto(x, om), 0.0)
     assert T.ranks(z0)[4] > 2
     assert np.linalg.norm(T.full(z) - T.full(z0)) <= 1e-13 * info["xnorm"]
+
+
+def test_capped_truncation_error_is_not_orthogonal_to_the_projection_error():
+    # a rank cap truncates interior bonds of the sketched train; the result's
+    # left interfaces leave the sketch's span, so ||x - z||^2 differs from
+    # e_s^2 + sum tails^2 by a cross term well above rounding (brute force on
+    # the dense tensors), while the linear bound e_s + sqrt(sum tails^2) holds
+    m = [3] + [2] * 9
+    nat = _natural(m)
+    x = I.graded_tt(m, [1] + [min(v, 24) for v in nat[1:-1]] + [1], decay=0.85, seed=3)
+    ells = [1] + [min(nat[k], 10) for k in range(1, len(m))] + [1]
+    om = I.gaussian_sketch(m, ells, seed=7)
+    z, info = SK.sketch_round(x, om, 1e-6, rmax=6)
+    X, Z = T.full(x).ravel(), T.full(z).ravel()
+    nx = np.linalg.norm(X)
+    true = np.linalg.norm(X - Z) / nx
+    tails2 = float(np.sum(np.asarray(info["disc"]) ** 2))
+    quad = math.sqrt(info["sketch_err"] ** 2 + tails2) / nx
+    assert abs(true - quad) > 1e-4 * true
+    assert true <= info["err_bound"] * (1 + 1e-12)
+    assert info["err_bound"] <= 2.0 * true
+
+
+def test_uncapped_sketch_round_keeps_eps_by_the_linear_budget():
+    m = [3] + [2] * 9
+    x = I.graded_tt(m, [1, 3, 6, 10, 12, 12, 12, 10, 6, 3, 1], decay=0.5, seed=41)
+    nat = _natural(m)
+    ells = [1] + [min(nat[k], 14) for k in range(1, len(m))] + [1]
+    om = I.gaussian_sketch(m, ells, seed=42)
+    for eps in (1e-2, 1e-4):
+        z, info = SK.sketch_round(x, om, eps)
+        X, Z = T.full(x), T.full(z)
+        assert info["ok"]
+        assert np.linalg.norm(X - Z) <= info["err_bound"] * np.linalg.norm(X) * (1 + 1e-12)
+        assert info["err_bound"] <= eps * (1 + 1e-12)
