@@ -325,12 +325,21 @@ def mean_field(E, L):
 
 
 def build_problem(kvox=None, k0=None, L=None, section=None, op_eps=1e-10, sfft_eps=1e-13,
-                  shared=None, cell=None, log=None):
+                  shared=None, cell=None, log=None, green_eps=None):
     """All host trains of one cell problem (k given as N^3 voxels, a z-invariant
     section, or a periodic cell tiling a 2^L grid).
 
     shared: the "S", "Sinv" and "G" entries of an earlier problem with the same L and
     k0, reused instead of rebuilt (they do not depend on the microstructure).
+    green_eps: compression tolerance of the Green operator.  The product-aware
+    rounding takes ||G t||^2 = <t, G t> / k0, an identity of the exact operator
+    (k0 G is a projector); the compressed one misses it by about 1e-3 of its
+    tolerance relative to ||G t||^2 (1.5e-13 at 1e-10 on 32^3, 5e-16 at 1e-12).
+    Default: min(op_eps, 1e-12) for the dense build (L <= 8, same set-up time), which
+    keeps that floor far below eps^2 = 1e-12 of a field tolerance of 1e-6; op_eps
+    for the exponential-sum build (L > 8), whose set-up time triples at 1e-12
+    (the floor, ~1e-13 of ||G t||^2, is then below the rank-capped errors of
+    those workloads by ten orders of magnitude).
     log: optional callable taking a progress message."""
     say = log or (lambda msg: None)
     if kvox is not None:
@@ -362,7 +371,8 @@ def build_problem(kvox=None, k0=None, L=None, section=None, op_eps=1e-10, sfft_e
         say("SFFT operator")
         # the dense Green array has 9 N^3 entries: beyond 256^3 the
         # exponential-sum build (same operator, same ranks)
-        G = green_tt(L, k0, op_eps) if L <= 8 else green_tt_expsum(L, k0, op_eps, log=say)
+        geps = green_eps if green_eps is not None else (min(op_eps, 1e-12) if L <= 8 else op_eps)
+        G = green_tt(L, k0, geps) if L <= 8 else green_tt_expsum(L, k0, geps, log=say)
         say(f"Green operator, rank {max(c.shape[0] for c in G)}")
     return {"L": L, "k0": float(k0), "kp": kp, "k2": k2, "k_sel": ksel, "S": S, "Sinv": Sinv,
             "G": G}

@@ -4,8 +4,9 @@ field rank cap 128), in the launch configuration of `bench.py --config cyl1024`
 dense Moulinec-Suquet iterate of the exact 2D reduction of this z-invariant
 cell (oracle), lifted to 3D as a train with all-ones z cores.  The cap binds
 hard here (the exact iterate's best rank-128 train is 4 % off), so the bound
-is a small multiple of that best-approximation error: a wrong operator, bit
-order or Green build is off by O(1)."""
+is a small multiple of that best-approximation error (2.5x; the four capped
+roundings of the first iteration measure 2.2x with the fixed sketch seed): a
+wrong operator, bit order or Green build is off by O(1)."""
 import math
 
 import numpy as np
@@ -23,7 +24,8 @@ def test_cylinders_1024_first_iterate_matches_dense_2d_reduction():
     from paper_2512_07811_amd import qtt as q
     L, k0, rmax = 10, 25.5, 128
     sec = I.cylinders_section(L, 4)
-    prob = P.build_problem(section=sec, k0=k0)
+    print("[large] 1024^3 fibre cell: building operands", flush=True)
+    prob = P.build_problem(section=sec, k0=k0, log=lambda m: print(f"[large] {m}", flush=True))
     ctx = q.Context(0)
     try:
         ops, e = P.upload(prob, [[1.0, 0.0, 0.0]], rmax)
@@ -50,10 +52,10 @@ def test_cylinders_1024_first_iterate_matches_dense_2d_reduction():
         assert abs(nrm - best["norm"]) <= 1e-10 * nrm
         dist = math.sqrt(max(aa + bb - 2.0 * ab.real, 0.0)) / nrm
         print(f"1024^3 first iterate: distance {dist:.4f}, best rank-{rmax} error {best['err']:.4f}")
-        assert dist <= 4.0 * best["err"]
+        assert dist <= 2.5 * best["err"]
         # the mean of the iterate is E (Gamma(0) = 0) up to the rounding
         M = q.DeviceTT.from_cores([P.mean_field(np.array([1.0, 0.0, 0.0]), L)])
         mean_x = q.tt_dot(ctx, M, e).cpu().numpy()[0].real / 2.0 ** (3 * L)
-        assert abs(mean_x - 1.0) <= 4.0 * best["err"]
+        assert abs(mean_x - 1.0) <= 2.5 * best["err"]
     finally:
         ctx.close()
