@@ -311,6 +311,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-split", action="store_true",
                     help="skip the untimed kernel-class timing iterations")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="learned mode: skip the SVD-truncated window")
     ap.add_argument("--round-ranks", default="64,128",
                     help="uniform ranks of the tt_round micro-benchmark ('' skips it)")
     ap.add_argument("--round-batches", default="1,64",
@@ -446,7 +448,7 @@ def main():
     dt, res, cnt = window(opts, args.mode)
     A_main = a_eff(qtt, ctx, ops, e, ops.L)
     comparison = accuracy = None
-    if args.mode == "learned":
+    if args.mode == "learned" and not args.no_compare:
         dt_sk, res_sk, cnt_sk = window(sk_opts, "SVD-truncated")
         A_sk = a_eff(qtt, ctx, ops, e, ops.L)
         gap = float(np.linalg.norm(A_main - A_sk) / np.linalg.norm(A_sk))
@@ -474,7 +476,8 @@ def main():
     # kernel classes of both paths, one untimed iteration per class
     split = {}
     if not args.no_split:
-        paths = [(args.mode, opts)] + ([("svd_truncated", sk_opts)] if args.mode == "learned" else [])
+        paths = [(args.mode, opts)] + ([("svd_truncated", sk_opts)]
+                                       if args.mode == "learned" and not args.no_compare else [])
         for name, o in paths:
             e.data.copy_(snap[0])
             e.ranks.copy_(snap[1])

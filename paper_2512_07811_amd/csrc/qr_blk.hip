@@ -324,6 +324,23 @@ __device__ inline cplx grp_sum(cplx v) {
 // Writes the panel back (R on and above the diagonal), V (explicit, zero
 // above the diagonal, one on it, zero columns past the last reflector) and T.
 constexpr int QP_CH = 6;
+
+// Column q of the panel's T: T[a][q] = -t_q sum_{c=a}^{q-1} T[a][c] z_c for
+// a < q, T[q][q] = t_q.  Eight consecutive threads share a row a (strided
+// partial sums, then an 8-lane sum), so the step's critical path holds about
+// q / 8 LDS reads instead of q.  Rows a <= q need 8 (q + 1) <= NT threads.
+template <int NT, int NB>
+__device__ inline void qp_t_column(int q, int tid, cplx (*Ts)[NB], const cplx* z,
+                                   const double* tl) {
+  const int a = tid >> 3, l8 = tid & 7;
+  if (a > q) return;          // whole 8-lane groups leave together
+  cplx acc = czero();
+  for (int c = a + l8; c < q; c += 8) cfma(acc, Ts[a][c], z[c]);
+  acc.x = grp_sum<8>(acc.x);
+  acc.y = grp_sum<8>(acc.y);
+  if (l8 == 0) Ts[a][q] = (a == q) ? make_double2(tl[q], 0.0) : cscale(acc, -tl[q]);
+}
+
 template <int NT, int GL, int RPL>
 __global__ __launch_bounds__(NT) void k_qrp_panel(int j0, Dim Md, Dim Nd, cplx* __restrict__ M,
                                                     int64_t sM, int ld, cplx* __restrict__ V,
@@ -332,6 +349,7 @@ __global__ __launch_bounds__(NT) void k_qrp_panel(int j0, Dim Md, Dim Nd, cplx* 
                                                     int64_t sT) {
   constexpr int NB = NT / GL;
   constexpr int MP = GL * RPL;
+  static_assert(8 * NB <= NT, "T columns take eight threads per row");
   const int b = blockIdx.x;
   const int m = dimv(Md, b), n = dimv(Nd, b), s = min(m, n);
   if (j0 >= s) return;
@@ -357,15 +375,18 @@ __global__ __launch_bounds__(NT) void k_qrp_panel(int j0, Dim Md, Dim Nd, cplx* 
   for (int jj = 0; jj < nbw; ++jj) {
     const int j = j0 + jj, buf = jj & 1;
     if (grp == jj) {
-      double sig2 = 0.0;
+      double s0 = 0.0, s1 = 0.0;
       cplx al = czero();
 #pragma unroll
       for (int r = 0; r < RPL; ++r) {
         const int i = j0 + l + GL * r;
-        if (i > j && i < m) sig2 += cabs2(a[r]);
+        if (i > j && i < m) {
+          if (r & 1) s1 += cabs2(a[r]);
+          else s0 += cabs2(a[r]);
+        }
         if (i == j) al = a[r];
       }
-      sig2 = grp_sum<GL>(sig2);
+      const double sig2 = grp_sum<GL>(s0 + s1);
       al = grp_sum<GL>(al);   // one lane contributes
       double t;
       cplx beta, iu0;
@@ -403,29 +424,24 @@ __global__ __launch_bounds__(NT) void k_qrp_panel(int j0, Dim Md, Dim Nd, cplx* 
     __syncthreads();
     const double t = tl[jj];
     // T column jj - 1 from the previous step's z (published by the barrier)
-    if (jj >= 1 && tid < jj) {
-      const int q = jj - 1;
-      if (tid == q) {
-        Ts[q][q] = make_double2(tl[q], 0.0);
-      } else {
-        cplx acc = czero();
-        for (int cc = tid; cc < q; ++cc) cfma(acc, Ts[tid][cc], zsh[q & 1][cc]);
-        Ts[tid][q] = cscale(acc, -tl[q]);
-      }
-    }
+    if (jj >= 1) qp_t_column<NT>(jj - 1, tid, Ts, zsh[(jj - 1) & 1], tl);
     const cplx* u = ush[buf];
     // the reflector is read from LDS in chunks of QP_CH rows (the empty asm
     // statements keep the compiler from loading all of it at once: the
     // registers hold the column)
     if (grp > jj && have && t != 0.0) {
-      cplx w = czero();
+      // two interleaved partial sums halve the dependent FMA chain
+      cplx w0 = czero(), w1 = czero();
 #pragma unroll
       for (int r0 = 0; r0 < RPL; r0 += QP_CH) {
         asm volatile("" ::: "memory");
 #pragma unroll
-        for (int r = r0; r < r0 + QP_CH && r < RPL; ++r) cfma(w, cconj(u[l + GL * r]), a[r]);
+        for (int r = r0; r < r0 + QP_CH && r < RPL; ++r) {
+          if (r & 1) cfma(w1, cconj(u[l + GL * r]), a[r]);
+          else cfma(w0, cconj(u[l + GL * r]), a[r]);
+        }
       }
-      w = grp_sum<GL>(w);
+      cplx w = grp_sum<GL>(cadd(w0, w1));
       const cplx f = cscale(w, -t);
 #pragma unroll
       for (int r0 = 0; r0 < RPL; r0 += QP_CH) {
@@ -435,31 +451,24 @@ __global__ __launch_bounds__(NT) void k_qrp_panel(int j0, Dim Md, Dim Nd, cplx* 
       }
     } else if (grp < jj) {
       // rows i >= j > c: a holds this column's reflector there
-      cplx z = czero();
+      cplx z0 = czero(), z1 = czero();
 #pragma unroll
       for (int r0 = 0; r0 < RPL; r0 += QP_CH) {
         asm volatile("" ::: "memory");
 #pragma unroll
         for (int r = r0; r < r0 + QP_CH && r < RPL; ++r) {
           const int i = j0 + l + GL * r;
-          if (i >= j) cfma(z, cconj(a[r]), u[l + GL * r]);
+          if (i < j) continue;
+          if (r & 1) cfma(z1, cconj(a[r]), u[l + GL * r]);
+          else cfma(z0, cconj(a[r]), u[l + GL * r]);
         }
       }
-      z = grp_sum<GL>(z);
+      const cplx z = grp_sum<GL>(cadd(z0, z1));
       if (l == 0) zsh[buf][grp] = z;
     }
   }
   __syncthreads();
-  {
-    const int q = nbw - 1;
-    if (tid == q) {
-      Ts[q][q] = make_double2(tl[q], 0.0);
-    } else if (tid < q) {
-      cplx acc = czero();
-      for (int cc = tid; cc < q; ++cc) cfma(acc, Ts[tid][cc], zsh[q & 1][cc]);
-      Ts[tid][q] = cscale(acc, -tl[q]);
-    }
-  }
+  qp_t_column<NT>(nbw - 1, tid, Ts, zsh[(nbw - 1) & 1], tl);
   // the panel back (R part) and the explicit reflectors
 #pragma unroll
   for (int r = 0; r < RPL; ++r) {
