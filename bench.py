@@ -333,10 +333,6 @@ def main():
     batched = "instances" in cfg
     if batched and args.instances > 0:
         cfg["instances"] = args.instances
-    if batched and args.mode == "learned":
-        print("[bench] learned rounding runs one field at a time; batched config uses --mode sketch",
-              file=sys.stderr, flush=True)
-        args.mode = "sketch"
     profiled = under_profiler()
     # host work that forks worker processes runs before anything touches the GPU
     cpu = None

@@ -115,9 +115,9 @@ qt_status qt_ctx_sync(qt_ctx ctx);
 
 /* Device event counters since creation (or the last reset), int64 each:
  *  [0] truncated SVDs, [1] Jacobi sweeps they used, [2] sketch roundings whose
- *  error exceeded the budget, [3] learned roundings that fell back to SVD
- *  rounding, [4] structured-GEMM flops, [5] structured-GEMM bytes,
- *  [6] learned (fixed predicted rank) roundings attempted.
+ *  error exceeded the budget, [3] learned instance-roundings that fell back to
+ *  SVD rounding, [4] structured-GEMM flops, [5] structured-GEMM bytes,
+ *  [6] learned (fixed predicted rank) instance-roundings attempted.
  *  Synchronizes the stream. */
 qt_status qt_ctx_counters(qt_ctx ctx, int64_t* out, int32_t n, int32_t reset);
 
@@ -285,18 +285,23 @@ qt_status homogenize(qt_ctx ctx, const qt_operands* ops, const qt_tt* k_sel, qt_
 
 /* ---------------------------------------------------------------------------
  * Learned-rank rounding (rank predictor).  The method's fixed-rank truncation
- * (Sec. 3, truncated SVD at a given rank) and its coarse-grained rank classes
- * r_c = c * r_0 (Sec. 5.1) are combined with a small FP32 MLP that predicts
- * each bond's rank from the previous iteration's sketched spectrum, so that the
- * product-aware rounding can skip its SVD truncation sweep.  The exact
- * a-posteriori error decides: above eps, or above max(eps, accept * e_s) when
- * e_s > eps, where e_s is the error of the last SVD-truncated rounding of the
- * same step (e_s > eps only where the rank cap binds), the step is redone with
- * the SVD-truncated sketch rounding (fallback, counted).  The tolerance eps
- * always holds; accept only scales the comparison with the SVD truncation
- * where the cap binds.  With
- * accept <= 1 every rounding is as accurate as the SVD truncation would be (to
- * the drift of e_s between its refreshes, which happen at every fallback).
+ * (Sec. 2.2, "prescribe a fixed number of singular values") and its
+ * coarse-grained rank classes r_c = c * r_0 (Sec. 5.1) are combined with a
+ * small FP32 MLP that predicts each bond's rank from the previous iteration's
+ * sketched spectrum, so that the product-aware rounding can skip its SVD
+ * truncation sweep.  Batches: every instance's features are predicted, and
+ * the sketch takes the largest prediction of the batch per bond.  The exact
+ * a-posteriori error of each instance decides, on the device: above eps, or
+ * above max(eps, accept * e_s) when e_s > eps, where e_s is the error estimate
+ * (sqrt(e_proj^2 + tails^2)) of the last SVD-truncated rounding of the same
+ * step and instance (e_s > eps only where the rank cap binds), the instance is
+ * redone with the SVD-truncated sketch rounding (fallback, counted; the host
+ * reads only the number of fallbacks and skips the redo when it is zero).  The
+ * tolerance eps always holds; accept only scales the comparison with the SVD
+ * truncation where the cap binds.  With accept <= 1 every rounding is as
+ * accurate as the SVD truncation would be (to the drift of e_s between its
+ * refreshes, which happen at every fallback).  ls_iterate does not capture
+ * the learned path in a graph (its predicted widths are launch parameters).
  * ------------------------------------------------------------------------- */
 
 /* Number of floats in the MLP parameter vector for n_in inputs and n_cls
@@ -353,6 +358,18 @@ qt_status qt_set_predictor(qt_ctx ctx, const float* params, int32_t n_cls, float
 /* Forgets the previous-iteration features and reference errors (call before
  * iterating a new field from its start). */
 qt_status qt_learn_reset(qt_ctx ctx);
+
+/* Learned-rounding log (diagnostics): while enabled (capacity > 0), every
+ * learned rounding appends one row per instance of QT_LEARN_LOG_COLS = 6
+ * doubles: iteration count of the context, step (0 Hadamard, 1 SFFT, 2 Green,
+ * 3 inverse SFFT), instance, its exact relative error, the reference e_s of
+ * that step and instance (0 before the first SVD-truncated rounding), and 1 if
+ * kept, 0 if it fell back.  capacity == 0 disables and frees the log.
+ * qt_learn_log_get copies min(count, max_rows) rows to the HOST buffer rows
+ * and returns the number logged in *count (synchronizes the stream).
+ * Errors: QT_EINVAL when the log is not enabled or an argument is null. */
+qt_status qt_learn_log_enable(qt_ctx ctx, int32_t capacity);
+qt_status qt_learn_log_get(qt_ctx ctx, double* rows, int32_t max_rows, int32_t* count);
 
 #ifdef __cplusplus
 }

@@ -543,143 +543,184 @@ static qt_tt view_caps(const qt_tt& t, const std::vector<int32_t>& caps) {
 }
 
 // One product-aware rounding step s of the iteration.  Learned path: fixed
-// ranks predicted by the MLP from the previous iteration's features; accepted
-// when the exact a-posteriori error sqrt(||x||^2 - ||x~||^2)/||x|| is at most
-// eps, or, where the last SVD-truncated rounding of this step could not meet
-// eps (its error e_s > eps: the rank cap binds), at most max(eps, accept * e_s);
-// otherwise redone with the SVD-truncated sketch (fallback).  The factor never
-// relaxes eps.
+// widths predicted by the MLP from the previous iteration's features (the
+// largest prediction over the batch, per bond); instance b keeps its learned
+// rounding when its exact a-posteriori error sqrt(||x||^2 - ||x~||^2)/||x|| is
+// at most eps, or, where the last SVD-truncated rounding of this step and
+// instance could not meet eps (its error estimate e_s > eps: the rank cap
+// binds), at most max(eps, accept * e_s).  The decision is taken on the
+// device per instance; the host reads the number of instances that fell back
+// and, when there are any, runs the SVD-truncated rounding of the whole batch
+// into the spare buffer and copies it over the instances that fell back.  The
+// factor never relaxes eps.
+// lo_flags (device [B]): 1 where the output is left-orthogonal (a kept
+// fixed-rank rounding, weight in the last core), 0 where it is right-
+// orthogonal (SVD-truncated, weight in core 0).
+__global__ void k_fill_i32(int64_t count, int32_t v, int32_t* p) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = v;
+}
+
+// out <- spare for the instances b with keep[b] == 0 (cores of every slot,
+// ranks, error and estimate)
+__global__ void k_take_fallback(int64_t per, int n1, int B, const int32_t* __restrict__ keep,
+                                const cplx* __restrict__ spare, const int32_t* __restrict__ rk2,
+                                const double* __restrict__ err2, cplx* out, int32_t* rk,
+                                double* err) {
+  const int b = blockIdx.y;
+  if (keep[b]) return;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < per;
+       e += (int64_t)gridDim.x * blockDim.x)
+    out[(int64_t)b * per + e] = spare[(int64_t)b * per + e];
+  if (blockIdx.x == 0) {
+    for (int k = threadIdx.x; k < n1; k += blockDim.x) rk[(int64_t)b * n1 + k] = rk2[(int64_t)b * n1 + k];
+    if (threadIdx.x == 0) {
+      err[b] = err2[b];
+      err[B + b] = err2[B + b];
+    }
+  }
+}
+
+__global__ void k_keep_to_flags(int B, const int32_t* __restrict__ keep, int32_t* lo) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < B) lo[b] = keep[b];
+}
+
 static qt_status round_step(qt_ctx ctx, int step, const qt_mpo* A, const qt_tt* y,
                             const std::vector<int32_t>& ell_plan, const qt_round_opts& base,
                             const double* xn2, qt_tt* out, double* err_dev, uint64_t iter_id,
-                            bool learned, bool logging, bool* left_orth) {
-  const int n = y->n;
+                            bool learned, bool logging, int32_t* lo_flags, qt_tt* spare,
+                            double* err2) {
+  const int n = y->n, B = y->batch;
   LearnCtx* L = ctx->learn;
   const bool track = L && (learned || logging);
-  double* rd = track ? L->rdiag + (int64_t)step * (n + 1) * RD_MAX : nullptr;
+  double* rd = track ? L->rdiag_at(step) : nullptr;
   const size_t mark = ctx->ws_top;
   qt_round_opts so = base;
   so.mode = QT_ROUND_SKETCH;
   std::vector<int32_t> ell = ell_plan;
   const bool use_learned = learned && L->have_prev && L->params && !L->pred_ell[step].empty();
-  bool sketch_mode = true;
+  // the SVD-truncated rounding's error as the learned path's reference: the
+  // quadrature estimate (the reported bound adds the two parts linearly)
+  double* est_dev = err_dev + B;
   if (use_learned) {
     const int rcap = base.max_rank > 0 ? base.max_rank : (1 << 30);
     for (size_t k = 1; k + 1 < ell.size(); ++k)
       ell[k] = std::min({ell[k], L->pred_ell[step][k], rcap});
     so.mode = QT_ROUND_LEARNED;
-    sketch_mode = false;
   }
-  // the SVD-truncated rounding's error as the learned path's reference: the
-  // quadrature estimate (the reported bound adds the two parts linearly)
-  double* est_dev = err_dev + y->batch;
   QT_TRY(sround_impl(ctx, A, y, nullptr, nullptr, ell, &so, xn2, out, err_dev, nullptr,
                      iter_id * 4 + step, nullptr, 0, 0, rd, est_dev));
   ctx->ws_top = mark;
+  int32_t nfail = B;
   if (use_learned) {
-    double err = 0.0;
-    QT_HIP(hipMemcpyAsync(&err, err_dev, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    learn_decide(ctx, step, err_dev, base.eps);
+    QT_HIP(hipMemcpyAsync(&nfail, L->nfail, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
     QT_HIP(hipStreamSynchronize(ctx->stream));
-    ++L->learned_roundings;
-    const double es = L->ref_err[step];
-    const double ref = es > base.eps ? std::max(base.eps, (double)L->accept * es) : base.eps;
-    if (!(err <= ref)) {
-      ++L->fallbacks;
-      ell = ell_plan;
-      so.mode = QT_ROUND_SKETCH;
-      sketch_mode = true;
-      QT_TRY(sround_impl(ctx, A, y, nullptr, nullptr, ell, &so, xn2, out, err_dev, nullptr,
-                         iter_id * 4 + step + (1ull << 40), nullptr, 0, 0, rd, est_dev));
+    // kept instances: left-orthogonal fixed-rank output
+    k_fill_i32<<<(B + 255) / 256, 256, 0, ctx->stream>>>(B, 1, lo_flags);
+    if (nfail > 0) {
+      qt_round_opts fo = base;
+      fo.mode = QT_ROUND_SKETCH;
+      QT_TRY(sround_impl(ctx, A, y, nullptr, nullptr, ell_plan, &fo, xn2, spare, err2, nullptr,
+                         iter_id * 4 + step + (1ull << 40), nullptr, 0, 0, rd, err2 + B));
       ctx->ws_top = mark;
+      const int64_t per = out->inst_stride;
+      dim3 grid((unsigned)std::min<int64_t>((per + 255) / 256, 64), B);
+      k_take_fallback<<<grid, 256, 0, ctx->stream>>>(per, n + 1, B, L->keep, (const cplx*)spare->data,
+                                                     spare->ranks, err2, (cplx*)out->data,
+                                                     out->ranks, err_dev);
+      // fallen-back instances are right-orthogonal
+      k_keep_to_flags<<<(B + 255) / 256, 256, 0, ctx->stream>>>(B, L->keep, lo_flags);
+      learn_set_ref(ctx, step, est_dev, L->keep);
     }
   }
-  // a kept fixed-rank rounding is left-orthogonal with its weight in the last
-  // core; the SVD-truncated one is right-orthogonal with its weight in core 0
-  *left_orth = !sketch_mode;
-  if (track) learn_features(ctx, step, ell, xn2, base.eps, base.max_rank);
-  if (sketch_mode && logging) learn_log(ctx, step, out->ranks);
-  if (sketch_mode && learned) {
-    double err = 0.0;
-    QT_HIP(hipMemcpyAsync(&err, est_dev, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-    QT_HIP(hipStreamSynchronize(ctx->stream));
-    L->ref_err[step] = err;
+  if (!use_learned) {
+    k_fill_i32<<<(B + 255) / 256, 256, 0, ctx->stream>>>(B, 0, lo_flags);
+    if (learned && L) learn_set_ref(ctx, step, est_dev, nullptr);
   }
+  // the stored sketch R diagonals are the fallback's where one ran
+  if (track)
+    learn_features(ctx, step, (use_learned && nfail == 0) ? ell : ell_plan, xn2, base.eps,
+                   base.max_rank);
+  if (!use_learned && logging) learn_log(ctx, step, out->ranks);
   QT_HIP(hipGetLastError());
   return QT_OK;
 }
 
 // After an iteration: the features just written become "previous"; the
-// learned path predicts the next iteration's ranks with the MLP.
+// learned path predicts the next iteration's widths with the MLP.
 static qt_status learn_advance(qt_ctx ctx, bool learned, const std::vector<int32_t>* ells[4]) {
   LearnCtx* L = ctx->learn;
   if (!L) return QT_OK;
-  const int n = L->n;
-  const int cur = L->cur;
-  L->cur = 1 - cur;
+  L->cur = 1 - L->cur;
   L->have_prev = true;
+  ++L->iter;
   if (!learned || !L->params) return QT_OK;
-  // caps = plan sketch ranks per (step, bond); features of bond k at row k-1
-  std::vector<int32_t> caps(4 * QT_MAX_CORES, 1);
-  for (int s = 0; s < 4; ++s)
-    for (int k = 1; k < n; ++k) caps[s * QT_MAX_CORES + k - 1] = (*ells[s])[k];
-  int32_t* dcap = L->pred_at(1, 0);
-  int32_t* dpred = L->pred_at(0, 0);
-  QT_HIP(hipMemcpyAsync(dcap, caps.data(), sizeof(int32_t) * caps.size(), hipMemcpyHostToDevice,
-                        ctx->stream));
-  QT_TRY(qt_mlp_infer(ctx, L->params, L->feat_at(cur, 0), 4 * QT_MAX_CORES, QT_RANK_FEATURES,
-                      L->pred_cls, L->quantile, nullptr, dpred, dcap));
-  std::vector<int32_t> pr(4 * QT_MAX_CORES);
-  QT_HIP(hipMemcpyAsync(pr.data(), dpred, sizeof(int32_t) * pr.size(), hipMemcpyDeviceToHost,
-                        ctx->stream));
-  QT_HIP(hipStreamSynchronize(ctx->stream));
-  for (int s = 0; s < 4; ++s) {
-    L->pred_ell[s].assign(n + 1, 1);
-    for (int k = 1; k < n; ++k) L->pred_ell[s][k] = pr[s * QT_MAX_CORES + k - 1];
-  }
-  return QT_OK;
+  return learn_predict(ctx, ells);
 }
 
-// ||t||^2 of an orthogonalized train: the squared norm of its weight core.
-static void weight_norm2(hipStream_t st, const qt_tt& t, bool left_orth, double* out) {
-  const int n = t.n, rs = n + 1;
-  if (left_orth)
-    sumsq(st, t.batch, dref(t.ranks + n - 1, rs, t.modes[n - 1]), dconst(1),
-          (const cplx*)t.data + t.offsets[n - 1], t.inst_stride, out, 1.0);
-  else
-    sumsq(st, t.batch, dconst(1), dref(t.ranks + 1, rs, t.modes[0]), (const cplx*)t.data,
-          t.inst_stride, out, 1.0);
+// ||t||^2 of an orthogonalized train per instance: the squared norm of core
+// n-1 where lo[b] (left-orthogonal), of core 0 otherwise.
+__global__ void k_pick_norm(int B, const int32_t* lo, const double* last, const double* first,
+                            double* out) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < B) out[b] = lo[b] ? last[b] : first[b];
 }
+
+static void weight_norm2(hipStream_t st, const qt_tt& t, const int32_t* lo, double* tmp,
+                         double* out) {
+  const int n = t.n, rs = n + 1, B = t.batch;
+  sumsq(st, B, dref(t.ranks + n - 1, rs, t.modes[n - 1]), dconst(1),
+        (const cplx*)t.data + t.offsets[n - 1], t.inst_stride, tmp, 1.0);
+  sumsq(st, B, dconst(1), dref(t.ranks + 1, rs, t.modes[0]), (const cplx*)t.data,
+        t.inst_stride, tmp + B, 1.0);
+  k_pick_norm<<<(B + 127) / 128, 128, 0, st>>>(B, lo, tmp, tmp + B, out);
+}
+
+// Buffers of the learned path: spare outputs for the fallback (layout of each
+// step's output), its ranks and errors, per-instance orientation flags and
+// norm scratch.
+struct LearnBufs {
+  char* spare = nullptr;
+  int32_t* rS = nullptr;
+  double* err2 = nullptr;
+  int32_t* lo = nullptr;
+  double* ntmp = nullptr;
+};
 
 static qt_status iterate_once_sketch(qt_ctx ctx, const qt_operands* ops, qt_tt* e,
                                      const SketchPlan& P, const qt_round_opts& ro, char* bufA,
                                      char* bufB, int32_t* rA, int32_t* rB, double* dnorm,
                                      const double* dinv, double* xn2, double* err_dev,
                                      double* res_out, uint64_t iter_id, bool learned,
-                                     bool logging) {
-  const int B = e->batch, n = e->n, rs = n + 1;
+                                     bool logging, const LearnBufs& lb) {
+  const int B = e->batch, n = e->n;
   hipStream_t st = ctx->stream;
   const size_t mark = ctx->ws_top;
-  if (learned || logging) QT_TRY(learn_ensure(ctx, n));
-  bool lo = false;
+  if (learned || logging) QT_TRY(learn_ensure(ctx, n, B));
+  int32_t* lo = lb.lo;
+  qt_tt sp1 = P.l1.view(lb.spare, lb.rS, B), sp2 = P.l2.view(lb.spare, lb.rS, B);
+  qt_tt sp3 = P.l3.view(lb.spare, lb.rS, B), sp4 = P.l4.view(lb.spare, lb.rS, B);
   // tau = R(k' e)
   QT_TRY(sandwich_impl(ctx, &ops->K2, e, 1.0, xn2));
   ctx->ws_top = mark;
   qt_tt t1 = P.l1.view(bufA, rA, B);
   QT_TRY(round_step(ctx, 0, &ops->Kp, e, P.ell1, ro, xn2, &t1, err_dev, iter_id, learned, logging,
-                    &lo));
+                    lo, &sp1, lb.err2));
   qt_tt t1r = view_caps(t1, P.c1r);
   // tau^ = R(S tau);  ||S tau|| = ||tau|| (S unitary)
-  weight_norm2(st, t1r, lo, xn2);
+  weight_norm2(st, t1r, lo, lb.ntmp, xn2);
   qt_tt t2 = P.l2.view(bufB, rB, B);
   QT_TRY(round_step(ctx, 1, &ops->S, &t1r, P.ell2, ro, xn2, &t2, err_dev, iter_id, learned, logging,
-                    &lo));
+                    lo, &sp2, lb.err2));
   qt_tt t2r = view_caps(t2, P.c2r);
   // eps^ = R(G tau^);  ||G t||^2 = <t, G t>/k0
   QT_TRY(sandwich_impl(ctx, &ops->G, &t2r, 1.0 / ops->k0, xn2));
   ctx->ws_top = mark;
   qt_tt t3 = P.l3.view(bufA, rA, B);
   QT_TRY(round_step(ctx, 2, &ops->G, &t2r, P.ell3, ro, xn2, &t3, err_dev, iter_id, learned, logging,
-                    &lo));
+                    lo, &sp3, lb.err2));
   qt_tt t3r = view_caps(t3, P.c3r);
   // t = S E - eps^;  ||t||^2 by environments (no cancellation: Gamma(0) = 0
   // makes eps^ vanish at the zero frequency, where S E lives)
@@ -696,7 +737,7 @@ static qt_status iterate_once_sketch(qt_ctx ctx, const qt_operands* ops, qt_tt* 
   // e' = R(S^H t) = E - S^H eps^
   qt_tt t4 = P.l4.view(bufA, rA, B);
   QT_TRY(round_step(ctx, 3, &ops->Sinv, &ttr, P.ell4, ro, xn2, &t4, err_dev, iter_id, learned,
-                    logging, &lo));
+                    logging, lo, &sp4, lb.err2));
   qt_tt t4r = view_caps(t4, P.c4r);
   if (learned || logging) {
     const std::vector<int32_t>* ells[4] = {&P.ell1, &P.ell2, &P.ell3, &P.ell4};
@@ -728,6 +769,7 @@ struct Solver {
   double* dinv = nullptr;
   double* xn2 = nullptr;
   double* err = nullptr;
+  LearnBufs lb;
   bool learned = false;
   bool logging = false;
 };
@@ -745,7 +787,7 @@ static qt_status solver_setup(qt_ctx ctx, const qt_operands* ops, qt_tt* e,
   if (S.learned) {
     QT_CHECK(ctx->learn && ctx->learn->params, QT_EINVAL,
              "solver: learned rounding needs a predictor (qt_set_predictor)");
-    QT_CHECK(e->batch == 1, QT_EINVAL, "solver: learned rounding runs one field at a time");
+    QT_CHECK(e->batch <= 1024, QT_EINVAL, "solver: learned rounding takes at most 1024 fields");
   }
   if (S.sketch) {
     QT_CHECK(ops->Kp.n == n && ops->K2.n == n && ops->k0 > 0.0, QT_EINVAL,
@@ -763,9 +805,14 @@ static qt_status solver_setup(qt_ctx ctx, const qt_operands* ops, qt_tt* e,
     S.P = plan_iteration(ops, e, rmax);
     bytesA = S.P.bytesA; bytesB = S.P.bytesB; ws = iteration_bytes(S.P, B, rmax) - S.P.bytesA - S.P.bytesB;
   }
+  // the learned path's fallback writes into a spare train of the largest step layout
+  size_t spare = 0;
+  if (S.learned)
+    spare = sizeof(cplx) * B * std::max({S.SP.l1.stride, S.SP.l2.stride, S.SP.l3.stride,
+                                         S.SP.l4.stride});
   ctx->ws_top = 0;
-  QT_TRY(ws_reserve(ctx, bytesA + bytesB + ws + extra + sizeof(int32_t) * B * (n + 1) * 2 +
-                             sizeof(double) * B * 5 + 8 * 256));
+  QT_TRY(ws_reserve(ctx, bytesA + bytesB + ws + extra + spare + sizeof(int32_t) * B * (n + 1) * 3 +
+                             sizeof(double) * B * 9 + sizeof(int32_t) * B + 14 * 256));
   S.bufA = (char*)ws_take(ctx, bytesA);
   S.bufB = (char*)ws_take(ctx, bytesB);
   S.rA = (int32_t*)ws_take(ctx, sizeof(int32_t) * B * (n + 1));
@@ -776,6 +823,13 @@ static qt_status solver_setup(qt_ctx ctx, const qt_operands* ops, qt_tt* e,
   S.err = (double*)ws_take(ctx, sizeof(double) * 2 * B);   // bound, then estimate
   QT_CHECK(S.bufA && S.bufB && S.rA && S.rB && S.dnorm && S.dinv && S.xn2 && S.err, QT_ENOMEM,
            "iteration workspace");
+  S.lb.rS = (int32_t*)ws_take(ctx, sizeof(int32_t) * B * (n + 1));
+  S.lb.err2 = (double*)ws_take(ctx, sizeof(double) * 2 * B);
+  S.lb.lo = (int32_t*)ws_take(ctx, sizeof(int32_t) * B);
+  S.lb.ntmp = (double*)ws_take(ctx, sizeof(double) * 2 * B);
+  if (spare) S.lb.spare = (char*)ws_take(ctx, spare);
+  QT_CHECK(S.lb.rS && S.lb.err2 && S.lb.lo && S.lb.ntmp && (!spare || S.lb.spare), QT_ENOMEM,
+           "iteration workspace (learned path)");
   std::vector<double> inv(B);
   const double N3 = std::ldexp(1.0, 3 * ops->L);
   for (int b = 0; b < B; ++b) inv[b] = 1.0 / (ops->E_norm[b] * std::sqrt(N3));
@@ -788,7 +842,7 @@ static qt_status solver_step(qt_ctx ctx, const qt_operands* ops, qt_tt* e, const
   if (S.sketch) {
     uint64_t id = ctx->sketch_counter++;
     return iterate_once_sketch(ctx, ops, e, S.SP, ro, S.bufA, S.bufB, S.rA, S.rB, S.dnorm, S.dinv,
-                               S.xn2, S.err, res_out, id, S.learned, S.logging);
+                               S.xn2, S.err, res_out, id, S.learned, S.logging, S.lb);
   }
   return iterate_once(ctx, ops, e, S.P, ro, S.bufA, S.bufB, S.rA, S.rB, S.dnorm, S.dinv, res_out);
 }
@@ -816,7 +870,7 @@ static qt_status iterate_graph(qt_ctx ctx, const qt_operands* ops, qt_tt* e, con
   hipError_t he = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
   if (he == hipSuccess) {
     st = iterate_once_sketch(ctx, ops, e, S.SP, ro, S.bufA, S.bufB, S.rA, S.rB, S.dnorm, S.dinv,
-                             S.xn2, S.err, residual_out ? res_tmp : nullptr, 0, false, false);
+                             S.xn2, S.err, residual_out ? res_tmp : nullptr, 0, false, false, S.lb);
     k_inc_u64<<<1, 1, 0, ctx->cap_stream>>>(ctx->dev_iter);
     hipError_t he2 = hipStreamEndCapture(ctx->cap_stream, &graph);
     if (he == hipSuccess) he = he2;
@@ -974,9 +1028,6 @@ qt_status qt_ctx_counters(qt_ctx ctx, int64_t* out, int32_t n, int32_t reset) {
   QT_HIP(hipMemcpyAsync(h, ctx->counters, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
   QT_HIP(hipStreamSynchronize(ctx->stream));
   for (int i = 0; i < n && i < CNT_N; ++i) out[i] = (int64_t)h[i];
-  if (ctx->learn && n > CNT_FALLBACK) out[CNT_FALLBACK] += ctx->learn->fallbacks;
-  if (ctx->learn && n > 6) out[6] += ctx->learn->learned_roundings;
-  if (reset && ctx->learn) { ctx->learn->fallbacks = 0; ctx->learn->learned_roundings = 0; }
   if (reset) QT_HIP(hipMemsetAsync(ctx->counters, 0, sizeof(h), ctx->stream));
   return QT_OK;
 }

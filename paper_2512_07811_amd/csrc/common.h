@@ -236,7 +236,7 @@ __host__ __device__ inline double* status_diag(int32_t* status) {
 
 // Device event counters (int64, indices below), read with qt_ctx_counters.
 enum : int32_t { CNT_SVD_CALLS = 0, CNT_SVD_SWEEPS = 1, CNT_SKETCH_FAIL = 2, CNT_FALLBACK = 3,
-                 CNT_GEMM_FLOPS = 4, CNT_GEMM_BYTES = 5, CNT_N = 8 };
+                 CNT_GEMM_FLOPS = 4, CNT_GEMM_BYTES = 5, CNT_LEARNED = 6, CNT_N = 8 };
 
 // Kernel classes that can be timed with events (qt_ctx_profile).
 enum : int32_t { PROF_GEMM = 1, PROF_QR = 2, PROF_SVD = 4 };

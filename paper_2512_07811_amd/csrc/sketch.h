@@ -18,8 +18,8 @@ SketchWs sketch_ws_layout(const qt_mpo* A, const qt_tt* y, const std::vector<int
 // Randomize-then-orthogonalize of x = A (*) y with sketch cores omega (slot k at
 // om_off[k], shape (ell[k], p_k, ell[k+1]), shared by all instances).  out gets
 // left-orthogonal cores 0..n-2 and the centre in core n-1; ynorm2[b] = ||x~||^2.
-// rdiag (optional): [n+1][RD_MAX] sorted |R_jj| of the QR of Y_k written at
-// bond k+1 (instance 0), the input of the rank-predictor features.
+// rdiag (optional): [B][n+1][RD_MAX] sorted |R_jj| of the QR of Y_k written at
+// bond k+1 of each instance, the input of the rank-predictor features.
 constexpr int RD_MAX = 128;
 qt_status sketch_impl(qt_ctx ctx, const qt_mpo* A, const qt_tt* y, const cplx* omega,
                       const std::vector<int64_t>& om_off, const std::vector<int32_t>& ell,

@@ -145,10 +145,15 @@ SketchWs sketch_ws_layout(const qt_mpo* A, const qt_tt* y, const std::vector<int
   return w;
 }
 
-// |R_jj| of the sketch QR at bond k+1, sorted descending (instance 0)
-__global__ void k_rdiag(const cplx* R, int ldr, const int32_t* s_rank, double* out) {
+// |R_jj| of the sketch QR at bond k+1, sorted descending; block b handles
+// instance b (R slice sR, rank s_rank[b * rs], output slice so)
+__global__ void k_rdiag(const cplx* R, int64_t sR, int ldr, const int32_t* s_rank, int rs,
+                        double* out, int64_t so) {
   __shared__ double v[RD_MAX];
-  const int s = min(*s_rank, RD_MAX);
+  const int b = blockIdx.x;
+  R += b * sR;
+  out += b * so;
+  const int s = min(s_rank[(int64_t)b * rs], RD_MAX);
   for (int j = threadIdx.x; j < RD_MAX; j += blockDim.x)
     v[j] = j < s ? sqrt(cabs2(R[(int64_t)j * ldr + j])) : 0.0;
   __syncthreads();
@@ -293,7 +298,9 @@ qt_status sketch_impl(qt_ctx ctx, const qt_mpo* A, const qt_tt* y, const cplx* o
     else
       qr_auto(st, B, lk * p, lk1, dref(ro + k, rs, p), dconst(lk1), Yb, iY, Wq, iY, tau, w.tau,
               Od + out->offsets[k], out->inst_stride, Rb, w.R, ro + k + 1, rs);
-    if (rdiag) k_rdiag<<<1, 128, 0, st>>>(Rb, lk1, ro + k + 1, rdiag + (int64_t)(k + 1) * RD_MAX);
+    if (rdiag)
+      k_rdiag<<<B, 128, 0, st>>>(Rb, w.R, lk1, ro + k + 1, rs, rdiag + (int64_t)(k + 1) * RD_MAX,
+                                 (int64_t)(n + 1) * RD_MAX);
     // M_k = Q_k^H Z   (s' x R_{k+1})
     gemm_ex(st, B, 1, 1, dref(ro + k + 1, rs), dref(ry + k + 1, rs, rd1), dref(ro + k, rs, p), lk1,
             rd1 * y->cap[k + 1],

@@ -26,7 +26,8 @@ EXPORTS = ["qt_ctx_create", "qt_ctx_destroy", "qt_last_error", "qt_ctx_sync",
            "tt_hadamard",
            "tt_mpo_apply", "tt_add", "tt_round", "tt_round_noalloc", "tt_dot", "tt_sketch_round", "tt_sandwich",
            "ls_iterate", "homogenize", "qt_mlp_num_params", "qt_mlp_train_step", "qt_mlp_infer",
-           "qt_ranklog_enable", "qt_ranklog_get", "qt_set_predictor", "qt_learn_reset"]
+           "qt_ranklog_enable", "qt_ranklog_get", "qt_set_predictor", "qt_learn_reset",
+           "qt_learn_log_enable", "qt_learn_log_get"]
 
 
 class QtError(RuntimeError):
@@ -110,6 +111,8 @@ def load_library(path: str = LIB_PATH):
     lib.qt_ranklog_get.argtypes = [vp, vp, vp, i32, C.POINTER(C.c_int32)]
     lib.qt_set_predictor.argtypes = [vp, vp, i32, f32, f32]
     lib.qt_learn_reset.argtypes = [vp]
+    lib.qt_learn_log_enable.argtypes = [vp, i32]
+    lib.qt_learn_log_get.argtypes = [vp, vp, i32, C.POINTER(C.c_int32)]
     for name in EXPORTS:
         if name not in ("qt_ctx_destroy", "qt_last_error"):
             getattr(lib, name).restype = C.c_int32
@@ -552,3 +555,22 @@ def set_predictor(ctx: Context, params, n_cls: int, quantile: float = 0.9,
 
 def learn_reset(ctx: Context):
     _check(ctx.lib.qt_learn_reset(ctx.h))
+
+
+LEARN_LOG_COLS = 6
+
+
+def learn_log_enable(ctx: Context, capacity: int):
+    _check(ctx.lib.qt_learn_log_enable(ctx.h, capacity))
+
+
+def learn_log_get(ctx: Context):
+    """Rows (iteration, step, instance, error, reference, kept) of the learned-
+    rounding log as a host float64 array [count, 6]."""
+    cnt = C.c_int32()
+    _check(ctx.lib.qt_learn_log_get(ctx.h, None, 0, C.byref(cnt)))
+    rows = np.zeros((max(cnt.value, 1), LEARN_LOG_COLS), dtype=np.float64)
+    if cnt.value:
+        _check(ctx.lib.qt_learn_log_get(ctx.h, rows.ctypes.data_as(C.c_void_p), cnt.value,
+                                        C.byref(cnt)))
+    return rows[:cnt.value]

@@ -348,3 +348,83 @@ def test_ablation_trained_network_saves_work(q, cell, trained):
         c2.close()
     print("ablation", {"sketch": cnt_sk, "trained": cnt_ln, "untrained": cnt_un})
     assert np.max(np.abs(res_un - res_sk)) < 1e-4 * np.max(res_sk)
+
+
+def test_batched_learned_matches_svd_path(q, cell, trained):
+    # three loads of the cell in one batch: per-instance features and
+    # acceptance on the device, the largest prediction of the batch per bond;
+    # every rounding meets eps (cap above the ranks), so each field's A_eff
+    # agrees with the batched SVD-truncated path to 1e-6
+    from paper_2512_07811_amd import operands as P
+    c, pred, X, Y, A_sk1, its_sk1, hist = trained
+    loads = [[1.0, 0.0, 0.0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0]]
+    runs = {}
+    for mode in (q.ROUND_SKETCH, q.ROUND_LEARNED):
+        ops, e = P.upload(cell[1], loads, RMAX)
+        c.counters(reset=True)
+        A, its, res, st = q.homogenize(c, ops, e, sketch_opts(q, mode))
+        runs[mode] = (A, its, c.counters(reset=True))
+        assert st == q.QT_OK
+    (A_s, its_s, _), (A_l, its_l, cnt) = runs[q.ROUND_SKETCH], runs[q.ROUND_LEARNED]
+    assert cnt["learned_roundings"] > 0
+    for b in range(3):
+        assert abs(A_l[b, b] - A_s[b, b]) < 1e-6 * abs(A_s[b, b])
+        assert abs(its_l[b] - its_s[b]) <= 2
+    # cubic symmetry of the sphere: the three diagonal entries agree
+    assert np.ptp(np.diag(A_l)) < 1e-5 * A_l[0, 0]
+
+
+def test_capped_learned_roundings_obey_the_acceptance_rule(q, cell, trained):
+    # rank cap 12 below the cell's ranks: every SVD-truncated error exceeds eps
+    # and the learned roundings are judged against accept * e_s.  The device's
+    # rounding log holds each instance's exact learned error (the fixed-rank
+    # projection's, equal to the oracle's dense error: test_gpu_aposteriori) and
+    # its reference; kept <=> error <= max(eps, accept e_s) where e_s > eps,
+    # error <= eps elsewhere; fallbacks counted; and the residual history stays
+    # close to the SVD-truncated path's
+    from paper_2512_07811_amd import learned
+    from paper_2512_07811_amd import operands as P
+    c, pred, X, Y, A_sk1, its_sk1, hist = trained
+    rmax, eps, accept = 12, 1e-8, 1.25
+    loads = [[1.0, 0.0, 0.0], [0.0, 1.0, 0.0]]
+    ctx2 = q.Context(0)
+    try:
+        n_cls = learned.n_classes(rmax)
+        ops, e = P.upload(cell[1], loads, rmax)
+        opts_s = q.solve_opts(eps, rmax, tol=1e-12, max_iter=6, mode=q.ROUND_SKETCH, oversample=4,
+                              seed=3)
+        q.ranklog_enable(ctx2, 100000, n_cls)
+        q.homogenize(ctx2, ops, e, opts_s)
+        Xl, Yl = q.ranklog_get(ctx2)
+        q.ranklog_enable(ctx2, 0, n_cls)
+        p2 = learned.RankPredictor(ctx2, n_cls=n_cls, seed=7)
+        p2.train(Xl, Yl, epochs=200)
+        p2.install(quantile=0.9, accept_factor=accept)
+        q.learn_log_enable(ctx2, 100000)
+        ops, e = P.upload(cell[1], loads, rmax)
+        opts_l = q.solve_opts(eps, rmax, tol=1e-12, max_iter=6, mode=q.ROUND_LEARNED,
+                              oversample=4, seed=3)
+        ctx2.counters(reset=True)
+        A_l, its_l, res_l, _ = q.homogenize(ctx2, ops, e, opts_l)
+        cnt = ctx2.counters(reset=True)
+        rows = q.learn_log_get(ctx2)
+        assert rows.shape[0] == cnt["learned_roundings"] > 0
+        err, ref, kept = rows[:, 3], rows[:, 4], rows[:, 5]
+        lim = np.where(ref > eps, np.maximum(eps, accept * ref), eps)
+        assert np.array_equal(kept == 1, err <= lim)
+        assert int(np.sum(kept == 0)) == cnt["learned_fallbacks"]
+        assert np.any((ref > eps) & (kept == 1))      # capped roundings were kept
+        assert set(np.unique(rows[:, 2]).astype(int)) == {0, 1}
+        ops, e = P.upload(cell[1], loads, rmax)
+        A_s, its_s, res_s, _ = q.homogenize(ctx2, ops, e, opts_s)
+        print(f"residuals learned {res_l[:, 0]}\n          svd-truncated {res_s[:, 0]}\n"
+              f"A_eff learned {np.diag(A_l[:, :2])} svd-truncated {np.diag(A_s[:, :2])}",
+              flush=True)
+        # capped: both iterations stall at the truncation level; their residual
+        # levels agree within a factor 2 and A_eff within the stall level
+        ratio = np.median(res_l[2:], axis=0) / np.median(res_s[2:], axis=0)
+        assert np.all((ratio > 0.5) & (ratio < 2.0))
+        gap = np.abs(np.diag(A_l[:, :2]) - np.diag(A_s[:, :2])) / np.abs(np.diag(A_s[:, :2]))
+        assert np.all(gap <= 20.0 * np.max(res_s[-1]))
+    finally:
+        ctx2.close()
