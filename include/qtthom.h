@@ -8,8 +8,14 @@
  *   error message is available from qt_last_error().  No C++ exception crosses
  *   the boundary.
  * Memory: all tensor data is device memory owned by the caller (the Python
- *   binding uses PyTorch allocations).  The library owns only its workspace,
- *   which it allocates at context creation or on first need and reuses.
+ *   binding uses PyTorch allocations).  A context made by qt_ctx_create owns
+ *   its workspace, which it allocates at creation or on first need and
+ *   reuses; a context made by qt_ctx_create_with_memory takes every device
+ *   buffer it needs (workspace, GEMM split-K partials, tile-timing output,
+ *   learned-rank state and logs) from one caller-owned block and never calls
+ *   hipMalloc after creation: a call that does not fit returns QT_ENOMEM
+ *   with the bytes it needed, and the size to pass is given by
+ *   qt_ctx_fixed_bytes() plus qt_workspace_query / qt_ls_workspace_query.
  * Streams: calls are asynchronous on the context's stream unless a host
  *   output is requested (then they synchronize that stream before returning).
  * Numbers: every TT is complex double, interleaved (re, im).  Core k of a TT
@@ -105,8 +111,34 @@ typedef struct {
 /* ---- context ------------------------------------------------------------ */
 
 /* Create a context on `device` using the borrowed hipStream_t `stream`
- * (NULL = default stream).  Reserves `ws_bytes` of workspace now (0 = lazily). */
+ * (NULL = default stream).  Reserves `ws_bytes` of workspace now (0 = lazily);
+ * the workspace grows (hipMalloc) when a call needs more. */
 qt_status qt_ctx_create(int device, void* stream, size_t ws_bytes, qt_ctx* out);
+
+/* Create a context whose device memory is all in the caller's block `mem`
+ * (device memory on `device`, 256-byte aligned, `mem_bytes` long, borrowed:
+ * the caller frees it after qt_ctx_destroy and must not touch it while the
+ * context lives).  The head of the block, qt_ctx_fixed_bytes() long, holds the
+ * status word, the event counters and the GEMM split-K partials (cleared by
+ * this call, which synchronizes); the rest is the workspace arena, from whose
+ * end persistent buffers (learned-rank state, rank and rounding logs) are
+ * taken when first needed.  No call on this context allocates device memory:
+ * one that needs more than is free returns QT_ENOMEM (its message gives the
+ * bytes) before launching anything.  GEMM tile timing writes into the free
+ * part of the arena and is skipped when that is too small.
+ * Errors: QT_EINVAL for a null or misaligned block, QT_ENOMEM when mem_bytes
+ * is below qt_ctx_fixed_bytes(), QT_EHIP when clearing the head fails. */
+qt_status qt_ctx_create_with_memory(int device, void* stream, void* mem, size_t mem_bytes,
+                                    qt_ctx* out);
+/* Bytes of the fixed head of a caller-owned context block (a constant of the
+ * library build, about 64 MiB of split-K partials). */
+size_t    qt_ctx_fixed_bytes(void);
+
+/* Workspace bytes tt_round (and tt_round_noalloc) needs for a train of x's
+ * capacities and batch with these options.  Host-only, launches nothing.
+ * QT_EINVAL for a malformed x. */
+qt_status qt_workspace_query(const qt_tt* x, const qt_round_opts* opts, size_t* bytes);
+
 void      qt_ctx_destroy(qt_ctx ctx);
 /* Last error message of the calling thread ("" if none). */
 const char* qt_last_error(void);
@@ -282,6 +314,20 @@ qt_status ls_iterate(qt_ctx ctx, const qt_operands* ops, qt_tt* e, const qt_solv
 qt_status homogenize(qt_ctx ctx, const qt_operands* ops, const qt_tt* k_sel, qt_tt* e,
                      const qt_solve_opts* opts, double* A_eff, int32_t* iters,
                      double* residuals);
+
+/* Workspace bytes ls_iterate (k_sel NULL) or homogenize (k_sel = its three
+ * selector trains) needs for this field batch, operands and options: the
+ * iteration arena plus, in the sketch modes, the persistent learned-rank
+ * state used by learned rounding and rank logging (it stays taken after the
+ * solve, so a later call of another kind on the same caller-owned context
+ * needs its own query added).  Rank or rounding logs (qt_ranklog_enable,
+ * qt_learn_log_enable) need capacity * 100 + 768 (24 feature floats and a
+ * label per row) and capacity * 48 + 512 (6 doubles per row) bytes more.  A
+ * caller-owned context of qt_ctx_fixed_bytes() + *bytes runs that solve.
+ * Host-only, launches nothing.  Errors as ls_iterate's argument checks. */
+qt_status qt_ls_workspace_query(const qt_operands* ops, const qt_tt* k_sel, const qt_tt* e,
+                                const qt_solve_opts* opts, size_t* bytes);
+
 
 /* ---------------------------------------------------------------------------
  * Learned-rank rounding (rank predictor).  The method's fixed-rank truncation

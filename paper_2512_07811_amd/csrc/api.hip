@@ -58,6 +58,15 @@ std::string hip_msg(hipError_t e, const char* what) {
 qt_status ws_reserve(qt_ctx ctx, size_t bytes) {
   bytes = (bytes + 255) & ~(size_t)255;
   if (ctx->ws_top + bytes <= ctx->ws_size) return QT_OK;
+  if (ctx->ext) {
+    char msg[200];
+    snprintf(msg, sizeof(msg),
+             "caller-owned memory: the call needs %zu bytes of workspace, %zu are free "
+             "(size the memory with qt_workspace_query / qt_ls_workspace_query)",
+             ctx->ws_top + bytes, ctx->ws_size);
+    set_error(msg);
+    return QT_ENOMEM;
+  }
   size_t want = std::max(ctx->ws_top + bytes, ctx->ws_size + ctx->ws_size / 2);
   // earlier work on the stream may still read the old arena
   QT_HIP(hipStreamSynchronize(ctx->stream));
@@ -76,6 +85,58 @@ qt_status ws_reserve(qt_ctx ctx, size_t bytes) {
   }
   ctx->ws_size = want;
   return QT_OK;
+}
+
+qt_status ctx_dev_alloc(qt_ctx ctx, void** p, size_t bytes) {
+  *p = nullptr;
+  if (!ctx->ext) {
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+      set_error(hip_msg(e, "hipMalloc(context buffer)"));
+      return QT_ENOMEM;
+    }
+    return QT_OK;
+  }
+  bytes = (bytes + 255) & ~(size_t)255;
+  // a freed block that is large enough is taken again (re-enabled logs of the
+  // same capacity, learned state of the same shape)
+  for (auto& b : ctx->ext_blocks)
+    if (b[2] && b[1] >= bytes) {
+      b[2] = 0;
+      *p = ctx->ext_lo + b[0];
+      return QT_OK;
+    }
+  if (ctx->ext_persist + bytes + ctx->ws_top > ctx->ext_size) {
+    char msg[200];
+    snprintf(msg, sizeof(msg),
+             "caller-owned memory: %zu more bytes for persistent buffers, %zu are free", bytes,
+             ctx->ext_size - ctx->ext_persist - ctx->ws_top);
+    set_error(msg);
+    return QT_ENOMEM;
+  }
+  ctx->ext_persist += bytes;
+  const size_t off = ctx->ext_size - ctx->ext_persist;
+  ctx->ext_blocks.push_back({off, bytes, 0});
+  ctx->ws_size = off;
+  *p = ctx->ext_lo + off;
+  return QT_OK;
+}
+
+void ctx_dev_free(qt_ctx ctx, void* p) {
+  if (!p) return;
+  if (!ctx->ext) {
+    hipFree(p);
+    return;
+  }
+  const size_t off = (size_t)((char*)p - ctx->ext_lo);
+  for (auto& b : ctx->ext_blocks)
+    if (b[0] == off) b[2] = 1;
+  // give back the freed blocks at the low end of the persistent region
+  while (!ctx->ext_blocks.empty() && ctx->ext_blocks.back()[2]) {
+    ctx->ext_persist -= ctx->ext_blocks.back()[1];
+    ctx->ext_blocks.pop_back();
+  }
+  ctx->ws_size = ctx->ext_size - ctx->ext_persist;
 }
 
 void* ws_take(qt_ctx ctx, size_t bytes) {
@@ -774,21 +835,39 @@ struct Solver {
   bool logging = false;
 };
 
-static qt_status solver_setup(qt_ctx ctx, const qt_operands* ops, qt_tt* e,
-                              const qt_solve_opts* opts, Solver& S, size_t extra) {
+// Arena bytes homogenize needs beyond the iteration: its residuals and the
+// three A_eff dot products (environments of k_sel[c] against the field).
+static size_t homogenize_extra(const qt_tt* k_sel, const qt_tt* e) {
+  const int B = e->batch;
+  size_t need = 4096 + sizeof(double) * 4 * B;
+  int64_t env = 1, tcap = 1;
+  for (int k = 0; k <= e->n; ++k) env = std::max<int64_t>(env, (int64_t)k_sel[0].cap[k] * e->cap[k]);
+  for (int k = 0; k < e->n; ++k)
+    tcap = std::max<int64_t>(tcap, (int64_t)k_sel[0].cap[k] * e->modes[k] * e->cap[k + 1]);
+  return need + sizeof(cplx) * B * (2 * env + tcap) + 1024;
+}
+
+// Arena bytes of ls_iterate beyond the iteration: its residual scratch.
+static size_t ls_extra(const qt_tt* e) { return sizeof(double) * e->batch + 256; }
+
+static size_t solver_arena_bytes(size_t bytesA, size_t bytesB, size_t ws, size_t extra,
+                                 size_t spare, int B, int n) {
+  return bytesA + bytesB + ws + extra + spare + sizeof(int32_t) * B * (n + 1) * 3 +
+         sizeof(double) * B * 9 + sizeof(int32_t) * B + 14 * 256;
+}
+
+// Plan and arena sizes of a solve (no context needed: also the workspace query).
+static qt_status solver_plan(const qt_operands* ops, const qt_tt* e, const qt_solve_opts* opts,
+                             Solver& S, size_t& bytesA, size_t& bytesB, size_t& ws,
+                             size_t& spare) {
   const int B = e->batch, n = e->n;
   const int rmax = opts->round.max_rank;
   S.sketch = opts->round.mode != QT_ROUND_SVD;
   QT_CHECK(opts->round.precision == QT_PREC_F64, QT_EINVAL,
            "solver: only QT_PREC_F64 contractions are available");
   S.learned = opts->round.mode == QT_ROUND_LEARNED;
-  S.logging = ctx->learn && ctx->learn->log_count && S.sketch;
-  size_t bytesA, bytesB, ws;
-  if (S.learned) {
-    QT_CHECK(ctx->learn && ctx->learn->params, QT_EINVAL,
-             "solver: learned rounding needs a predictor (qt_set_predictor)");
+  if (S.learned)
     QT_CHECK(e->batch <= 1024, QT_EINVAL, "solver: learned rounding takes at most 1024 fields");
-  }
   if (S.sketch) {
     QT_CHECK(ops->Kp.n == n && ops->K2.n == n && ops->k0 > 0.0, QT_EINVAL,
              "solver: sketch mode needs Kp, K2 and k0 operands");
@@ -806,13 +885,27 @@ static qt_status solver_setup(qt_ctx ctx, const qt_operands* ops, qt_tt* e,
     bytesA = S.P.bytesA; bytesB = S.P.bytesB; ws = iteration_bytes(S.P, B, rmax) - S.P.bytesA - S.P.bytesB;
   }
   // the learned path's fallback writes into a spare train of the largest step layout
-  size_t spare = 0;
+  spare = 0;
   if (S.learned)
     spare = sizeof(cplx) * B * std::max({S.SP.l1.stride, S.SP.l2.stride, S.SP.l3.stride,
                                          S.SP.l4.stride});
+  return QT_OK;
+}
+
+static qt_status solver_setup(qt_ctx ctx, const qt_operands* ops, qt_tt* e,
+                              const qt_solve_opts* opts, Solver& S, size_t extra) {
+  const int B = e->batch, n = e->n;
+  size_t bytesA = 0, bytesB = 0, ws = 0, spare = 0;
+  QT_TRY(solver_plan(ops, e, opts, S, bytesA, bytesB, ws, spare));
+  S.logging = ctx->learn && ctx->learn->log_count && S.sketch;
+  if (S.learned)
+    QT_CHECK(ctx->learn && ctx->learn->params, QT_EINVAL,
+             "solver: learned rounding needs a predictor (qt_set_predictor)");
   ctx->ws_top = 0;
-  QT_TRY(ws_reserve(ctx, bytesA + bytesB + ws + extra + spare + sizeof(int32_t) * B * (n + 1) * 3 +
-                             sizeof(double) * B * 9 + sizeof(int32_t) * B + 14 * 256));
+  // persistent learned state first (caller-owned memory takes it from the
+  // end, outside the arena reserved next)
+  if (S.learned || S.logging) QT_TRY(learn_ensure(ctx, n, B));
+  QT_TRY(ws_reserve(ctx, solver_arena_bytes(bytesA, bytesB, ws, extra, spare, B, n)));
   S.bufA = (char*)ws_take(ctx, bytesA);
   S.bufB = (char*)ws_take(ctx, bytesB);
   S.rA = (int32_t*)ws_take(ctx, sizeof(int32_t) * B * (n + 1));
@@ -911,6 +1004,85 @@ static qt_status iterate_graph(qt_ctx ctx, const qt_operands* ops, qt_tt* e, con
   return QT_OK;
 }
 
+// Fixed device state of a context: status word, counters, graph iteration
+// counter and the GEMM split-K buffer (256-byte aligned pieces).
+static size_t fixed_piece(size_t b) { return (b + 255) & ~(size_t)255; }
+static size_t ctx_fixed_bytes() {
+  return fixed_piece(QT_STATUS_BYTES) + fixed_piece(sizeof(unsigned long long) * CNT_N) +
+         fixed_piece(sizeof(uint64_t)) + fixed_piece(sizeof(cplx) * QT_SPLITK_ELEMS);
+}
+
+static void ctx_release(qt_ctx c) {
+  if (!c->ext) {
+    if (c->ws) hipFree(c->ws);
+    if (c->status) hipFree(c->status);
+    if (c->counters) hipFree(c->counters);
+    if (c->splitk.p) hipFree(c->splitk.p);
+    if (c->dev_iter) hipFree(c->dev_iter);
+  }
+  if (c->tuner.scratch) hipFree(c->tuner.scratch);
+  for (hipEvent_t e : c->tuner.ev)
+    if (e) hipEventDestroy(e);
+  if (qt::g_tuner == &c->tuner) qt::g_tuner = nullptr;
+  if (c->cap_stream) hipStreamDestroy(c->cap_stream);
+  for (hipEvent_t e : c->prof.ev) hipEventDestroy(e);
+  qt_learn_free(c);
+  delete c;
+}
+
+static qt_status ctx_init(int device, void* stream, char* mem, size_t mem_bytes, qt_ctx* out) {
+  QT_CHECK(out, QT_EINVAL, "qt_ctx_create: null out");
+  *out = nullptr;
+  QT_HIP(hipSetDevice(device));
+  qt_ctx c = new qt_ctx_s();
+  c->device = device;
+  c->stream = (hipStream_t)stream;
+  c->tuner.owner = c;
+  hipError_t e = hipSuccess;
+  if (mem) {
+    // caller-owned memory: fixed state at its head, the arena after it
+    c->ext = true;
+    char* p = mem;
+    c->status = (int32_t*)p;
+    p += fixed_piece(QT_STATUS_BYTES);
+    c->counters = (unsigned long long*)p;
+    p += fixed_piece(sizeof(unsigned long long) * CNT_N);
+    c->dev_iter = (uint64_t*)p;
+    p += fixed_piece(sizeof(uint64_t));
+    c->splitk.p = (cplx*)p;
+    c->splitk.elems = QT_SPLITK_ELEMS;
+    p += fixed_piece(sizeof(cplx) * QT_SPLITK_ELEMS);
+    c->ext_lo = p;
+    c->ext_size = mem_bytes - ctx_fixed_bytes();
+    c->ws = p;
+    c->ws_size = c->ext_size;
+  } else {
+    e = hipMalloc((void**)&c->status, QT_STATUS_BYTES);
+    if (e == hipSuccess) e = hipMalloc((void**)&c->counters, sizeof(unsigned long long) * CNT_N);
+    if (e == hipSuccess) {
+      e = hipMalloc((void**)&c->splitk.p, sizeof(cplx) * QT_SPLITK_ELEMS);
+      if (e == hipSuccess) c->splitk.elems = QT_SPLITK_ELEMS;
+    }
+    if (e == hipSuccess) e = hipMalloc((void**)&c->dev_iter, sizeof(uint64_t));
+  }
+  if (e == hipSuccess) e = hipMemset(c->status, 0, QT_STATUS_BYTES);
+  if (e == hipSuccess) e = hipMemset(c->counters, 0, sizeof(unsigned long long) * CNT_N);
+  if (e == hipSuccess) e = hipMemset(c->dev_iter, 0, sizeof(uint64_t));
+  if (e != hipSuccess) {
+    ctx_release(c);
+    set_error(hip_msg(e, "qt_ctx_create: device state"));
+    return QT_EHIP;
+  }
+  // the allocation-free entry points' scratch on this device
+  qt_status s = noalloc_attach(device);
+  if (s != QT_OK) {
+    ctx_release(c);
+    return s;
+  }
+  *out = c;
+  return QT_OK;
+}
+
 }  // namespace qt
 
 using namespace qt;
@@ -920,76 +1092,62 @@ extern "C" {
 const char* qt_last_error(void) { return g_last_error.c_str(); }
 
 qt_status qt_ctx_create(int device, void* stream, size_t ws_bytes, qt_ctx* out) {
-  QT_CHECK(out, QT_EINVAL, "qt_ctx_create: null out");
-  *out = nullptr;
-  QT_HIP(hipSetDevice(device));
-  qt_ctx c = new qt_ctx_s();
-  c->device = device;
-  c->stream = (hipStream_t)stream;
-  hipError_t e = hipMalloc((void**)&c->status, QT_STATUS_BYTES);
-  if (e != hipSuccess) {
-    delete c;
-    set_error(hip_msg(e, "hipMalloc(status)"));
-    return QT_ENOMEM;
-  }
-  e = hipMemset(c->status, 0, QT_STATUS_BYTES);
-  if (e == hipSuccess) e = hipMalloc((void**)&c->counters, sizeof(unsigned long long) * CNT_N);
-  if (e == hipSuccess) e = hipMemset(c->counters, 0, sizeof(unsigned long long) * CNT_N);
-  if (e == hipSuccess) {
-    e = hipMalloc((void**)&c->splitk.p, sizeof(cplx) * QT_SPLITK_ELEMS);
-    if (e == hipSuccess) c->splitk.elems = QT_SPLITK_ELEMS;
-  }
-  if (e == hipSuccess) e = hipMalloc((void**)&c->dev_iter, sizeof(uint64_t));
-  if (e == hipSuccess) e = hipMemset(c->dev_iter, 0, sizeof(uint64_t));
-  if (e != hipSuccess) {
-    hipFree(c->status);
-    if (c->counters) hipFree(c->counters);
-    if (c->splitk.p) hipFree(c->splitk.p);
-    if (c->dev_iter) hipFree(c->dev_iter);
-    delete c;
-    set_error(hip_msg(e, "qt_ctx_create: device allocations"));
-    return QT_EHIP;
-  }
-  {
-    // the allocation-free entry points' scratch on this device
-    qt_status s = noalloc_attach(device);
-    if (s != QT_OK) {
-      hipFree(c->status);
-      hipFree(c->counters);
-      hipFree(c->splitk.p);
-      hipFree(c->dev_iter);
-      delete c;
-      return s;
-    }
-  }
+  QT_TRY(ctx_init(device, stream, nullptr, 0, out));
   if (ws_bytes) {
-    qt_status s = ws_reserve(c, ws_bytes);
+    qt_status s = ws_reserve(*out, ws_bytes);
     if (s != QT_OK) {
-      hipFree(c->status);
-      delete c;
+      ctx_release(*out);
+      *out = nullptr;
       return s;
     }
   }
-  *out = c;
   return QT_OK;
+}
+
+size_t qt_ctx_fixed_bytes(void) { return ctx_fixed_bytes(); }
+
+qt_status qt_workspace_query(const qt_tt* x, const qt_round_opts* opts, size_t* bytes) {
+  QT_CHECK(x && opts && bytes, QT_EINVAL, "qt_workspace_query: null argument");
+  QT_TRY(tt_validate(x, "x"));
+  const int lmax_cap = opts->max_rank > 0 ? opts->max_rank : (1 << 30);
+  *bytes = (round_ws_layout(x, lmax_cap).bytes + 255) & ~(size_t)255;
+  return QT_OK;
+}
+
+qt_status qt_ls_workspace_query(const qt_operands* ops, const qt_tt* k_sel, const qt_tt* e,
+                                const qt_solve_opts* opts, size_t* bytes) {
+  QT_CHECK(ops && e && opts && bytes, QT_EINVAL, "qt_ls_workspace_query: null argument");
+  QT_TRY(validate_ops(ops, e));
+  QT_TRY(validate_field_cap(e, opts->round.max_rank));
+  if (k_sel)
+    for (int c = 0; c < 3; ++c) {
+      QT_TRY(tt_validate(&k_sel[c], "k_sel"));
+      QT_CHECK(k_sel[c].n == e->n, QT_EINVAL, "qt_ls_workspace_query: k_sel cores");
+    }
+  Solver S;
+  size_t bytesA = 0, bytesB = 0, ws = 0, spare = 0;
+  QT_TRY(solver_plan(ops, e, opts, S, bytesA, bytesB, ws, spare));
+  const size_t extra = k_sel ? homogenize_extra(k_sel, e) : ls_extra(e);
+  size_t b = (solver_arena_bytes(bytesA, bytesB, ws, extra, spare, e->batch, e->n) + 255) &
+             ~(size_t)255;
+  if (S.sketch) b += learn_state_bytes(e->n, e->batch);
+  *bytes = b;
+  return QT_OK;
+}
+
+qt_status qt_ctx_create_with_memory(int device, void* stream, void* mem, size_t mem_bytes,
+                                    qt_ctx* out) {
+  QT_CHECK(mem && ((uintptr_t)mem & 255) == 0, QT_EINVAL,
+           "qt_ctx_create_with_memory: memory must be non-null and 256-byte aligned");
+  QT_CHECK(mem_bytes >= ctx_fixed_bytes(), QT_ENOMEM,
+           "qt_ctx_create_with_memory: memory below qt_ctx_fixed_bytes()");
+  return ctx_init(device, stream, (char*)mem, mem_bytes, out);
 }
 
 void qt_ctx_destroy(qt_ctx ctx) {
   if (!ctx) return;
   hipStreamSynchronize(ctx->stream);
-  if (ctx->ws) hipFree(ctx->ws);
-  if (ctx->status) hipFree(ctx->status);
-  if (ctx->counters) hipFree(ctx->counters);
-  if (ctx->splitk.p) hipFree(ctx->splitk.p);
-  if (ctx->tuner.scratch) hipFree(ctx->tuner.scratch);
-  for (hipEvent_t e : ctx->tuner.ev)
-    if (e) hipEventDestroy(e);
-  if (qt::g_tuner == &ctx->tuner) qt::g_tuner = nullptr;
-  if (ctx->dev_iter) hipFree(ctx->dev_iter);
-  if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
-  for (hipEvent_t e : ctx->prof.ev) hipEventDestroy(e);
-  qt_learn_free(ctx);
-  delete ctx;
+  ctx_release(ctx);
 }
 
 qt_status qt_ctx_profile(qt_ctx ctx, int32_t classes) {
@@ -1045,7 +1203,7 @@ qt_status ls_iterate(qt_ctx ctx, const qt_operands* ops, qt_tt* e, const qt_solv
   QT_CHECK(n_iter >= 0, QT_EINVAL, "ls_iterate: n_iter < 0");
   QT_TRY(validate_field_cap(e, opts->round.max_rank));
   Solver S;
-  QT_TRY(solver_setup(ctx, ops, e, opts, S, sizeof(double) * e->batch + 256));
+  QT_TRY(solver_setup(ctx, ops, e, opts, S, ls_extra(e)));
   double* res_tmp = (double*)ws_take(ctx, sizeof(double) * e->batch);
   QT_CHECK(res_tmp, QT_ENOMEM, "ls_iterate: workspace");
   const bool graph = opts->graph && S.sketch && !S.learned && !S.logging && !ctx->prof.cls;
@@ -1077,15 +1235,7 @@ qt_status homogenize(qt_ctx ctx, const qt_operands* ops, const qt_tt* k_sel, qt_
   QT_TRY(validate_field_cap(e, opts->round.max_rank));
   const int B = e->batch;
   Solver S;
-  size_t dot_need = 4096 + sizeof(double) * 4 * B;
-  {
-    int64_t env = 1, tcap = 1;
-    for (int k = 0; k <= e->n; ++k) env = std::max<int64_t>(env, (int64_t)k_sel[0].cap[k] * e->cap[k]);
-    for (int k = 0; k < e->n; ++k)
-      tcap = std::max<int64_t>(tcap, (int64_t)k_sel[0].cap[k] * e->modes[k] * e->cap[k + 1]);
-    dot_need += sizeof(cplx) * B * (2 * env + tcap) + 1024;
-  }
-  QT_TRY(solver_setup(ctx, ops, e, opts, S, dot_need));
+  QT_TRY(solver_setup(ctx, ops, e, opts, S, homogenize_extra(k_sel, e)));
   double* dres = (double*)ws_take(ctx, sizeof(double) * B);
   QT_CHECK(dres, QT_ENOMEM, "homogenize: workspace");
   QT_TRY(tt_copy(ctx, &ops->E, e));

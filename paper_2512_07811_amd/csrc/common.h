@@ -270,6 +270,7 @@ struct GemmTuner {
   std::map<std::array<int64_t, 9>, int> choice;
   cplx* scratch = nullptr;      // output of the timing launches
   int64_t scratch_elems = 0;
+  qt_ctx owner = nullptr;       // caller-memory contexts time into their free arena
   hipEvent_t ev[2] = {nullptr, nullptr};
 };
 extern thread_local GemmTuner* g_tuner;
@@ -294,6 +295,14 @@ struct qt_ctx_s {
   qt::GemmTuner tuner;                     // GEMM tile shapes per call signature
   qt::ProfSink prof;
   qt::LearnCtx* learn = nullptr;   // learned-rank state (created on demand)
+  // caller-owned device memory (qt_ctx_create_with_memory): the context's
+  // fixed state at its head, the arena after it, persistent buffers (learned
+  // state, logs) taken from its end; the library then never allocates
+  bool ext = false;
+  char* ext_lo = nullptr;        // first byte of the arena
+  size_t ext_size = 0;           // arena + persistent bytes
+  size_t ext_persist = 0;        // bytes taken from the end
+  std::vector<std::array<size_t, 3>> ext_blocks;   // (offset, bytes, freed)
   int jacobi_default = 30;
   uint64_t sketch_counter = 0;  // distinct Gaussian streams across iterations
   uint64_t* dev_iter = nullptr;  // device copy of the iteration number (graph replays)
@@ -312,6 +321,11 @@ struct Arena {
 };
 qt_status ws_reserve(qt_ctx ctx, size_t bytes);
 void* ws_take(qt_ctx ctx, size_t bytes);
+// Persistent device buffers of a context (learned state, logs): hipMalloc, or,
+// with caller-owned memory, blocks taken from its end (QT_ENOMEM when the
+// arena in use would be overrun).
+qt_status ctx_dev_alloc(qt_ctx ctx, void** p, size_t bytes);
+void ctx_dev_free(qt_ctx ctx, void* p);
 
 // Host-side helpers for qt_tt metadata.
 int64_t tt_slot_elems(const qt_tt* t, int k);

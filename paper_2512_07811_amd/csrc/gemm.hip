@@ -254,7 +254,15 @@ static int tune_shape(hipStream_t st, GemmTuner& T, bool cA, bool cB, GemmArgs a
   const int64_t items1 = (int64_t)a.nb1 * a.nb2;
   const int64_t need = items1 * a.Mcap * a.Ncap;
   if (need > QT_TUNE_MAX_ELEMS) return 0;
-  if (need > T.scratch_elems) {
+  cplx* out = nullptr;
+  if (T.owner && T.owner->ext) {
+    // caller-owned memory: the unused arena above the live workspace (the
+    // timing launches are ordered on the stream after every earlier user)
+    qt_ctx c = T.owner;
+    const size_t lo = (c->ws_top + 255) & ~(size_t)255;
+    if (lo + sizeof(cplx) * need > c->ws_size) return 0;
+    out = (cplx*)(c->ws + lo);
+  } else if (need > T.scratch_elems) {
     if (T.scratch) (void)hipFree(T.scratch);
     T.scratch = nullptr;
     T.scratch_elems = 0;
@@ -265,10 +273,11 @@ static int tune_shape(hipStream_t st, GemmTuner& T, bool cA, bool cB, GemmArgs a
     }
     T.scratch_elems = need;
   }
+  if (!out) out = T.scratch;
   if (!T.ev[0] && (hipEventCreate(&T.ev[0]) != hipSuccess || hipEventCreate(&T.ev[1]) != hipSuccess))
     return 0;
   const Str one{nullptr, 0, 0, 1}, zero{nullptr, 0, 0, 0};
-  a.C = mat(T.scratch, 0, Str{nullptr, 0, 0, a.Ncap}, one,
+  a.C = mat(out, 0, Str{nullptr, 0, 0, a.Ncap}, one,
             Str{nullptr, 0, 0, (int64_t)a.nb2 * a.Mcap * a.Ncap},
             Str{nullptr, 0, 0, (int64_t)a.Mcap * a.Ncap}, zero);
   a.acc = 0;

@@ -52,6 +52,8 @@ struct LearnCtx {
 };
 
 qt_status learn_ensure(qt_ctx ctx, int n, int B);
+// device bytes of the learned state of n cores and B instances
+size_t learn_state_bytes(int n, int B);
 void learn_features(qt_ctx ctx, int step, const std::vector<int32_t>& ell, const double* xn2,
                     double eps, int rmax);
 void learn_log(qt_ctx ctx, int step, const int32_t* ranks);

@@ -111,17 +111,28 @@ __global__ void k_pred_max(int B, const int32_t* __restrict__ pred, int32_t* pma
   pmax[s * QT_MAX_CORES + k] = v;
 }
 
-static void learn_free_state(LearnCtx* L) {
-  if (L->rdiag) hipFree(L->rdiag);
-  if (L->feat) hipFree(L->feat);
-  if (L->pred) hipFree(L->pred);
-  if (L->pcap) hipFree(L->pcap);
-  if (L->pmax) hipFree(L->pmax);
-  if (L->ref) hipFree(L->ref);
-  if (L->keep) hipFree(L->keep);
-  if (L->nfail) hipFree(L->nfail);
+// freed in the reverse order of allocation (caller-owned memory gives its
+// blocks back from the low end of the persistent region)
+static void learn_free_state(qt_ctx ctx, LearnCtx* L) {
+  ctx_dev_free(ctx, L->nfail);
+  ctx_dev_free(ctx, L->keep);
+  ctx_dev_free(ctx, L->ref);
+  ctx_dev_free(ctx, L->pmax);
+  ctx_dev_free(ctx, L->pcap);
+  ctx_dev_free(ctx, L->pred);
+  ctx_dev_free(ctx, L->feat);
+  ctx_dev_free(ctx, L->rdiag);
   L->rdiag = nullptr; L->feat = nullptr; L->pred = nullptr; L->pcap = nullptr;
   L->pmax = nullptr; L->ref = nullptr; L->keep = nullptr; L->nfail = nullptr;
+}
+
+size_t learn_state_bytes(int n, int B) {
+  auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  const size_t nf = (size_t)2 * 4 * B * QT_MAX_CORES * QT_RANK_FEATURES;
+  const size_t np = (size_t)4 * B * QT_MAX_CORES;
+  return al(sizeof(double) * 4 * B * (n + 1) * RD_MAX) + al(sizeof(float) * nf) +
+         2 * al(sizeof(int32_t) * np) + al(sizeof(int32_t) * 4 * QT_MAX_CORES) +
+         al(sizeof(double) * 4 * B) + al(sizeof(int32_t) * B) + al(sizeof(int32_t));
 }
 
 qt_status learn_ensure(qt_ctx ctx, int n, int B) {
@@ -130,21 +141,23 @@ qt_status learn_ensure(qt_ctx ctx, int n, int B) {
   LearnCtx* L = ctx->learn;
   if (L->n == n && L->B == B && L->rdiag) return QT_OK;
   QT_HIP(hipStreamSynchronize(ctx->stream));
-  learn_free_state(L);
-  L->n = n;
-  L->B = B;
+  learn_free_state(ctx, L);
+  L->n = 0;
+  L->B = 0;
   const size_t nf = (size_t)2 * 4 * B * QT_MAX_CORES * QT_RANK_FEATURES;
   const size_t np = (size_t)4 * B * QT_MAX_CORES;
-  QT_HIP(hipMalloc((void**)&L->rdiag, sizeof(double) * 4 * B * (n + 1) * RD_MAX));
-  QT_HIP(hipMemset(L->rdiag, 0, sizeof(double) * 4 * B * (n + 1) * RD_MAX));
-  QT_HIP(hipMalloc((void**)&L->feat, sizeof(float) * nf));
-  QT_HIP(hipMalloc((void**)&L->pred, sizeof(int32_t) * np));
-  QT_HIP(hipMalloc((void**)&L->pcap, sizeof(int32_t) * np));
-  QT_HIP(hipMalloc((void**)&L->pmax, sizeof(int32_t) * 4 * QT_MAX_CORES));
-  QT_HIP(hipMalloc((void**)&L->ref, sizeof(double) * 4 * B));
-  QT_HIP(hipMemset(L->ref, 0, sizeof(double) * 4 * B));
-  QT_HIP(hipMalloc((void**)&L->keep, sizeof(int32_t) * B));
-  QT_HIP(hipMalloc((void**)&L->nfail, sizeof(int32_t)));
+  QT_TRY(ctx_dev_alloc(ctx, (void**)&L->rdiag, sizeof(double) * 4 * B * (n + 1) * RD_MAX));
+  QT_TRY(ctx_dev_alloc(ctx, (void**)&L->feat, sizeof(float) * nf));
+  QT_TRY(ctx_dev_alloc(ctx, (void**)&L->pred, sizeof(int32_t) * np));
+  QT_TRY(ctx_dev_alloc(ctx, (void**)&L->pcap, sizeof(int32_t) * np));
+  QT_TRY(ctx_dev_alloc(ctx, (void**)&L->pmax, sizeof(int32_t) * 4 * QT_MAX_CORES));
+  QT_TRY(ctx_dev_alloc(ctx, (void**)&L->ref, sizeof(double) * 4 * B));
+  QT_TRY(ctx_dev_alloc(ctx, (void**)&L->keep, sizeof(int32_t) * B));
+  QT_TRY(ctx_dev_alloc(ctx, (void**)&L->nfail, sizeof(int32_t)));
+  QT_HIP(hipMemsetAsync(L->rdiag, 0, sizeof(double) * 4 * B * (n + 1) * RD_MAX, ctx->stream));
+  QT_HIP(hipMemsetAsync(L->ref, 0, sizeof(double) * 4 * B, ctx->stream));
+  L->n = n;
+  L->B = B;
   L->have_prev = false;
   L->cur = 0;
   for (int s = 0; s < 4; ++s) L->pred_ell[s].clear();
@@ -220,12 +233,16 @@ extern "C" qt_status qt_ranklog_enable(qt_ctx ctx, int32_t capacity, int32_t n_c
   if (!ctx->learn) ctx->learn = new LearnCtx();
   LearnCtx* L = ctx->learn;
   QT_HIP(hipStreamSynchronize(ctx->stream));
-  if (L->log_feat) { hipFree(L->log_feat); hipFree(L->log_label); hipFree(L->log_count); }
+  ctx->ws_top = 0;   // between calls: nothing lives in the arena
+  ctx_dev_free(ctx, L->log_count);
+  ctx_dev_free(ctx, L->log_label);
+  ctx_dev_free(ctx, L->log_feat);
   L->log_feat = nullptr; L->log_label = nullptr; L->log_count = nullptr; L->log_cap = 0;
   if (capacity == 0) return QT_OK;
-  QT_HIP(hipMalloc((void**)&L->log_feat, sizeof(float) * (size_t)capacity * QT_RANK_FEATURES));
-  QT_HIP(hipMalloc((void**)&L->log_label, sizeof(int32_t) * (size_t)capacity));
-  QT_HIP(hipMalloc((void**)&L->log_count, sizeof(int32_t)));
+  QT_TRY(ctx_dev_alloc(ctx, (void**)&L->log_feat,
+                       sizeof(float) * (size_t)capacity * QT_RANK_FEATURES));
+  QT_TRY(ctx_dev_alloc(ctx, (void**)&L->log_label, sizeof(int32_t) * (size_t)capacity));
+  QT_TRY(ctx_dev_alloc(ctx, (void**)&L->log_count, sizeof(int32_t)));
   QT_HIP(hipMemset(L->log_count, 0, sizeof(int32_t)));
   L->log_cap = capacity;
   L->log_cls = n_cls;
@@ -258,11 +275,14 @@ extern "C" qt_status qt_learn_log_enable(qt_ctx ctx, int32_t capacity) {
   if (!ctx->learn) ctx->learn = new LearnCtx();
   LearnCtx* L = ctx->learn;
   QT_HIP(hipStreamSynchronize(ctx->stream));
-  if (L->rlog) { hipFree(L->rlog); hipFree(L->rlog_count); }
+  ctx->ws_top = 0;
+  ctx_dev_free(ctx, L->rlog_count);
+  ctx_dev_free(ctx, L->rlog);
   L->rlog = nullptr; L->rlog_count = nullptr; L->rlog_cap = 0;
   if (capacity == 0) return QT_OK;
-  QT_HIP(hipMalloc((void**)&L->rlog, sizeof(double) * (size_t)capacity * QT_LEARN_LOG_COLS));
-  QT_HIP(hipMalloc((void**)&L->rlog_count, sizeof(int32_t)));
+  QT_TRY(ctx_dev_alloc(ctx, (void**)&L->rlog,
+                       sizeof(double) * (size_t)capacity * QT_LEARN_LOG_COLS));
+  QT_TRY(ctx_dev_alloc(ctx, (void**)&L->rlog_count, sizeof(int32_t)));
   QT_HIP(hipMemset(L->rlog_count, 0, sizeof(int32_t)));
   L->rlog_cap = capacity;
   return QT_OK;
@@ -315,9 +335,12 @@ extern "C" qt_status qt_learn_reset(qt_ctx ctx) {
 void qt_learn_free(qt_ctx ctx) {
   if (!ctx || !ctx->learn) return;
   LearnCtx* L = ctx->learn;
-  learn_free_state(L);
-  if (L->log_feat) { hipFree(L->log_feat); hipFree(L->log_label); hipFree(L->log_count); }
-  if (L->rlog) { hipFree(L->rlog); hipFree(L->rlog_count); }
+  learn_free_state(ctx, L);
+  ctx_dev_free(ctx, L->log_count);
+  ctx_dev_free(ctx, L->log_label);
+  ctx_dev_free(ctx, L->log_feat);
+  ctx_dev_free(ctx, L->rlog_count);
+  ctx_dev_free(ctx, L->rlog);
   delete L;
   ctx->learn = nullptr;
 }

@@ -27,7 +27,8 @@ EXPORTS = ["qt_ctx_create", "qt_ctx_destroy", "qt_last_error", "qt_ctx_sync",
            "tt_mpo_apply", "tt_add", "tt_round", "tt_round_noalloc", "tt_dot", "tt_sketch_round", "tt_sandwich",
            "ls_iterate", "homogenize", "qt_mlp_num_params", "qt_mlp_train_step", "qt_mlp_infer",
            "qt_ranklog_enable", "qt_ranklog_get", "qt_set_predictor", "qt_learn_reset",
-           "qt_learn_log_enable", "qt_learn_log_get"]
+           "qt_learn_log_enable", "qt_learn_log_get", "qt_ctx_fixed_bytes",
+           "qt_ctx_create_with_memory", "qt_workspace_query", "qt_ls_workspace_query"]
 
 
 class QtError(RuntimeError):
@@ -113,9 +114,17 @@ def load_library(path: str = LIB_PATH):
     lib.qt_learn_reset.argtypes = [vp]
     lib.qt_learn_log_enable.argtypes = [vp, i32]
     lib.qt_learn_log_get.argtypes = [vp, vp, i32, C.POINTER(C.c_int32)]
+    lib.qt_ctx_fixed_bytes.argtypes = []
+    lib.qt_ctx_create_with_memory.argtypes = [C.c_int, vp, vp, C.c_size_t, C.POINTER(vp)]
+    lib.qt_workspace_query.argtypes = [C.POINTER(TTDesc), C.POINTER(RoundOpts),
+                                       C.POINTER(C.c_size_t)]
+    lib.qt_ls_workspace_query.argtypes = [C.POINTER(Operands), C.POINTER(TTDesc),
+                                          C.POINTER(TTDesc), C.POINTER(SolveOpts),
+                                          C.POINTER(C.c_size_t)]
     for name in EXPORTS:
-        if name not in ("qt_ctx_destroy", "qt_last_error"):
+        if name not in ("qt_ctx_destroy", "qt_last_error", "qt_ctx_fixed_bytes"):
             getattr(lib, name).restype = C.c_int32
+    lib.qt_ctx_fixed_bytes.restype = C.c_size_t
     _lib = lib
     return lib
 
@@ -152,15 +161,25 @@ def _p64(a):
 class Context:
     """A library context bound to torch's current stream on `device`."""
 
-    def __init__(self, device: int = 0, ws_bytes: int = 0):
+    def __init__(self, device: int = 0, ws_bytes: int = 0, memory=None):
+        """memory: optional caller-owned device block (a uint8 torch tensor on
+        `device`, 256-byte aligned) holding all of the context's device state
+        (qt_ctx_create_with_memory); the context keeps a reference to it."""
         torch = _torch()
         self.lib = load_library()
         self.device = device
         torch.cuda.set_device(device)
         self.stream = torch.cuda.current_stream(device)
         h = C.c_void_p()
-        _check(self.lib.qt_ctx_create(device, C.c_void_p(self.stream.cuda_stream), ws_bytes,
-                                      C.byref(h)))
+        self.memory = memory
+        if memory is None:
+            _check(self.lib.qt_ctx_create(device, C.c_void_p(self.stream.cuda_stream), ws_bytes,
+                                          C.byref(h)))
+        else:
+            nbytes = memory.numel() * memory.element_size()
+            _check(self.lib.qt_ctx_create_with_memory(
+                device, C.c_void_p(self.stream.cuda_stream), C.c_void_p(memory.data_ptr()),
+                nbytes, C.byref(h)))
         self.h = h
 
     def close(self):
@@ -395,6 +414,30 @@ def tt_round(ctx: Context, x: DeviceTT, eps: float, max_rank: int = 0, **kw):
     _check(ctx.lib.tt_round(ctx.h, C.byref(x.desc()), C.byref(o), C.c_void_p(err.data_ptr()),
                             C.c_void_p(nrm.data_ptr())))
     return err, nrm
+
+
+def ctx_fixed_bytes() -> int:
+    """Bytes of the fixed head of a caller-owned context block."""
+    return int(load_library().qt_ctx_fixed_bytes())
+
+
+def workspace_query(x: DeviceTT, eps: float = 0.0, max_rank: int = 0, **kw) -> int:
+    """Workspace bytes of tt_round on x with these options (host only)."""
+    o = round_opts(eps, max_rank, **kw)
+    b = C.c_size_t()
+    _check(load_library().qt_workspace_query(C.byref(x.desc()), C.byref(o), C.byref(b)))
+    return b.value
+
+
+def ls_workspace_query(ops: "DeviceOperands", e: DeviceTT, opts: "SolveOpts",
+                       homogenize: bool = False) -> int:
+    """Workspace bytes of ls_iterate (or homogenize) on this batch (host only)."""
+    b = C.c_size_t()
+    st = ops.struct()
+    ksel = (TTDesc * 3)(*[t.desc() for t in ops.k_sel]) if homogenize else None
+    _check(load_library().qt_ls_workspace_query(C.byref(st), ksel, C.byref(e.desc()),
+                                                C.byref(opts), C.byref(b)))
+    return b.value
 
 
 def tt_round_noalloc(ctx: Context, x: DeviceTT, eps: float, err, nrm, max_rank: int = 0, **kw):
