@@ -229,7 +229,15 @@ qt_status tt_round(qt_ctx ctx, qt_tt* x, const qt_round_opts* opts, double* err_
 qt_status tt_round_noalloc(qt_ctx ctx, qt_tt* x, const qt_round_opts* opts, double* err_out,
                            double* norm_out);
 
-/* out[b] = sum_i conj(a_i) b_i for every instance (device [B][2] doubles). */
+/* Frobenius inner product of two trains with equal modes, per instance:
+ * out[b] = sum_i conj(a_b(i)) x b_b(i), device [B][2] doubles (re, im),
+ * contracted core by core through left environments (nothing materialized).
+ * sqrt(Re tt_dot(x, x)) is the Frobenius norm of the rounding condition
+ * (Sec. 2.2, eq. rounding_condition_tt) and of Algorithm 2's convergence test;
+ * with a = the selector train of k times a component, Re tt_dot(a, e) / N^3
+ * is the mean flux that gives a column of the effective tensor (Appendix A,
+ * the macroscopic stress-strain relation in Voigt form).  a->batch is 1
+ * (broadcast) or b->batch.  QT_EINVAL on mismatched modes or batches. */
 qt_status tt_dot(qt_ctx ctx, const qt_tt* a, const qt_tt* b, double* out);
 
 /* ---- product-aware rounding ---------------------------------------------- */
@@ -300,7 +308,12 @@ typedef struct {
  * structure, and the last one rounds S^dagger t with t = S E - eps^ (the rank-1
  * term S E is added before the rounding, so there are four roundings).
  * residual_out: device [n_iter][B] doubles (may be NULL).
- * e->cap must hold opts->round.max_rank on every bond. */
+ * e->cap must hold opts->round.max_rank on every bond.
+ * Capacity: every truncated SVD runs on a block of at most 1024 columns
+ * (rank cap + oversampling on the bonds of the sketch modes; r_A r_x on the
+ * materializing path), so max_rank + oversample <= 1024 / 2 on the 2-mode
+ * bonds; larger blocks return QT_ECAPACITY before any launch.  The
+ * workspace of a solve is given by qt_ls_workspace_query. */
 qt_status ls_iterate(qt_ctx ctx, const qt_operands* ops, qt_tt* e, const qt_solve_opts* opts,
                      int32_t n_iter, double* residual_out);
 
