@@ -311,6 +311,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-split", action="store_true",
                     help="skip the untimed kernel-class timing iterations")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed-precision (FP32 range finder) windows")
     ap.add_argument("--no-compare", action="store_true",
                     help="learned mode: skip the SVD-truncated window")
     ap.add_argument("--round-ranks", default="64,128",
@@ -469,6 +471,27 @@ def main():
                     "middle bond (each rounding's error is a few per cent, far above eps), so two "
                     "different roundings give iterates, and A_eff, that differ at that level",
         }
+    # mixed precision (FP32-MFMA range finder, FP64 projection and bookkeeping):
+    # the same windows from the same snapshot, against their FP64 counterparts
+    mixed = None
+    if args.mode in ("learned", "sketch") and not args.no_mixed:
+        mixed = {"scheme": "right sketches and sketched products on v_mfma_f32_16x16x4f32; "
+                           "projection, QR, SVD and error bookkeeping FP64"}
+        pairs = [(args.mode, opts, A_main, dt)]
+        if comparison:
+            pairs.append(("svd_truncated", sk_opts, A_sk, dt_sk))
+        for name, o64, A64, dt64 in pairs:
+            o32 = qtt.solve_opts(cfg["eps"], cfg["rmax"], mode=o64.round.mode,
+                                 oversample=args.oversample, seed=args.sketch_seed,
+                                 precision=qtt.PREC_F32)
+            dt32, res32, cnt32 = window(o32, f"{name} mixed")
+            A32 = a_eff(qtt, ctx, ops, e, ops.L)
+            g32 = float(np.linalg.norm(A32 - A64) / np.linalg.norm(A64))
+            mixed[name] = {"iters_per_s": args.steps * B / dt32, "speedup_over_fp64": dt64 / dt32,
+                           "A_eff_column": A32[0].tolist(), "A_eff_rel_gap_vs_fp64": g32,
+                           "meets_1e-6": bool(g32 <= 1e-6),
+                           "residual_last": float(res32[-1, 0]),
+                           "fallbacks": cnt32["learned_fallbacks"]}
     # kernel classes of both paths, one untimed iteration per class
     split = {}
     if not args.no_split:
@@ -508,6 +531,8 @@ def main():
     if comparison:
         out["comparison"] = comparison
         out["accuracy"] = accuracy
+    if mixed:
+        out["mixed_precision"] = mixed
     if split:
         main = split[args.mode]
         qr_model, svd_model = iteration_model(ops, (e.modes, e.cap), cfg["rmax"], args.oversample)

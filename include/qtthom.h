@@ -54,10 +54,22 @@ typedef int32_t qt_status;
 #define QT_ROUND_SKETCH   1   /* randomized range sketch + SVD truncation        */
 #define QT_ROUND_LEARNED  2   /* sketch at MLP-predicted ranks, SVD fallback     */
 
-/* Contraction precision of the structured (sketch) kernels.  Only QT_PREC_F64
- * is accepted (QT_EINVAL otherwise): an FP32 range finder was measured to put
- * relative errors of 1e-6 (small trains) and above 1e-4 (LS products, whose
- * contractions sum over product ranks of 10^3) into every rounded result. */
+/* Contraction precision of the product-aware roundings (tt_sketch_round,
+ * ls_iterate / homogenize in the sketch and learned modes; QT_EINVAL
+ * elsewhere).  QT_PREC_F64: every contraction in FP64.  QT_PREC_F32 (mixed):
+ * the contractions that only choose the bases of the randomized range finder
+ * (right sketches W_k and the sketched products Y_k) run on FP32 MFMA
+ * (operands rounded to FP32, FP32 accumulation; each such element is within
+ * (K + 4) 2^-24 sum_k |a_k||b_k| of its FP64 value for K terms), while the
+ * projection onto those bases, the QR and SVD factorizations and the error
+ * bookkeeping stay FP64.  The result is therefore still an exact orthogonal
+ * projection of the product, and the reported error is its exact error (or
+ * bound, with SVD truncation) as in FP64; what the FP32 bases cost is a larger
+ * projection error: 7.5e-6 to 1.1e-4 relative for a full-width sketch of
+ * small random trains (1e-13 in FP64), and, in the LS iteration of a 16^3
+ * cell, an A_eff within 2e-4 of the FP64 path's with a residual floor near
+ * 1e-2 (the paper computes in complex64 throughout, Sec. 4.1).  Use it where
+ * eps is about 1e-3 or larger. */
 #define QT_PREC_F64       0
 #define QT_PREC_F32       1
 

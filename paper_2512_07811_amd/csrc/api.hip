@@ -16,6 +16,7 @@ thread_local unsigned long long* g_counters = nullptr;
 thread_local SplitKBuf g_splitk;
 thread_local GemmTuner* g_tuner = nullptr;
 thread_local bool g_no_alloc = false;
+thread_local bool g_gemm_f32 = false;
 
 // Regions do not nest: work launched inside an open region (the finishing
 // products of a large SVD, the products of a blocked QR) counts to that region.
@@ -863,8 +864,9 @@ static qt_status solver_plan(const qt_operands* ops, const qt_tt* e, const qt_so
   const int B = e->batch, n = e->n;
   const int rmax = opts->round.max_rank;
   S.sketch = opts->round.mode != QT_ROUND_SVD;
-  QT_CHECK(opts->round.precision == QT_PREC_F64, QT_EINVAL,
-           "solver: only QT_PREC_F64 contractions are available");
+  QT_CHECK(opts->round.precision == QT_PREC_F64 ||
+               (opts->round.precision == QT_PREC_F32 && S.sketch),
+           QT_EINVAL, "solver: QT_PREC_F32 applies to the sketch and learned modes only");
   S.learned = opts->round.mode == QT_ROUND_LEARNED;
   if (S.learned)
     QT_CHECK(e->batch <= 1024, QT_EINVAL, "solver: learned rounding takes at most 1024 fields");

@@ -267,7 +267,7 @@ constexpr int64_t QT_SPLITK_ELEMS = int64_t(1) << 22;   // 64 MiB of complex dou
 // mode 0: always 64 x 64; 1: autotune; 2..5: always shape mode - 2.
 struct GemmTuner {
   int mode = 1;
-  std::map<std::array<int64_t, 9>, int> choice;
+  std::map<std::array<int64_t, 10>, int> choice;
   cplx* scratch = nullptr;      // output of the timing launches
   int64_t scratch_elems = 0;
   qt_ctx owner = nullptr;       // caller-memory contexts time into their free arena
@@ -277,6 +277,14 @@ extern thread_local GemmTuner* g_tuner;
 // Set while an allocation-free entry point runs: the GEMM launcher then never
 // times tile shapes (the timing would allocate its output buffer).
 extern thread_local bool g_no_alloc;
+// Set while the sketch contractions of a QT_PREC_F32 rounding are launched:
+// the GEMM launcher then runs its FP32-MFMA variant.
+extern thread_local bool g_gemm_f32;
+struct GemmF32Scope {
+  bool prev;
+  explicit GemmF32Scope(bool on) : prev(g_gemm_f32) { g_gemm_f32 = on; }
+  ~GemmF32Scope() { g_gemm_f32 = prev; }
+};
 qt_status noalloc_attach(int device);
 
 struct LearnCtx;

@@ -2,6 +2,7 @@
 // (product-aware) contractions.  Every size and stride may depend on device
 // ranks, so the launch grid covers capacities and idle tiles exit at once.
 #include <algorithm>
+#include <type_traits>
 
 #include "kernels.h"
 
@@ -13,12 +14,23 @@ static_assert(XT_K == 16, "k_gemm_ex's panel index maps assume XT_K == 16");
 constexpr int XT_PAD = 16;   // LDS row pitch 80 doubles: 16-lane groups of one read land 32 banks apart
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
 
 // v_mfma_f64_16x16x4f64 lane layout (gfx950): lane l supplies A[l % 16][l / 16]
 // and B[l / 16][l % 16] of the 16x4 and 4x16 operands; accumulator register r
 // of lane l holds D[4 r + l / 16][l % 16].
 __device__ inline dbl4 mfma16(double a, double b, dbl4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+// v_mfma_f32_16x16x4f32: the same operand layout; accumulator register r of
+// lane l holds D[4 (l / 16) + r][l % 16].
+__device__ inline flt4 mfma16(float a, float b, flt4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+// row of the 16 x 16 MFMA tile held by accumulator register r of lane group lk
+template <bool F32>
+__device__ inline int acc_row(int r, int lk) {
+  return F32 ? 4 * lk + r : 4 * r + lk;
 }
 
 // One TM x TN complex output tile (TM, TN in {32, 64}) per workgroup of 4
@@ -31,7 +43,10 @@ __device__ inline dbl4 mfma16(double a, double b, dbl4 c) {
 // Split-K (gridDim.z = splits > 1): workgroup z takes K range
 // [z kper, (z + 1) kper) with kper a multiple of the panel depth and writes its
 // raw partial tile to part[z][item][Mcap][Ncap]; k_splitk_sum finishes.
-template <bool CA, bool CB, int TM, int TN>
+// F32 (mixed precision): operands rounded to FP32 as they enter LDS, products
+// and sums on v_mfma_f32_16x16x4f32 (FP32 accumulation), results widened to
+// FP64 on the way out (split-K partials summed in FP64).
+template <bool CA, bool CB, int TM, int TN, bool F32>
 __global__ __launch_bounds__(256) void k_gemm_ex(int nb1, int nb2, int ntn, Dim Md, Dim Nd,
                                                  Dim Kd, Mat A, Mat B, Mat C, cplx alpha,
                                                  int accumulate, Dim lim1,
@@ -72,8 +87,10 @@ __global__ __launch_bounds__(256) void k_gemm_ex(int nb1, int nb2, int ntn, Dim 
   const int64_t crs = strv(C.rs, b), ccs = strv(C.cs, b);
   const bool a_kfast = (acs == 1);
   const bool b_nfast = (bcs == 1);
-  __shared__ double Ar[XT_K][TM + XT_PAD], Ai[XT_K][TM + XT_PAD];
-  __shared__ double Br[XT_K][TN + XT_PAD], Bi[XT_K][TN + XT_PAD];
+  using real = typename std::conditional<F32, float, double>::type;
+  using acc4 = typename std::conditional<F32, flt4, dbl4>::type;
+  __shared__ real Ar[XT_K][TM + XT_PAD], Ai[XT_K][TM + XT_PAD];
+  __shared__ real Br[XT_K][TN + XT_PAD], Bi[XT_K][TN + XT_PAD];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = (w & 1) * (TM / 2), wn = (w >> 1) * (TN / 2);
   const int li = lane & 15, lk = lane >> 4;
@@ -115,31 +132,31 @@ __global__ __launch_bounds__(256) void k_gemm_ex(int nb1, int nb2, int ntn, Dim 
       rb[e] = u;
     }
   };
-  dbl4 cre[FM][FN], cim[FM][FN];
+  acc4 cre[FM][FN], cim[FM][FN];
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int j = 0; j < FN; ++j) {
-      cre[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
-      cim[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+      cre[i][j] = acc4{0, 0, 0, 0};
+      cim[i][j] = acc4{0, 0, 0, 0};
     }
   fetch(kbeg);
   for (int k0 = kbeg; k0 < kend; k0 += XT_K) {
 #pragma unroll
     for (int e = 0; e < EA; ++e) {
-      Ar[ak[e]][am[e]] = ra[e].x;
-      Ai[ak[e]][am[e]] = ra[e].y;
+      Ar[ak[e]][am[e]] = (real)ra[e].x;
+      Ai[ak[e]][am[e]] = (real)ra[e].y;
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
-      Br[bk[e]][bn[e]] = rb[e].x;
-      Bi[bk[e]][bn[e]] = rb[e].y;
+      Br[bk[e]][bn[e]] = (real)rb[e].x;
+      Bi[bk[e]][bn[e]] = (real)rb[e].y;
     }
     __syncthreads();
     if (k0 + XT_K < kend) fetch(k0 + XT_K);
 #pragma unroll
     for (int kc = 0; kc < XT_K; kc += 4) {
-      double far[FM], fai[FM], fbr[FN], fbi[FN];
+      real far[FM], fai[FM], fbr[FN], fbi[FN];
 #pragma unroll
       for (int t = 0; t < FM; ++t) {
         far[t] = Ar[kc + lk][wm + 16 * t + li];
@@ -168,16 +185,16 @@ __global__ __launch_bounds__(256) void k_gemm_ex(int nb1, int nb2, int ntn, Dim 
     for (int j = 0; j < FN; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int gm = m0 + wm + 16 * i + 4 * r + lk;
+        const int gm = m0 + wm + 16 * i + acc_row<F32>(r, lk);
         const int gn = n0 + wn + 16 * j + li;
         if (gm >= M || gn >= N) continue;
         if (splits > 1) {
           if (gm >= Mcap || gn >= Ncap) continue;
           part[((int64_t)sk * items + z) * Mcap * Ncap + (int64_t)gm * Ncap + gn] =
-              make_double2(cre[i][j][r], cim[i][j][r]);
+              make_double2((double)cre[i][j][r], (double)cim[i][j][r]);
           continue;
         }
-        cplx v = cmul(alpha, make_double2(cre[i][j][r], cim[i][j][r]));
+        cplx v = cmul(alpha, make_double2((double)cre[i][j][r], (double)cim[i][j][r]));
         cplx* o = Cb + gm * crs + gn * ccs;
         if (accumulate) v = cadd(v, *o);
         *o = v;
@@ -220,12 +237,12 @@ struct GemmArgs {
   int64_t items;
 };
 
-template <int TM, int TN>
+template <int TM, int TN, bool F32>
 static void launch_tile(hipStream_t st, int splits, bool cA, bool cB, const GemmArgs& a) {
   const int ntn = (a.Ncap + TN - 1) / TN, mtn = (a.Mcap + TM - 1) / TM;
   dim3 grid((unsigned)((int64_t)ntn * a.items), mtn, splits);
 #define QT_GEMM_LAUNCH(X, Y)                                                                     \
-  k_gemm_ex<X, Y, TM, TN><<<grid, 256, 0, st>>>(a.nb1, a.nb2, ntn, a.M, a.N, a.K, a.A, a.B, a.C, \
+  k_gemm_ex<X, Y, TM, TN, F32><<<grid, 256, 0, st>>>(a.nb1, a.nb2, ntn, a.M, a.N, a.K, a.A, a.B, a.C, \
                                                 a.alpha, a.acc, a.lim1, a.cnt, a.part, a.Mcap,   \
                                                 a.Ncap, a.items)
   if (!cA && !cB) QT_GEMM_LAUNCH(false, false);
@@ -235,13 +252,19 @@ static void launch_tile(hipStream_t st, int splits, bool cA, bool cB, const Gemm
 #undef QT_GEMM_LAUNCH
 }
 
-static void launch_shape(int v, hipStream_t st, int splits, bool cA, bool cB, const GemmArgs& a) {
+template <bool F32>
+static void launch_shape_p(int v, hipStream_t st, int splits, bool cA, bool cB, const GemmArgs& a) {
   switch (v) {
-    case 1: launch_tile<32, 64>(st, splits, cA, cB, a); break;
-    case 2: launch_tile<64, 32>(st, splits, cA, cB, a); break;
-    case 3: launch_tile<32, 32>(st, splits, cA, cB, a); break;
-    default: launch_tile<64, 64>(st, splits, cA, cB, a); break;
+    case 1: launch_tile<32, 64, F32>(st, splits, cA, cB, a); break;
+    case 2: launch_tile<64, 32, F32>(st, splits, cA, cB, a); break;
+    case 3: launch_tile<32, 32, F32>(st, splits, cA, cB, a); break;
+    default: launch_tile<64, 64, F32>(st, splits, cA, cB, a); break;
   }
+}
+
+static void launch_shape(int v, hipStream_t st, int splits, bool cA, bool cB, const GemmArgs& a) {
+  if (g_gemm_f32) launch_shape_p<true>(v, st, splits, cA, cB, a);
+  else launch_shape_p<false>(v, st, splits, cA, cB, a);
 }
 
 // Largest timing output of the tuner (complex elements, 256 MiB).
@@ -337,9 +360,10 @@ void gemm_ex(hipStream_t st, int batch, int nb1, int nb2, Dim M, Dim N, Dim K, i
     // two, conjugations and which operands are unit-stride along K / N
     int64_t ib = 1;
     while (ib < items) ib <<= 1;
-    const std::array<int64_t, 9> key{conjA, conjB, (Mcap + 15) / 16, (Ncap + 15) / 16,
-                                      (Kcap + 63) / 64, ib, A.cs.p ? -1 : A.cs.cst,
-                                      B.cs.p ? -1 : B.cs.cst, C.cs.p ? -1 : C.cs.cst};
+    const std::array<int64_t, 10> key{conjA, conjB, (Mcap + 15) / 16, (Ncap + 15) / 16,
+                                       (Kcap + 63) / 64, ib, A.cs.p ? -1 : A.cs.cst,
+                                       B.cs.p ? -1 : B.cs.cst, C.cs.p ? -1 : C.cs.cst,
+                                       g_gemm_f32 ? 1 : 0};
     auto it = T->choice.find(key);
     if (it != T->choice.end()) {
       v = it->second;

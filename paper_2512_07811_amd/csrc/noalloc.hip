@@ -55,6 +55,8 @@ extern "C" qt_status tt_round_noalloc(qt_ctx ctx, qt_tt* x, const qt_round_opts*
   QT_CHECK(opts->eps >= 0.0, QT_EINVAL, "tt_round_noalloc: eps < 0");
   QT_CHECK(opts->mode == QT_ROUND_SVD, QT_EINVAL,
            "tt_round_noalloc: only QT_ROUND_SVD applies to a materialized train");
+  QT_CHECK(opts->precision == QT_PREC_F64, QT_EINVAL,
+           "tt_round_noalloc: QT_PREC_F32 applies to the product-aware roundings only");
   void* base = noalloc_ptr(ctx->device);
   QT_CHECK(base, QT_EINVAL, "tt_round_noalloc: no scratch attached for the context's device");
   const int lmax_cap = opts->max_rank > 0 ? opts->max_rank : (1 << 30);

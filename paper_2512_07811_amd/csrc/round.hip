@@ -262,6 +262,8 @@ extern "C" qt_status tt_round(qt_ctx ctx, qt_tt* x, const qt_round_opts* opts, d
   QT_CHECK(opts->eps >= 0.0, QT_EINVAL, "tt_round: eps < 0");
   QT_CHECK(opts->mode == QT_ROUND_SVD, QT_EINVAL,
            "tt_round: only QT_ROUND_SVD applies to a materialized train");
+  QT_CHECK(opts->precision == QT_PREC_F64, QT_EINVAL,
+           "tt_round: QT_PREC_F32 applies to the product-aware roundings only");
   ctx->ws_top = 0;
   const int lmax_cap = opts->max_rank > 0 ? opts->max_rank : (1 << 30);
   QT_TRY(qt::ws_reserve(ctx, qt::round_ws_layout(x, lmax_cap).bytes));

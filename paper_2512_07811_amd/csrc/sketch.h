@@ -20,10 +20,14 @@ SketchWs sketch_ws_layout(const qt_mpo* A, const qt_tt* y, const std::vector<int
 // left-orthogonal cores 0..n-2 and the centre in core n-1; ynorm2[b] = ||x~||^2.
 // rdiag (optional): [B][n+1][RD_MAX] sorted |R_jj| of the QR of Y_k written at
 // bond k+1 of each instance, the input of the rank-predictor features.
+// f32: the contractions that only choose the bases (right sketches W_k and
+// Y_k = Z_k W_{k+1}) run on the FP32-MFMA GEMM; the projection (T3, Z, M) and
+// everything after it stay FP64, so the output is still the exact orthogonal
+// projection of x onto the chosen subspace and ||x~||^2 is exact.
 constexpr int RD_MAX = 128;
 qt_status sketch_impl(qt_ctx ctx, const qt_mpo* A, const qt_tt* y, const cplx* omega,
                       const std::vector<int64_t>& om_off, const std::vector<int32_t>& ell,
-                      qt_tt* out, double* ynorm2, double* rdiag = nullptr);
+                      qt_tt* out, double* ynorm2, double* rdiag = nullptr, bool f32 = false);
 
 struct SandwichWs {
   int64_t E = 1, F = 1, G = 1;

@@ -167,7 +167,7 @@ __global__ void k_rdiag(const cplx* R, int64_t sR, int ldr, const int32_t* s_ran
 
 qt_status sketch_impl(qt_ctx ctx, const qt_mpo* A, const qt_tt* y, const cplx* omega,
                       const std::vector<int64_t>& om_off, const std::vector<int32_t>& ell,
-                      qt_tt* out, double* ynorm2, double* rdiag) {
+                      qt_tt* out, double* ynorm2, double* rdiag, bool f32) {
   const int n = y->n, B = y->batch;
   hipStream_t st = ctx->stream;
   SketchWs w = sketch_ws_layout(A, y, ell);
@@ -210,6 +210,7 @@ qt_status sketch_impl(qt_ctx ctx, const qt_mpo* A, const qt_tt* y, const cplx* o
   // ---- right pass: W_n = 1
   k_fill_one<<<(B + 127) / 128, 128, 0, st>>>(B, Wall + w.Woff[n], iW);
   for (int k = n - 1; k >= 1; --k) {
+    GemmF32Scope prec(f32);
     const int p = y->modes[k];
     const int lk = ell[k], lk1 = ell[k + 1];
     const int rd = A->ranks[k], rd1 = A->ranks[k + 1];
@@ -287,10 +288,12 @@ qt_status sketch_impl(qt_ctx ctx, const qt_mpo* A, const qt_tt* y, const cplx* o
     }
     const int lk1 = ell[k + 1];
     // Y_k = Z W_{k+1}   ((s p) x l_{k+1})
+    GemmF32Scope prec(f32);
     gemm_ex(st, B, 1, 1, dref(ro + k, rs, p), dconst(lk1), dref(ry + k + 1, rs, rd1), lk * p, lk1,
             mat(Zb, iZ, sref(ry + k + 1, rs, rd1), sc(1)), false,
             mat(Wall + w.Woff[k + 1], iW, sc(lk1), sc(1)), false, mat(Yb, iY, sc(lk1), sc(1)),
             one, false, dconst(1 << 30), (int64_t)rd1 * y->cap[k + 1]);
+    g_gemm_f32 = false;
     // Q_k = qr(Y_k) -> out core k, new rank s' -> ro[k+1]
     if (qb.V && qr_blocked_wanted(lk * p, lk1))
       qr_blocked(st, B, lk * p, lk1, dref(ro + k, rs, p), dconst(lk1), Yb, iY, Wq, iY, qb,

@@ -113,7 +113,8 @@ qt_status sround_impl(qt_ctx ctx, const qt_mpo* A, const qt_tt* y, const cplx* o
   double* es2 = (double*)ws_take(ctx, sizeof(double) * B);
   int32_t* rkl = (int32_t*)ws_take(ctx, sizeof(int32_t) * B * (n + 1));
   QT_CHECK(yn2 && delta && disc2 && es2 && rkl, QT_ENOMEM, "sketch rounding: workspace too small");
-  QT_TRY(sketch_impl(ctx, A, y, omega, *om_off, ell, out, yn2, rdiag));
+  QT_TRY(sketch_impl(ctx, A, y, omega, *om_off, ell, out, yn2, rdiag,
+                     o->precision == QT_PREC_F32));
   k_budget<<<(B + 127) / 128, 128, 0, st>>>(B, n - 1, o->eps, xn2, yn2, delta, disc2, es2, fail,
                                             ctx->counters);
   if (o->mode == QT_ROUND_SKETCH && n > 1) {
@@ -167,7 +168,8 @@ extern "C" qt_status tt_sketch_round(qt_ctx ctx, const qt_mpo* A, const qt_tt* y
   QT_CHECK(out->data != y->data, QT_EINVAL, "tt_sketch_round: out aliases y");
   QT_CHECK(opts->mode == QT_ROUND_SKETCH || opts->mode == QT_ROUND_LEARNED, QT_EINVAL,
            "tt_sketch_round: mode must be QT_ROUND_SKETCH or QT_ROUND_LEARNED");
-  QT_CHECK(opts->precision == QT_PREC_F64, QT_EINVAL, "tt_sketch_round: precision not available");
+  QT_CHECK(opts->precision == QT_PREC_F64 || opts->precision == QT_PREC_F32, QT_EINVAL,
+           "tt_sketch_round: precision must be QT_PREC_F64 or QT_PREC_F32");
   const int n = y->n;
   std::vector<int32_t> ell;
   std::vector<int64_t> off;

@@ -467,12 +467,13 @@ def tt_sandwich(ctx: Context, Q: DeviceMPO, y: DeviceTT, scale: float = 1.0):
 
 def tt_sketch_round(ctx: Context, A: DeviceMPO, y: DeviceTT, xnorm2, out: DeviceTT,
                     omega: DeviceTT = None, eps: float = 0.0, max_rank: int = 0,
-                    mode: int = ROUND_SKETCH, oversample: int = 8, seed: int = 1):
+                    mode: int = ROUND_SKETCH, oversample: int = 8, seed: int = 1,
+                    precision: int = PREC_F64):
     """Product-aware rounding of A y into out; returns (err, fail) device tensors [batch]."""
     torch = _torch()
     err = torch.zeros(y.batch, dtype=torch.float64, device=y.data.device)
     fail = torch.zeros(y.batch, dtype=torch.int32, device=y.data.device)
-    o = round_opts(eps, max_rank, mode, 0, PREC_F64, oversample, seed)
+    o = round_opts(eps, max_rank, mode, 0, precision, oversample, seed)
     om = C.byref(omega.desc()) if omega is not None else None
     _check(ctx.lib.tt_sketch_round(ctx.h, C.byref(A.desc()), C.byref(y.desc()), om, C.byref(o),
                                    C.c_void_p(xnorm2.data_ptr()), C.byref(out.desc()),
