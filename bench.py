@@ -199,15 +199,31 @@ def round_microbench(ctx, ranks, batches=(1,), L=8, max_runs=100, budget_s=3.0):
         times = times[1:]                      # the first run pays the workspace set-up
         r_out = x.rank_array()[0].tolist()
         ms = float(np.mean(times))
+        # the same trains compressed by polar decomposition (QT_ROUND_POLAR)
+        ptimes = []
+        t_start = time.perf_counter()
+        while len(ptimes) < max_runs and (len(ptimes) < 3 or time.perf_counter() - t_start < budget_s):
+            x.data.copy_(d0)
+            x.ranks.copy_(r0)
+            ev0.record()
+            qtt.tt_round(ctx, x, 0.0, mode=qtt.ROUND_POLAR, seed=1)
+            ev1.record()
+            ev1.synchronize()
+            ptimes.append(ev0.elapsed_time(ev1))
+        pms = float(np.mean(ptimes[1:]))
         fl = B * round_model_flops(modes, rk, r_out)
         out.append({"R": R, "batch": B, "runs": len(times), "ms": ms, "model_gflop": fl / 1e9,
-                    "gflops": fl / (ms * 1e-3) / 1e9, "frac_fp64_peak": fl / (ms * 1e-3) / 78.6e12})
+                    "gflops": fl / (ms * 1e-3) / 1e9, "frac_fp64_peak": fl / (ms * 1e-3) / 78.6e12,
+                    "polar_ms": pms, "chi_polar_over_svd": pms / ms})
         print(f"[bench] tt_round R={R} batch {B}: {ms:.3f} ms, {out[-1]['gflops']:.1f} GFLOP/s "
-              f"({len(times)} runs)", file=sys.stderr, flush=True)
+              f"({len(times)} runs); polar {pms:.3f} ms", file=sys.stderr, flush=True)
         del x, d0, r0
     return {"family": f"i.i.d. complex N(0,1) cores, {n} cores (modes 3, 2, ..., 2), uniform "
                       f"rank R, eps 0", "flop_model": "Householder QR 2mN^2 - 2N^3/3, square "
-                      "SVD 21N^3, absorb/carry products 2mnk; x4 for complex", "results": out}
+                      "SVD 21N^3, absorb/carry products 2mnk; x4 for complex",
+            "polar": "the same calls with QT_ROUND_POLAR (polar-decomposition truncation on the "
+                     "GEMM); chi = tau_polar / tau_SVD as the paper's appendix defines it",
+            "results": out}
 
 
 def _qr_flops(m, N):

@@ -53,6 +53,7 @@ typedef int32_t qt_status;
 #define QT_ROUND_SVD      0   /* QR sweep + truncated-SVD sweep (Sec. 2.2)       */
 #define QT_ROUND_SKETCH   1   /* randomized range sketch + SVD truncation        */
 #define QT_ROUND_LEARNED  2   /* sketch at MLP-predicted ranks, SVD fallback     */
+#define QT_ROUND_POLAR    3   /* QR sweep + polar-decomposition truncation       */
 
 /* Contraction precision of the product-aware roundings (tt_sketch_round,
  * ls_iterate / homogenize in the sketch and learned modes; QT_EINVAL
@@ -216,7 +217,22 @@ qt_status tt_add(qt_ctx ctx, double alpha_re, double alpha_im, const qt_tt* x,
  * err_out (device [B], may be NULL): sqrt(sum of squared discarded tails)/||x||.
  * norm_out (device [B], may be NULL): ||x||_F before rounding.
  * QT_ECAPACITY (nothing launched) when a bond's SVD block, min(cap[k],
- * p_k min(cap[k+1], max_rank)), exceeds 1024 columns. */
+ * p_k min(cap[k+1], max_rank)), exceeds 1024 columns.
+ * QT_ROUND_POLAR (Sec. 2.2, compression via polar decomposition): the same
+ * left QR sweep, then right to left every centre A (r_k x p_k r_{k+1}) is
+ * split without an SVD: A^H = U H (polar factor by odd-polynomial
+ * Newton-Schulz-type iterations on the MFMA GEMM), U' = sign(H - d~ I) by the
+ * same iteration, P+ = (I + U')/2, C+ an orthonormal basis of range(P+) by
+ * subspace iteration (QR), core k = (U C+)^H, H C+ carried to core k-1.  The
+ * cutoff is absolute, d~ = delta / min(r_k, p_k r_{k+1}), so every singular
+ * value above it is kept: ||x - x~|| <= eps ||x|| with ranks at least those
+ * of QT_ROUND_SVD; singular values within about 5 % of d~ may land on
+ * either side (the iteration counts resolve |sigma - d~| down to a
+ * twentieth of d~).  max_rank keeps the directions of P+ that H ranks first
+ * (subspace iteration with H^2, 4 steps).
+ * err_out: sqrt(sum_k ||A_k - H C+ (U C+)^H||^2)/||x||, the discarded weight
+ * of each centre formed explicitly.
+ * opts->seed seeds the Gaussian start block of the subspace iteration. */
 qt_status tt_round(qt_ctx ctx, qt_tt* x, const qt_round_opts* opts, double* err_out,
                    double* norm_out);
 

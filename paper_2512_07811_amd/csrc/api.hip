@@ -1112,7 +1112,8 @@ qt_status qt_workspace_query(const qt_tt* x, const qt_round_opts* opts, size_t* 
   QT_CHECK(x && opts && bytes, QT_EINVAL, "qt_workspace_query: null argument");
   QT_TRY(tt_validate(x, "x"));
   const int lmax_cap = opts->max_rank > 0 ? opts->max_rank : (1 << 30);
-  *bytes = (round_ws_layout(x, lmax_cap).bytes + 255) & ~(size_t)255;
+  *bytes = (round_ws_layout(x, lmax_cap, opts->mode == QT_ROUND_POLAR).bytes + 255) &
+           ~(size_t)255;
   return QT_OK;
 }
 

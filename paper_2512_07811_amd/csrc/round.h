@@ -2,6 +2,7 @@
 #pragma once
 
 #include "kernels.h"
+#include "polar.h"
 
 namespace qt {
 
@@ -12,8 +13,10 @@ struct RoundWs {
   int64_t sb_v = 0, sb_t = 0, sb_w = 0, sb_tau = 0;   // blocked QRs of the SVD blocks
   size_t bytes = 0;
   size_t sweep_bytes = 0;   // extra for the fast SVD (reflectors, R V, tau, sigma)
+  bool polar = false;       // polar-decomposition truncation (QT_ROUND_POLAR)
+  PolarSizes pol;
 };
-RoundWs round_ws_layout(const qt_tt* x, int lmax_cap);
+RoundWs round_ws_layout(const qt_tt* x, int lmax_cap, bool polar = false);
 
 // left_only: QR sweep that carries only the R factors and reports the norm
 // (no truncation; Q is never formed, x's cores are consumed as scratch).

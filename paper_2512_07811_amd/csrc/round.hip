@@ -19,7 +19,7 @@ __global__ void k_init_left(int n, int batch, const int32_t* ranks, int32_t* rk_
     rk_left[(int64_t)b * (n + 1) + k] = (k == 0 || k == n) ? 1 : ranks[(int64_t)b * (n + 1) + k];
 }
 
-RoundWs round_ws_layout(const qt_tt* x, int lmax_cap) {
+RoundWs round_ws_layout(const qt_tt* x, int lmax_cap, bool polar) {
   RoundWs w;
   const int n = x->n;
   int64_t slot = 1, rr = 1, vv = 1, carry = 1, tau = 1;
@@ -70,6 +70,16 @@ RoundWs round_ws_layout(const qt_tt* x, int lmax_cap) {
   if (w.qb_v > 0)
     w.bytes += sizeof(cplx) * B * (w.qb_v + w.qb_t + 2 * w.qb_w) + sizeof(double) * B * w.qb_tau +
                sizeof(int32_t) * B + 8 * 256;
+  if (polar && n > 1) {
+    int nc = 1, mc = 1;
+    for (int k = 1; k < n; ++k) {
+      nc = std::max(nc, x->cap[k]);
+      mc = std::max(mc, x->modes[k] * std::min(x->cap[k + 1], lmax_cap));
+    }
+    w.polar = true;
+    w.pol = polar_sizes(nc, mc, std::min(nc, lmax_cap));
+    w.bytes += polar_ws_bytes(B, w.pol);
+  }
   return w;
 }
 
@@ -79,7 +89,8 @@ qt_status round_impl(qt_ctx ctx, qt_tt* x, const qt_round_opts* o, double* err_o
   const int n = x->n, B = x->batch;
   hipStream_t st = ctx->stream;
   const int lmax_cap = o->max_rank > 0 ? o->max_rank : (1 << 30);
-  RoundWs w = round_ws_layout(x, lmax_cap);
+  const bool polar = o->mode == QT_ROUND_POLAR;
+  RoundWs w = round_ws_layout(x, lmax_cap, polar);
   QT_CHECK(w.max_nb <= 1024, QT_ECAPACITY, "tt_round: SVD block above 1024 columns");
   const int sweeps = o->jacobi_max_sweeps > 0 ? o->jacobi_max_sweeps : ctx->jacobi_default;
   cplx* scratch = (cplx*)ws_take(ctx, sizeof(cplx) * B * w.slot);
@@ -156,6 +167,13 @@ qt_status round_impl(qt_ctx ctx, qt_tt* x, const qt_round_opts* o, double* err_o
   // ---- right truncation sweep
   SweepBufs buf{scratch, Bsv, Vb, Cb, w.slot, w.vv, w.carry};
   QT_TRY(take_sweep_extra(ctx, B, w, buf));
+  PolarWs pw{};
+  if (polar) {
+    QT_TRY(polar_ws_take(ctx, B, w.pol, pw));
+    buf.polar = &pw;
+    buf.polar_nq = polar_quintic_steps(o->eps, n - 1, std::min(w.pol.ncap, w.pol.mcap));
+    buf.polar_seed = o->seed;
+  }
   QT_TRY(right_sweep_impl(ctx, x, rkl, scratch, w.slot, buf, delta, disc2, lmax_cap, sweeps, svlog,
                           svstride_bond, svstride_inst));
   finalize_err(st, B, disc2, norm, err_out, norm_out);
@@ -232,7 +250,11 @@ qt_status right_sweep_impl(qt_ctx ctx, qt_tt* x, const int32_t* rkl, const cplx*
     const bool prof = prof_on(PROF_SVD);
     if (prof) g_prof->begin();
     const int nsw = std::min(mcap, ccap) > 100 ? sweeps_glb : sweeps;
-    const bool ok = svd_trunc_fast(st, B, mcap, ccap, dref(rkl + k, rs), dref(rk + k + 1, rs, p),
+    const bool ok = buf.polar ?
+        (polar_trunc(st, B, mcap, ccap, dref(rkl + k, rs), dref(rk + k + 1, rs, p), in, sin,
+                     *buf.polar, X + x->offsets[k], sX, buf.C, buf.carry, rk + k, rs, delta,
+                     disc2, lmax, buf.polar_nq, buf.polar_seed, (uint64_t)k), true) :
+        svd_trunc_fast(st, B, mcap, ccap, dref(rkl + k, rs), dref(rk + k + 1, rs, p),
                                    in, sin, buf.Bsv, buf.U, buf.slot, buf.V, buf.RV, buf.vv,
                                    buf.tau, buf.nbmax, buf.qb.V ? &buf.qb : nullptr,
                                    X + x->offsets[k], sX, buf.C,
@@ -260,12 +282,13 @@ extern "C" qt_status tt_round(qt_ctx ctx, qt_tt* x, const qt_round_opts* opts, d
   QT_CHECK(ctx && x && opts, QT_EINVAL, "tt_round: null argument");
   QT_TRY(qt::tt_validate(x, "x"));
   QT_CHECK(opts->eps >= 0.0, QT_EINVAL, "tt_round: eps < 0");
-  QT_CHECK(opts->mode == QT_ROUND_SVD, QT_EINVAL,
-           "tt_round: only QT_ROUND_SVD applies to a materialized train");
+  QT_CHECK(opts->mode == QT_ROUND_SVD || opts->mode == QT_ROUND_POLAR, QT_EINVAL,
+           "tt_round: QT_ROUND_SVD or QT_ROUND_POLAR apply to a materialized train");
   QT_CHECK(opts->precision == QT_PREC_F64, QT_EINVAL,
            "tt_round: QT_PREC_F32 applies to the product-aware roundings only");
   ctx->ws_top = 0;
   const int lmax_cap = opts->max_rank > 0 ? opts->max_rank : (1 << 30);
-  QT_TRY(qt::ws_reserve(ctx, qt::round_ws_layout(x, lmax_cap).bytes));
+  QT_TRY(qt::ws_reserve(ctx, qt::round_ws_layout(x, lmax_cap,
+                                                 opts->mode == QT_ROUND_POLAR).bytes));
   return qt::round_impl(ctx, x, opts, err_out, norm_out, false, nullptr, 0, 0);
 }

@@ -2,6 +2,7 @@
 #pragma once
 
 #include "kernels.h"
+#include "polar.h"
 #include "round.h"
 
 namespace qt {
@@ -56,6 +57,10 @@ struct SweepBufs {
   double* tau; // nbmax entries: reflector scalars, then 4 for the SVD's sizes
   int64_t nbmax;
   QrBlkWs qb;  // blocked QRs of large SVD blocks (V null when none)
+  // polar-decomposition truncation instead of the SVD (null: SVD)
+  const PolarWs* polar = nullptr;
+  int polar_nq = 0;
+  uint64_t polar_seed = 0;
 };
 qt_status take_sweep_extra(qt_ctx ctx, int B, const RoundWs& w, SweepBufs& buf);
 qt_status right_sweep_impl(qt_ctx ctx, qt_tt* x, const int32_t* rkl, const cplx* center,

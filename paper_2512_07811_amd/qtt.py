@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libqtthom.so")
 
 QT_OK, QT_NOT_CONVERGED = 0, 1
-ROUND_SVD, ROUND_SKETCH, ROUND_LEARNED = 0, 1, 2
+ROUND_SVD, ROUND_SKETCH, ROUND_LEARNED, ROUND_POLAR = 0, 1, 2, 3
 PREC_F64, PREC_F32 = 0, 1
 
 EXPORTS = ["qt_ctx_create", "qt_ctx_destroy", "qt_last_error", "qt_ctx_sync",
