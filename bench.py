@@ -54,9 +54,9 @@ CONFIGS = {
 
 # HBM bytes per k_gemm_ex launch from two copy-calibrated rocprofv3 counter runs
 # (FETCH_SIZE, WRITE_SIZE) of this bench on the learned path; the summary with the
-# commands is profiles/k_gemm_ex_sphere256_hbm_traffic.md.  Reported only for
-# the workload and mode it was measured on.
-GEMM_TRAFFIC = {("sphere256", "learned"): 26.69e6}
+# commands is in profiles/.  Reported only for the workload and mode it was
+# measured on, and only while the kernel is the one measured.
+GEMM_TRAFFIC = {}
 
 # accept factor of the ablation's relaxed learned window
 RELAXED_ACCEPT = 1.25
@@ -556,6 +556,8 @@ def main():
         g = main["gemm"]
         g_ach = g["gemm_flops"] / (g["ms"] * 1e-3) / 1e12 if g["ms"] > 0 else None
         classes = {"gemm": {"achieved": g_ach, "flops_per_step": g["gemm_flops"],
+                            "bytes_per_step": g["gemm_bytes"],
+                            "algorithmic_bytes_per_launch": g["gemm_bytes"] / max(g["launches"], 1),
                             "model": "structured GEMMs: 8 flops per complex multiply-add, counted "
                                      "on the device per launch"},
                    "qr": {"achieved": qr_model * B / (main["qr"]["ms"] * 1e-3) / 1e12
@@ -567,7 +569,8 @@ def main():
                        "qr": "QR of the sketches (register-panel blocked QR and its products)",
                        "svd": "truncated SVD (QRs + one-sided Jacobi)"}[dom],
             "bound": "alu", "achieved": ach, "peak": 78.6, "unit": "TFLOP/s",
-            "frac": ach / 78.6 if ach else None, "traffic": None,
+            "frac": ach / 78.6 if ach else None,
+            "traffic": GEMM_TRAFFIC.get((args.config, args.mode)) if dom == "gemm" else None,
             "avg_launch_us": 1000.0 * main[dom]["ms"] / max(main[dom]["launches"], 1),
             "kernel_ms_per_step": {k: v["ms"] for k, v in main.items()},
             "launches_per_step": {k: v["launches"] for k, v in main.items()},

@@ -388,9 +388,20 @@ static qt_status residual_norm(qt_ctx ctx, const qt_tt* enew, const qt_tt* e, qt
   ctx->ws_top = mark;
   k_res_choose<<<(B + 127) / 128, 128, 0, st>>>(B, n, pairs, pairs + 2 * B, pairs + 4 * B,
                                                 d->ranks, rdot, use);
-  qt_round_opts po = ro;
-  po.mode = QT_ROUND_SVD;
-  QT_TRY(round_impl(ctx, d, &po, nullptr, dnorm, true, nullptr, 0, 0));
+  // outside a graph capture, skip the sweep's launches when every instance
+  // took the dot value (one small read; its kernels would all exit at once)
+  bool sweep = true;
+  if (!ctx->capturing) {
+    std::vector<int32_t> hu(B);
+    QT_HIP(hipMemcpyAsync(hu.data(), use, sizeof(int32_t) * B, hipMemcpyDeviceToHost, st));
+    QT_HIP(hipStreamSynchronize(st));
+    sweep = std::any_of(hu.begin(), hu.end(), [](int32_t u) { return u == 0; });
+  }
+  if (sweep) {
+    qt_round_opts po = ro;
+    po.mode = QT_ROUND_SVD;
+    QT_TRY(round_impl(ctx, d, &po, nullptr, dnorm, true, nullptr, 0, 0));
+  }
   k_res_merge<<<(B + 127) / 128, 128, 0, st>>>(B, use, rdot, dnorm);
   QT_HIP(hipGetLastError());
   return QT_OK;
