@@ -46,22 +46,42 @@ __device__ inline int acc_row(int r, int lk) {
 // F32 (mixed precision): operands rounded to FP32 as they enter LDS, products
 // and sums on v_mfma_f32_16x16x4f32 (FP32 accumulation), results widened to
 // FP64 on the way out (split-K partials summed in FP64).
+// Tile order: workgroup w of the 1-D grid runs on XCD w mod 8 (round-robin
+// dispatch), so w is first mapped to the tile t = (w mod 8) * (full / 8) +
+// w / 8 (the last total mod 8 workgroups keep t = w): each XCD takes a
+// contiguous run of tiles.  Along that run the tiles walk N first when A is the
+// larger operand (the run's tiles of one row share the A panel in that XCD's
+// L2) and M first otherwise.
+__device__ inline int64_t xcd_tile(int64_t w, int64_t total) {
+  const int64_t full = total - total % 8;
+  return w < full ? (w % 8) * (full / 8) + w / 8 : w;
+}
+
 template <bool CA, bool CB, int TM, int TN, bool F32>
-__global__ __launch_bounds__(256) void k_gemm_ex(int nb1, int nb2, int ntn, Dim Md, Dim Nd,
-                                                 Dim Kd, Mat A, Mat B, Mat C, cplx alpha,
-                                                 int accumulate, Dim lim1,
+__global__ __launch_bounds__(256) void k_gemm_ex(int nb1, int nb2, int ntn, int mtn, int nfast,
+                                                 Dim Md, Dim Nd, Dim Kd, Mat A, Mat B, Mat C,
+                                                 cplx alpha, int accumulate, Dim lim1,
                                                  unsigned long long* counters, cplx* part,
                                                  int Mcap, int Ncap, int64_t items) {
   const int nbt = nb1 * nb2;
-  const int tn = blockIdx.x % ntn;
-  const int z = blockIdx.x / ntn;
+  const int64_t t = xcd_tile(blockIdx.x, (int64_t)gridDim.x);
+  int tn, tm, z;
+  if (nfast) {
+    tn = (int)(t % ntn);
+    tm = (int)((t / ntn) % mtn);
+    z = (int)(t / ((int64_t)ntn * mtn));
+  } else {
+    tm = (int)(t % mtn);
+    tn = (int)((t / mtn) % ntn);
+    z = (int)(t / ((int64_t)ntn * mtn));
+  }
   const int b = z / nbt;
   const int rem = z % nbt;
   const int b1 = rem / nb2, b2 = rem % nb2;
   const int M = dimv(Md, b), N = dimv(Nd, b), K = dimv(Kd, b);
   constexpr int FM = TM / 32, FN = TN / 32;     // MFMA tiles per wave
   constexpr int EA = TM * XT_K / 256, EB = TN * XT_K / 256;   // panel elements per thread
-  const int m0 = blockIdx.y * TM, n0 = tn * TN;
+  const int m0 = tm * TM, n0 = tn * TN;
   if (m0 >= M || n0 >= N || b1 >= dimv(lim1, b)) return;
   const int splits = gridDim.z, sk = blockIdx.z;
   int kbeg = 0, kend = K;
@@ -240,11 +260,13 @@ struct GemmArgs {
 template <int TM, int TN, bool F32>
 static void launch_tile(hipStream_t st, int splits, bool cA, bool cB, const GemmArgs& a) {
   const int ntn = (a.Ncap + TN - 1) / TN, mtn = (a.Mcap + TM - 1) / TM;
-  dim3 grid((unsigned)((int64_t)ntn * a.items), mtn, splits);
+  dim3 grid((unsigned)((int64_t)ntn * mtn * a.items), 1, splits);
+  // walk N first when A (Mcap x K) is the larger operand
+  const int nfast = a.Mcap >= a.Ncap ? 1 : 0;
 #define QT_GEMM_LAUNCH(X, Y)                                                                     \
-  k_gemm_ex<X, Y, TM, TN, F32><<<grid, 256, 0, st>>>(a.nb1, a.nb2, ntn, a.M, a.N, a.K, a.A, a.B, a.C, \
-                                                a.alpha, a.acc, a.lim1, a.cnt, a.part, a.Mcap,   \
-                                                a.Ncap, a.items)
+  k_gemm_ex<X, Y, TM, TN, F32><<<grid, 256, 0, st>>>(a.nb1, a.nb2, ntn, mtn, nfast, a.M, a.N,     \
+                                                     a.K, a.A, a.B, a.C, a.alpha, a.acc, a.lim1, \
+                                                     a.cnt, a.part, a.Mcap, a.Ncap, a.items)
   if (!cA && !cB) QT_GEMM_LAUNCH(false, false);
   else if (cA && !cB) QT_GEMM_LAUNCH(true, false);
   else if (!cA && cB) QT_GEMM_LAUNCH(false, true);

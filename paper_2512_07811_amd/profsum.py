@@ -93,8 +93,8 @@ def cmd_counters(a):
     con = sqlite3.connect(a.db)
     cols = [r[1] for r in con.execute("pragma table_info(counters_collection)")]
     kcol = "kernel_name" if "kernel_name" in cols else "name"
-    rows = list(con.execute(f"select {kcol}, counter_name, value, dispatch_id, start "
-                            f"from counters_collection order by start"))
+    rows = list(con.execute(f"select {kcol}, counter_name, value, dispatch_id, dispatch_id "
+                            f"from counters_collection order by dispatch_id"))
     keep = None
     if a.steps:
         # dispatches of the timed LS iterations (as for ``kernels``)
