@@ -302,12 +302,19 @@ qt_status tt_sandwich(qt_ctx ctx, const qt_mpo* Q, const qt_tt* y, double scale,
 /* ---- Algorithm 2 ------------------------------------------------------------ */
 
 /* Operands of one cell problem on a 2^L-per-axis grid: core 0 is the
- * component (control) core of mode 3, cores 1..3L the x, y, z bits. */
+ * component (control) core of mode d, cores 1..3L the x, y, z bits.
+ * Scalar conductivity (Sec. 3.1 in its conductivity form): d = 3 (gradient
+ * components).  Linear elasticity (Sec. 3.1, App. A): d = 6 (Voigt strain
+ * with engineering shears), Kp the Voigt operator C - C0 (a full 6 x 6
+ * component core), G the Green-Eshelby operator (6 x 6 component core), kp
+ * absent (n = 0) and G2 = G^H G given. */
 typedef struct {
   int32_t L;
-  qt_tt kp;                 /* k' = k - k0, all-ones control core                */
-  qt_mpo Kp;                /* the same k' as a diagonal operator (sketch modes) */
-  qt_mpo K2;                /* (k')^2 as a diagonal operator: ||k' e||^2 = <e, K2 e> */
+  qt_tt kp;                 /* k' = k - k0, all-ones control core (n = 0: the    */
+                            /* material acts through Kp on every path)           */
+  qt_mpo Kp;                /* the material operator (k' as a diagonal operator, */
+                            /* or C - C0)                                        */
+  qt_mpo K2;                /* Kp^H Kp: ||Kp e||^2 = <e, K2 e>                   */
   double k0;                /* reference conductivity: ||G t||^2 = <t, G t>/k0   */
   qt_mpo S;                 /* SFFT operator (Q_L per axis, identity on core 0)  */
   qt_mpo Sinv;              /* its adjoint                                       */
@@ -317,6 +324,8 @@ typedef struct {
   qt_tt SE;                 /* S applied to E (rank 1, batch = field batch);     */
                             /* read by the sketch modes, which round the last    */
                             /* step as S^dagger (S E - eps^) = E - S^dagger eps^ */
+  qt_mpo G2;                /* G^H G for ||G t||^2 = <t, G2 t> (n = 0: use the   */
+                            /* projector identity <t, G t>/k0 of conductivity)   */
 } qt_operands;
 
 typedef struct {
@@ -347,10 +356,13 @@ qt_status ls_iterate(qt_ctx ctx, const qt_operands* ops, qt_tt* e, const qt_solv
 
 /* Full solve: e_0 = E (per instance), iterate until every residual < tol or
  * max_iter; then A_eff[b][c] = Re <k_sel[c], e_b> / N^3 (Appendix A).
- * k_sel: three TTs of k (not k') with unit control cores, each holding one
- *   train for every field or one train per field (batch = e->batch).
+ * k_sel: d TTs (d = the field's component mode), train c holding row c of
+ *   the material (k e_c for conductivity, row c of C in Voigt form for
+ *   elasticity), each one train for every field or one per field
+ *   (batch = e->batch); A_eff[b][c] is then the mean flux or the mean stress
+ *   component c: column j of the effective tensor for the load e_j.
  * e: field batch used as the iterate (capacities as for ls_iterate).
- * A_eff: host [B][3]; iters: host [B] (iterations to convergence);
+ * A_eff: host [B][d]; iters: host [B] (iterations to convergence);
  * residuals: host [max_iter][B] (may be NULL). */
 qt_status homogenize(qt_ctx ctx, const qt_operands* ops, const qt_tt* k_sel, qt_tt* e,
                      const qt_solve_opts* opts, double* A_eff, int32_t* iters,

@@ -220,19 +220,25 @@ static std::vector<int32_t> natural_caps(const std::vector<int32_t>& modes) {
 }
 
 static qt_status validate_ops(const qt_operands* ops, const qt_tt* e) {
-  QT_TRY(tt_validate(&ops->kp, "operands.kp"));
+  // kp (the scalar material train) is optional: without it the material acts
+  // through the operator Kp on every path (elasticity: a Voigt operator)
+  if (ops->kp.n > 0) QT_TRY(tt_validate(&ops->kp, "operands.kp"));
   QT_TRY(tt_validate(&ops->E, "operands.E"));
   QT_TRY(tt_validate(e, "e"));
   const int n = e->n;
   QT_CHECK(n == 3 * ops->L + 1, QT_EINVAL, "operands: n != 3L+1");
-  QT_CHECK(ops->kp.n == n && ops->E.n == n && ops->S.n == n && ops->Sinv.n == n && ops->G.n == n,
+  QT_CHECK((ops->kp.n == n || (ops->kp.n == 0 && ops->Kp.n == n)) && ops->E.n == n &&
+               ops->S.n == n && ops->Sinv.n == n && ops->G.n == n,
            QT_EINVAL, "operands: core counts differ");
-  QT_CHECK(ops->kp.batch == 1, QT_EINVAL, "operands: kp must be a single train");
+  QT_CHECK(ops->kp.n == 0 || ops->kp.batch == 1, QT_EINVAL, "operands: kp must be a single train");
+  QT_CHECK(ops->G2.n == 0 || ops->G2.n == n, QT_EINVAL, "operands: G2 core count");
   QT_CHECK(ops->E.batch == e->batch, QT_EINVAL, "operands: E batch must equal e batch");
   QT_CHECK(ops->E_norm != nullptr, QT_EINVAL, "operands: E_norm missing");
   for (int b = 0; b < e->batch; ++b)
     QT_CHECK(ops->E_norm[b] > 0.0, QT_EINVAL, "operands: every load E must be nonzero");
-  for (int k = 0; k < n; ++k) QT_CHECK(e->modes[k] == (k == 0 ? 3 : 2), QT_EINVAL, "e: modes must be [3,2,...]");
+  for (int k = 0; k < n; ++k)
+    QT_CHECK(e->modes[k] == (k == 0 ? ops->E.modes[0] : 2) && ops->E.modes[k] == e->modes[k],
+             QT_EINVAL, "e: modes must be [d,2,...] with d the mode of E's component core");
   return QT_OK;
 }
 
@@ -266,7 +272,7 @@ static IterPlan plan_iteration(const qt_operands* ops, const qt_tt* e, int rmax)
   for (int k = 0; k <= n; ++k) {
     int ce = e->cap[k];
     P.rc[k] = std::min(std::min(nat[k], rmax > 0 ? rmax : ce), ce);
-    P.c1[k] = clampi((int64_t)ops->kp.cap[k] * ce);
+    P.c1[k] = clampi((int64_t)(ops->kp.n ? ops->kp.cap[k] : ops->Kp.ranks[k]) * ce);
     int r1 = std::min<int64_t>(P.c1[k], std::min<int64_t>(nat[k], rmax > 0 ? rmax : P.c1[k]));
     P.c2[k] = clampi((int64_t)ops->S.ranks[k] * r1);
     int r2 = std::min<int64_t>(P.c2[k], std::min<int64_t>(nat[k], rmax > 0 ? rmax : P.c2[k]));
@@ -417,7 +423,8 @@ static qt_status iterate_once(qt_ctx ctx, const qt_operands* ops, qt_tt* e, cons
   std::vector<int32_t> s1, s2, s3, s5;
   // tau = round(k' (.) e)
   qt_tt t1 = P.l1.view(bufA, rA, B);
-  QT_TRY(hadamard_impl(ctx, &ops->kp, e, &t1));
+  if (ops->kp.n) QT_TRY(hadamard_impl(ctx, &ops->kp, e, &t1));
+  else QT_TRY(mpo_impl(ctx, &ops->Kp, e, &t1));
   QT_TRY(round_impl(ctx, &t1, &ro, nullptr, nullptr, false, nullptr, 0, 0));
   ctx->ws_top = mark;
   qt_tt t1r = shrink(t1, P.c1, rmax, s1);
@@ -590,7 +597,7 @@ static SketchPlan plan_sketch(const qt_operands* ops, const qt_tt* e, const qt_r
   yv.cap = P.c2r.data();
   ov = P.l3.view(nullptr, nullptr, B);
   ws = std::max(ws, sround_ws_layout(&ops->G, &yv, &ov, P.ell3, lmax).bytes);
-  ws = std::max(ws, sandwich_ws_layout(&ops->G, &yv).bytes);
+  ws = std::max(ws, sandwich_ws_layout(ops->G2.n ? &ops->G2 : &ops->G, &yv).bytes);
   yv.cap = P.c5.data();
   ov = P.l4.view(nullptr, nullptr, B);
   ws = std::max(ws, sround_ws_layout(&ops->Sinv, &yv, &ov, P.ell4, lmax).bytes);
@@ -788,8 +795,10 @@ static qt_status iterate_once_sketch(qt_ctx ctx, const qt_operands* ops, qt_tt* 
   QT_TRY(round_step(ctx, 1, &ops->S, &t1r, P.ell2, ro, xn2, &t2, err_dev, iter_id, learned, logging,
                     lo, &sp2, lb.err2));
   qt_tt t2r = view_caps(t2, P.c2r);
-  // eps^ = R(G tau^);  ||G t||^2 = <t, G t>/k0
-  QT_TRY(sandwich_impl(ctx, &ops->G, &t2r, 1.0 / ops->k0, xn2));
+  // eps^ = R(G tau^);  ||G t||^2 = <t, G t>/k0 (scalar conductivity: k0 G is a
+  // projector), or <t, G2 t> with G2 = G^H G given as an operand (elasticity)
+  if (ops->G2.n) QT_TRY(sandwich_impl(ctx, &ops->G2, &t2r, 1.0, xn2));
+  else QT_TRY(sandwich_impl(ctx, &ops->G, &t2r, 1.0 / ops->k0, xn2));
   ctx->ws_top = mark;
   qt_tt t3 = P.l3.view(bufA, rA, B);
   QT_TRY(round_step(ctx, 2, &ops->G, &t2r, P.ell3, ro, xn2, &t3, err_dev, iter_id, learned, logging,
@@ -850,12 +859,15 @@ struct Solver {
 // Arena bytes homogenize needs beyond the iteration: its residuals and the
 // three A_eff dot products (environments of k_sel[c] against the field).
 static size_t homogenize_extra(const qt_tt* k_sel, const qt_tt* e) {
-  const int B = e->batch;
+  const int B = e->batch, d = e->modes[0];
   size_t need = 4096 + sizeof(double) * 4 * B;
   int64_t env = 1, tcap = 1;
-  for (int k = 0; k <= e->n; ++k) env = std::max<int64_t>(env, (int64_t)k_sel[0].cap[k] * e->cap[k]);
-  for (int k = 0; k < e->n; ++k)
-    tcap = std::max<int64_t>(tcap, (int64_t)k_sel[0].cap[k] * e->modes[k] * e->cap[k + 1]);
+  for (int c = 0; c < d; ++c) {
+    for (int k = 0; k <= e->n; ++k)
+      env = std::max<int64_t>(env, (int64_t)k_sel[c].cap[k] * e->cap[k]);
+    for (int k = 0; k < e->n; ++k)
+      tcap = std::max<int64_t>(tcap, (int64_t)k_sel[c].cap[k] * e->modes[k] * e->cap[k + 1]);
+  }
   return need + sizeof(cplx) * B * (2 * env + tcap) + 1024;
 }
 
@@ -1134,7 +1146,7 @@ qt_status qt_ls_workspace_query(const qt_operands* ops, const qt_tt* k_sel, cons
   QT_TRY(validate_ops(ops, e));
   QT_TRY(validate_field_cap(e, opts->round.max_rank));
   if (k_sel)
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < e->modes[0]; ++c) {
       QT_TRY(tt_validate(&k_sel[c], "k_sel"));
       QT_CHECK(k_sel[c].n == e->n, QT_EINVAL, "qt_ls_workspace_query: k_sel cores");
     }
@@ -1240,7 +1252,8 @@ qt_status homogenize(qt_ctx ctx, const qt_operands* ops, const qt_tt* k_sel, qt_
   QT_CHECK(ctx && ops && k_sel && e && opts && A_eff && iters, QT_EINVAL, "homogenize: null argument");
   enter(ctx);
   QT_TRY(validate_ops(ops, e));
-  for (int c = 0; c < 3; ++c) {
+  const int d = e->modes[0];   // components of the field (3 conductivity, 6 elasticity)
+  for (int c = 0; c < d; ++c) {
     QT_TRY(tt_validate(&k_sel[c], "k_sel"));
     QT_CHECK((k_sel[c].batch == 1 || k_sel[c].batch == e->batch) && k_sel[c].n == e->n,
              QT_EINVAL, "homogenize: k_sel must hold 1 or batch trains");
@@ -1276,7 +1289,7 @@ qt_status homogenize(qt_ctx ctx, const qt_operands* ops, const qt_tt* k_sel, qt_
   QT_CHECK(dd, QT_ENOMEM, "homogenize: workspace");
   std::vector<double> hd(2 * B);
   const double N3 = std::ldexp(1.0, 3 * ops->L);
-  for (int c = 0; c < 3; ++c) {
+  for (int c = 0; c < d; ++c) {
     ctx->ws_top = mark + 256 * ((sizeof(double) * 2 * B + 255) / 256);
     // dot workspace must fit in what setup reserved: environments are small
     qt_status s = dot_impl(ctx, &k_sel[c], e, dd, false);
@@ -1287,7 +1300,7 @@ qt_status homogenize(qt_ctx ctx, const qt_operands* ops, const qt_tt* k_sel, qt_
     QT_TRY(s);
     QT_HIP(hipMemcpyAsync(hd.data(), dd, sizeof(double) * 2 * B, hipMemcpyDeviceToHost, ctx->stream));
     QT_HIP(hipStreamSynchronize(ctx->stream));
-    for (int b = 0; b < B; ++b) A_eff[(int64_t)b * 3 + c] = hd[2 * b] / N3;
+    for (int b = 0; b < B; ++b) A_eff[(int64_t)b * d + c] = hd[2 * b] / N3;
   }
   QT_TRY(check_status(ctx));
   return all ? QT_OK : QT_NOT_CONVERGED;

@@ -147,11 +147,11 @@ def sfft_1d(L, eps=1e-13):
     return [c.reshape(c.shape[0], 2, 2, c.shape[2]) for c in train]
 
 
-def sfft_3d(L, eps=1e-13):
-    """Identity on the component core, Q_L on each axis group; and its adjoint."""
+def sfft_3d(L, eps=1e-13, d=3):
+    """Identity on the component core (mode d), Q_L on each axis group; and its adjoint."""
     one = sfft_1d(L, eps)
-    eye3 = np.eye(3, dtype=np.complex128).reshape(1, 3, 3, 1)
-    S = [eye3] + [c.copy() for _ in range(3) for c in one]
+    eye = np.eye(d, dtype=np.complex128).reshape(1, d, d, 1)
+    S = [eye] + [c.copy() for _ in range(3) for c in one]
     Sinv = [np.conj(np.transpose(c, (0, 2, 1, 3))) for c in S]
     return S, Sinv
 
@@ -272,6 +272,114 @@ def green_tt_expsum(L, k0, eps=1e-10, log=None):
     return [ctl.astype(np.complex128)] + [c.astype(np.complex128) for c in cores[1:]]
 
 
+# ------------------------------------------------------- linear elasticity
+
+# Voigt order of the strain / stress components: (11, 22, 33, 23, 13, 12)
+VOIGT_PAIRS = [(0, 0), (1, 1), (2, 2), (1, 2), (0, 2), (0, 1)]
+
+
+def voigt_green_momentum(L, lam0, mu0):
+    """Green-Eshelby operator of the isotropic reference medium (lam0, mu0) as a
+    6 x 6 Voigt matrix per frequency, G[a, b, x', y', z'] in the momentum order
+    of green_momentum_dense (position x' holds frequency rev(x')): strain a
+    (engineering shears) of a unit stress-like polarization b.  With
+    K^-1 = (I - c q q^T / |q|^2) / (mu0 |q|^2), c = (lam0 + mu0) / (lam0 + 2 mu0),
+    the strain is eps_ij = (q_i (K^-1 tau q)_j + q_j (K^-1 tau q)_i) / 2; zero at
+    q = 0 and on Nyquist frequencies."""
+    N = 2 ** L
+    f = signed_freq(N)[bit_reversal(L)]
+    q = [f[:, None, None], f[None, :, None], f[None, None, :]]
+    q2 = q[0] ** 2 + q[1] ** 2 + q[2] ** 2
+    bad = (q2 == 0) | (q[0] == -N // 2) | (q[1] == -N // 2) | (q[2] == -N // 2)
+    s2 = np.where(bad, 1.0, q2)
+    c = (lam0 + mu0) / (lam0 + 2.0 * mu0)
+
+    def kinv(m, k):
+        return (float(m == k) - c * q[m] * q[k] / s2) / (mu0 * s2)
+
+    G = np.zeros((6, 6, N, N, N))
+    for a, (i, j) in enumerate(VOIGT_PAIRS):
+        scale = 1.0 if i == j else 2.0
+        for b, (k, l) in enumerate(VOIGT_PAIRS):
+            pairs = [(k, l)] if k == l else [(k, l), (l, k)]
+            acc = 0.0
+            for kk, ll in pairs:
+                acc = acc + 0.5 * (q[i] * kinv(j, kk) + q[j] * kinv(i, kk)) * q[ll]
+            G[a, b] = np.where(bad, 0.0, scale * acc)
+    return G
+
+
+def green_tt_elastic(L, lam0, mu0, eps=1e-12):
+    """Green operator (component core (1, 6, 6, r), diagonal spatial cores) and
+    G2 = G^T G per frequency (the exact ||G t||^2 = <t, G2 t>), dense builds."""
+    G = voigt_green_momentum(L, lam0, mu0)
+    G2 = np.einsum("ca...,cb...->ab...", G, G)
+    out = []
+    for A in (G, G2):
+        cores = ttsvd(A.reshape(-1), [36] + [2] * (3 * L), eps)
+        ctrl = cores[0].reshape(1, 6, 6, cores[0].shape[2])
+        out.append([ctrl.astype(np.complex128)] + [c.astype(np.complex128) for c in cores[1:]])
+    return out[0], out[1]
+
+
+def _voigt_blocks():
+    A = np.zeros((6, 6))
+    A[:3, :3] = 1.0                            # lam: trace coupling
+    B = np.diag([2.0, 2.0, 2.0, 1.0, 1.0, 1.0])  # mu: 2 mu eps (engineering shears)
+    return A, B
+
+
+def _field_operator(fields, mats, eps):
+    """Operator cores of sum_t mats[t] (x) fields[t](x): component core
+    (1, 6, 6, r) and diagonal spatial cores, from one TT-SVD of the stacked fields."""
+    F = np.stack([np.asarray(f, dtype=np.float64) for f in fields])
+    L = int(round(math.log2(F.shape[1])))
+    cores = ttsvd(F.reshape(-1), [len(fields)] + [2] * (3 * L), eps)
+    first = cores[0][0]                         # (t, r1)
+    ctrl = np.einsum("tab,tr->abr", np.stack(mats), first)[None]
+    return [ctrl.astype(np.complex128)] + [c.astype(np.complex128) for c in cores[1:]]
+
+
+def _field_rows(fields, rows, eps):
+    """Trains of sum_t rows[t] (x) fields[t](x) with a component core (1, 6, r)."""
+    F = np.stack([np.asarray(f, dtype=np.float64) for f in fields])
+    L = int(round(math.log2(F.shape[1])))
+    cores = ttsvd(F.reshape(-1), [len(fields)] + [2] * (3 * L), eps)
+    first = cores[0][0]
+    ctrl = np.einsum("ta,tr->ar", np.stack(rows), first)[None]
+    return [ctrl.astype(np.complex128)] + [c.astype(np.complex128) for c in cores[1:]]
+
+
+def build_problem_elastic(lam, mu, lam0=None, mu0=None, op_eps=1e-10, sfft_eps=1e-13,
+                          green_eps=1e-12, log=None):
+    """Host trains of one linear-elasticity cell problem (Sec. 3.1, App. A) on an
+    N^3 grid of isotropic voxels (Lame parameters lam, mu): the field is the
+    Voigt strain (component core of mode 6), the material acts through the
+    Voigt operator C - C0 = (lam - lam0) A + (mu - mu0) B (A the trace
+    coupling, B = diag(2, 2, 2, 1, 1, 1)), the reference medium defaults to the
+    midpoints of the phase ranges.  k_sel[c] holds row c of C, so that
+    Re <k_sel[c], eps> / N^3 is the mean stress component c."""
+    say = log or (lambda msg: None)
+    lam = np.asarray(lam, dtype=np.float64)
+    mu = np.asarray(mu, dtype=np.float64)
+    lam0 = 0.5 * (lam.min() + lam.max()) if lam0 is None else float(lam0)
+    mu0 = 0.5 * (mu.min() + mu.max()) if mu0 is None else float(mu0)
+    L = int(round(math.log2(lam.shape[0])))
+    A, B = _voigt_blocks()
+    dl, dm = lam - lam0, mu - mu0
+    Kp = _field_operator([dl, dm], [A, B], op_eps)
+    # (C - C0)^T (C - C0) = dl^2 A^2 + dl dm (A B + B A) + dm^2 B^2
+    K2 = _field_operator([dl * dl, dl * dm, dm * dm], [A @ A, A @ B + B @ A, B @ B],
+                         op_eps * 1e-2)
+    ksel = [_field_rows([lam, mu], [A[c], B[c]], op_eps) for c in range(6)]
+    say(f"elastic material operators, C - C0 rank {max(c.shape[0] for c in Kp)}")
+    S, Sinv = sfft_3d(L, sfft_eps, d=6)
+    G, G2 = green_tt_elastic(L, lam0, mu0, green_eps)
+    say(f"Green-Eshelby operator, rank {max(c.shape[0] for c in G)}")
+    return {"kind": "elastic", "L": L, "k0": 1.0, "lam0": lam0, "mu0": mu0, "Kp_op": Kp,
+            "K2_op": K2, "k_sel": ksel, "S": S, "Sinv": Sinv, "G": G, "G2": G2}
+
+
 # ------------------------------------------------------- material, loads
 
 def material_tt(kvox, shift=0.0, eps=1e-10):
@@ -306,9 +414,9 @@ def material_tt_periodic(cell, L, shift=0.0, eps=1e-10):
 
 
 def with_component_core(spatial, control):
-    """Prepend a (1, 3, 1) component core to a spatial train (complex cores)."""
-    return [np.asarray(control, dtype=np.complex128).reshape(1, 3, 1)] + \
-        [c.astype(np.complex128) for c in spatial]
+    """Prepend a (1, d, 1) component core (d = len(control)) to a spatial train."""
+    ctl = np.asarray(control, dtype=np.complex128)
+    return [ctl.reshape(1, ctl.size, 1)] + [c.astype(np.complex128) for c in spatial]
 
 
 def apply_mpo(op, x):
@@ -383,10 +491,18 @@ def upload(prob, loads, max_rank, device=0):
     from . import qtt
     L = prob["L"]
     B = len(loads)
-    kp = qtt.DeviceTT.from_cores(prob["kp"], device=device)
     n = 3 * L + 1
-    Kp = qtt.DeviceMPO.from_cores(prob["kp"], [1] * n, device=device)
-    K2 = qtt.DeviceMPO.from_cores(prob["k2"], [1] * n, device=device)
+    G2 = None
+    if prob.get("kind") == "elastic":
+        # Voigt operators with full 6 x 6 component cores; no scalar material train
+        kp = None
+        Kp = qtt.DeviceMPO.from_cores(prob["Kp_op"], [0] + [1] * (n - 1), device=device)
+        K2 = qtt.DeviceMPO.from_cores(prob["K2_op"], [0] + [1] * (n - 1), device=device)
+        G2 = qtt.DeviceMPO.from_cores(prob["G2"], [0] + [1] * (n - 1), device=device)
+    else:
+        kp = qtt.DeviceTT.from_cores(prob["kp"], device=device)
+        Kp = qtt.DeviceMPO.from_cores(prob["kp"], [1] * n, device=device)
+        K2 = qtt.DeviceMPO.from_cores(prob["k2"], [1] * n, device=device)
     S = qtt.DeviceMPO.from_cores(prob["S"], device=device)
     Sinv = qtt.DeviceMPO.from_cores(prob["Sinv"], device=device)
     G = qtt.DeviceMPO.from_cores(prob["G"], [0] + [1] * (n - 1), device=device)
@@ -398,8 +514,8 @@ def upload(prob, loads, max_rank, device=0):
     SE = qtt.DeviceTT.from_cores(
         [compress(apply_mpo(prob["S"], mean_field(np.asarray(Ej, dtype=float), L)), 1e-14)
          for Ej in loads], device=device)
-    ops = qtt.DeviceOperands(L, kp, Kp, K2, prob["k0"], S, Sinv, G, E, E_norm, ksel, SE)
-    modes, cap = qtt.field_capacity(L, max_rank)
+    ops = qtt.DeviceOperands(L, kp, Kp, K2, prob["k0"], S, Sinv, G, E, E_norm, ksel, SE, G2)
+    modes, cap = qtt.field_capacity(L, max_rank, len(loads[0]))
     e = qtt.DeviceTT.empty(modes, cap, B, device)
     return ops, e
 

@@ -59,7 +59,8 @@ class RoundOpts(C.Structure):
 class Operands(C.Structure):
     _fields_ = [("L", C.c_int32), ("kp", TTDesc), ("Kp", MPODesc), ("K2", MPODesc),
                 ("k0", C.c_double), ("S", MPODesc), ("Sinv", MPODesc), ("G", MPODesc),
-                ("E", TTDesc), ("E_norm", C.POINTER(C.c_double)), ("SE", TTDesc)]
+                ("E", TTDesc), ("E_norm", C.POINTER(C.c_double)), ("SE", TTDesc),
+                ("G2", MPODesc)]
 
 
 class SolveOpts(C.Structure):
@@ -434,7 +435,7 @@ def ls_workspace_query(ops: "DeviceOperands", e: DeviceTT, opts: "SolveOpts",
     """Workspace bytes of ls_iterate (or homogenize) on this batch (host only)."""
     b = C.c_size_t()
     st = ops.struct()
-    ksel = (TTDesc * 3)(*[t.desc() for t in ops.k_sel]) if homogenize else None
+    ksel = (TTDesc * len(ops.k_sel))(*[t.desc() for t in ops.k_sel]) if homogenize else None
     _check(load_library().qt_ls_workspace_query(C.byref(st), ksel, C.byref(e.desc()),
                                                 C.byref(opts), C.byref(b)))
     return b.value
@@ -495,18 +496,21 @@ class DeviceOperands:
     E_norm: np.ndarray
     k_sel: list
     SE: DeviceTT
+    G2: DeviceMPO = None          # G^H G (elasticity); None: conductivity identity
     _struct: Operands = field(default=None, repr=False)
 
     def struct(self) -> Operands:
-        s = Operands(self.L, self.kp.desc(), self.Kp.desc(), self.K2.desc(), self.k0,
+        kp = self.kp.desc() if self.kp is not None else TTDesc()
+        g2 = self.G2.desc() if self.G2 is not None else MPODesc()
+        s = Operands(self.L, kp, self.Kp.desc(), self.K2.desc(), self.k0,
                      self.S.desc(), self.Sinv.desc(), self.G.desc(), self.E.desc(),
-                     self.E_norm.ctypes.data_as(C.POINTER(C.c_double)), self.SE.desc())
+                     self.E_norm.ctypes.data_as(C.POINTER(C.c_double)), self.SE.desc(), g2)
         self._struct = s
         return s
 
 
-def field_capacity(L: int, max_rank: int):
-    modes = [3] + [2] * (3 * L)
+def field_capacity(L: int, max_rank: int, d: int = 3):
+    modes = [d] + [2] * (3 * L)
     nat = natural_caps(modes)
     return modes, [min(r, max_rank) if max_rank > 0 else r for r in nat]
 
@@ -525,12 +529,14 @@ def ls_iterate(ctx: Context, ops: DeviceOperands, e: DeviceTT, opts: SolveOpts, 
 
 
 def homogenize(ctx: Context, ops: DeviceOperands, e: DeviceTT, opts: SolveOpts):
-    """Returns (A_eff columns [batch, 3], iterations [batch], residuals [max_iter, batch], status)."""
+    """Returns (A_eff [batch, d] (mean flux or stress per field), iterations [batch],
+    residuals [max_iter, batch], status); d = the field's component mode."""
     B = e.batch
-    A = np.zeros((B, 3))
+    d = int(e.modes[0])
+    A = np.zeros((B, d))
     its = np.zeros(B, dtype=np.int32)
     res = np.full((opts.max_iter, B), np.nan)
-    ksel = (TTDesc * 3)(*[t.desc() for t in ops.k_sel])
+    ksel = (TTDesc * d)(*[t.desc() for t in ops.k_sel])
     st = ops.struct()
     s = _check(ctx.lib.homogenize(ctx.h, C.byref(st), ksel, C.byref(e.desc()), C.byref(opts),
                                   A.ctypes.data_as(C.POINTER(C.c_double)),
