@@ -49,6 +49,13 @@ CONFIGS = {
     # 1024^2 section, and the Green operator by its exponential-sum form
     "cyl1024": dict(L=10, geom="cylinders", seed=4, k0=25.5, eps=1e-6, rmax=128,
                     loads=[[1.0, 0.0, 0.0]]),
+    # linear elasticity (Voigt strain, 6 components): a plane-strain cell of
+    # 4-12 periodic rectangles (the 2D box/multibox workload repeated along z),
+    # rectangles E = 10, nu = 0.25 (lam = mu = 4) in E = 1, nu = 0.3
+    # (lam = 0.577, mu = 0.385), reference medium at the midpoints, load e_11
+    "elastic128": dict(L=7, geom="elastic_boxes", seed=21, eps=1e-6, rmax=64,
+                       phases=((0.5769230769230769, 0.38461538461538464), (4.0, 4.0)),
+                       loads=[[1.0, 0.0, 0.0, 0.0, 0.0, 0.0]]),
 }
 
 
@@ -63,6 +70,8 @@ SPLIT_ITERS = 4
 
 
 def voxels(cfg, inst=0):
+    import numpy as np
+
     from paper_2512_07811_amd import inputs as I
     if cfg["geom"] == "boxes":
         return I.random_boxes(cfg["L"], cfg["seed0"] + inst)
@@ -72,6 +81,12 @@ def voxels(cfg, inst=0):
         return I.laminate(cfg["L"])
     if cfg["geom"] == "cylinders":      # the (N, N) section of a z-invariant cell
         return I.cylinders_section(cfg["L"], cfg["seed"])
+    if cfg["geom"] == "elastic_boxes":  # Lame fields (lam, mu) of the plane-strain cell
+        ph = I.boxes_section(cfg["L"], cfg["seed"])
+        N = ph.shape[0]
+        (l0, m0), (l1, m1) = cfg["phases"]
+        ph3 = np.broadcast_to(ph[:, :, None], (N, N, N))
+        return np.where(ph3 > 0, l1, l0), np.where(ph3 > 0, m1, m0)
     raise ValueError(cfg["geom"])
 
 
@@ -98,6 +113,20 @@ def _oracle_rate(args):
     import numpy as np
 
     from oracle import ms
+    if cfg["geom"] == "elastic_boxes":
+        from oracle import ms_elastic as ME
+        lam, mu = voxels(cfg)
+        lam0, mu0 = 0.5 * (lam.min() + lam.max()), 0.5 * (mu.min() + mu.max())
+        E = cfg["loads"][0]
+        ev = np.zeros((6,) + lam.shape) + np.asarray(E, dtype=float).reshape(6, 1, 1, 1)
+        t0 = time.perf_counter()
+        its = 0
+        while True:
+            ev = ME.ms_step(ev, lam, mu, lam0, mu0, E)
+            its += 1
+            if time.perf_counter() - t0 > budget_s or its >= 200:
+                break
+        return its, time.perf_counter() - t0
     kvox = voxels(cfg)
     d = kvox.ndim          # a z-invariant cell is timed on its exact 2D reduction
     E = cfg["loads"][0][:d]
@@ -121,6 +150,8 @@ def cpu_baseline(cfg, budget_s=20.0):
     Forked before the GPU is touched."""
     import multiprocessing as mp
     kvox = voxels(cfg)
+    if isinstance(kvox, tuple):         # elasticity: (lam, mu), a 6-component field
+        kvox = kvox[0]
     workers = min(16, os.cpu_count() or 1)
     if kvox.ndim == 3 and kvox.shape[0] >= 256:
         workers = min(workers, 8)
@@ -282,6 +313,11 @@ def iteration_model(ops, field_cap, rmax, oversample):
     return tot_qr, tot_svd
 
 
+def mat_rank(prob):
+    """Largest bond of the material train (or operator, for elasticity)."""
+    return max(c.shape[0] for c in (prob["Kp_op"] if prob.get("kind") == "elastic" else prob["kp"]))
+
+
 def under_profiler() -> bool:
     """rocprofv3 preloads its library, which initialises the GPU before this
     program starts: no worker processes may be forked then."""
@@ -293,7 +329,8 @@ def a_eff(q, ctx, ops, e, L):
     """A_eff[:, j] = Re <k_sel[c], e> / N^3 per field (Appendix A)."""
     import numpy as np
     N3 = 2.0 ** (3 * L)
-    cols = [q.tt_dot(ctx, ops.k_sel[c], e).cpu().numpy().real / N3 for c in range(3)]
+    cols = [q.tt_dot(ctx, ops.k_sel[c], e).cpu().numpy().real / N3
+            for c in range(len(ops.k_sel))]
     return np.stack(cols, axis=1)
 
 
@@ -391,13 +428,18 @@ def main():
         prob = P.build_problem(section=voxels(cfg), k0=cfg["k0"], log=say)
         probs = [prob]
         fields = list(cfg["loads"])
+    elif cfg["geom"] == "elastic_boxes":
+        lam, mu = voxels(cfg)
+        prob = P.build_problem_elastic(lam, mu, log=say)
+        probs = [prob]
+        fields = list(cfg["loads"])
     else:
         prob = P.build_problem(kvox=voxels(cfg), k0=cfg["k0"], log=say)
         probs = [prob]
         fields = list(cfg["loads"])
     t_setup = time.perf_counter() - t0
-    say(f"setup {t_setup:.1f}s  instances {len(probs)}  fields {len(fields)}  k' max rank "
-        f"{max(max(c.shape[0] for c in p['kp']) for p in probs)}  "
+    say(f"setup {t_setup:.1f}s  instances {len(probs)}  fields {len(fields)}  material max rank "
+        f"{max(mat_rank(p) for p in probs)}  "
         f"G max rank {max(c.shape[0] for c in prob['G'])}")
     if args.calibrate_copy:
         # a plain copy of known size: 512 MiB read, 512 MiB written
@@ -505,7 +547,7 @@ def main():
             "plain_fp64": "the FP64 SVD-truncated product-aware rounding stands in for the "
                           "plain (materializing) FP64 path, which cannot run here: the first "
                           "product k' e has rank "
-                          f"{max(c.shape[0] for c in prob['kp'])} x {cfg['rmax']} per bond",
+                          f"{mat_rank(prob)} x {cfg['rmax']} per bond",
         }
         accuracy = {
             "A_eff_column_learned": A_main[0].tolist(), "A_eff_column_svd_truncated": A_sk[0].tolist(),
@@ -546,6 +588,9 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c128",
         "data": "synthetic",
         "config": {"workload": args.config, "L": cfg["L"], "grid": f"{2 ** cfg['L']}^3",
+                   "physics": ("linear elasticity (Voigt strain, 6 components)"
+                               if cfg["geom"] == "elastic_boxes"
+                               else "scalar conductivity (3 gradient components)"),
                    "instances": len(probs),
                    "rounding": args.mode, "eps": cfg["eps"], "max_rank": cfg["rmax"],
                    "oversample": args.oversample,

@@ -60,6 +60,23 @@ def random_boxes(L: int, seed: int, n_min: int = 1, n_max: int = 8,
     return k
 
 
+def boxes_section(L: int, seed: int, n_min: int = 4, n_max: int = 12, edge_min: int = 8,
+                  edge_max: int = 40) -> np.ndarray:
+    """(N, N) phase indicator of periodic axis-aligned rectangles (1 inside,
+    0 outside), half-open [p, p+l) mod N: the 2D box/multibox cells of the
+    elasticity workload, repeated along z for a plane-strain cell."""
+    N = 2 ** L
+    g = rng(seed)
+    nb = int(g.integers(n_min, n_max + 1))
+    ph = np.zeros((N, N), dtype=np.float64)
+    for _ in range(nb):
+        edges = g.integers(edge_min, edge_max + 1, size=2)
+        corner = g.integers(0, N, size=2)
+        ix = [(corner[a] + np.arange(edges[a])) % N for a in range(2)]
+        ph[np.ix_(ix[0], ix[1])] = 1.0
+    return ph
+
+
 def cylinders_section(L: int, seed: int, count: int = 16, r_min: float = 20.0,
                       r_max: float = 40.0, k_in: float = 50.0, k_out: float = 1.0,
                       max_tries: int = 100000) -> np.ndarray:
