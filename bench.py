@@ -318,6 +318,12 @@ def mat_rank(prob):
     return max(c.shape[0] for c in (prob["Kp_op"] if prob.get("kind") == "elastic" else prob["kp"]))
 
 
+def max_op_rank(prob) -> int:
+    """Largest bond over the operators an iteration multiplies the field by."""
+    names = ("Kp_op", "S", "G", "Sinv") if prob.get("kind") == "elastic" else ("kp", "S", "G", "Sinv")
+    return max(c.shape[0] for n in names for c in prob[n])
+
+
 def under_profiler() -> bool:
     """rocprofv3 preloads its library, which initialises the GPU before this
     program starts: no worker processes may be forked then."""
@@ -545,9 +551,10 @@ def main():
             "svd_calls_learned": cnt["svd_calls"], "svd_calls_svd_truncated": cnt_sk["svd_calls"],
             "gemm_flops_ratio": cnt["gemm_flops"] / max(cnt_sk["gemm_flops"], 1),
             "plain_fp64": "the FP64 SVD-truncated product-aware rounding stands in for the "
-                          "plain (materializing) FP64 path, which cannot run here: the first "
-                          "product k' e has rank "
-                          f"{mat_rank(prob)} x {cfg['rmax']} per bond",
+                          "plain (materializing) FP64 path, which cannot run here: its "
+                          "products have ranks up to the operator's times the field's, "
+                          f"{max_op_rank(prob)} x {cfg['rmax']} per bond (an SVD block holds "
+                          "at most 1024 columns)",
         }
         accuracy = {
             "A_eff_column_learned": A_main[0].tolist(), "A_eff_column_svd_truncated": A_sk[0].tolist(),
