@@ -504,7 +504,8 @@ def main():
         dt = time.perf_counter() - t1
         cnt = ctx.counters(reset=True)
         r = res.cpu().numpy()
-        say(f"{label}: {args.steps} steps in {dt:.3f}s; residuals {r[:, 0].tolist()}")
+        say(f"{label}: {args.steps} steps in {dt:.3f}s; fallbacks {cnt['learned_fallbacks']} of "
+            f"{cnt['learned_roundings']}; residuals {r[:, 0].tolist()}")
         return dt, r, cnt
 
     def class_split(o, restore, iters=SPLIT_ITERS):
@@ -527,7 +528,11 @@ def main():
         ctx.profile(0)
         return cls_ms
 
+    # GEMM tile-shape signatures timed so far (a first call of a signature
+    # inside the window is timed there: its four shapes run on the stream)
+    tuned0 = ctx.autotune(1)
     dt, res, cnt = window(opts, args.mode)
+    tuned1 = ctx.autotune(1)
     A_main = a_eff(qtt, ctx, ops, e, ops.L)
     # kernel classes of the main path: the iterations continue from the end of
     # the timed window (the rank predictor's features belong to that field)
@@ -657,7 +662,9 @@ def main():
                        "gemm_bytes_timed_window": cnt["gemm_bytes"],
                        "jacobi_sweeps_per_svd": (cnt["svd_sweeps"] / cnt["svd_calls"]
                                                  if cnt["svd_calls"] else None),
-                       "sketch_over_budget": cnt["sketch_over_budget"]}
+                       "sketch_over_budget": cnt["sketch_over_budget"],
+                       "gemm_signatures_tuned_before_window": tuned0,
+                       "gemm_signatures_tuned_in_window": tuned1 - tuned0}
     if train_info:
         out["predictor"] = train_info
     if args.round_ranks:

@@ -180,9 +180,10 @@ qt_status qt_ctx_profile_read(qt_ctx ctx, double* total_ms, int64_t* launches);
  * Each call has one of four output-tile shapes (64 or 32 rows by 64 or 32
  * columns); every shape sums each output element's terms in the same order,
  * so results are bitwise equal across shapes.  mode 0: always 64 x 64;
- * 1 (default): autotune - the first call of each signature (capacities in
- * steps of 16 rows / columns and 64 terms, item count to a power of two,
- * conjugations, stride pattern) that runs outside a graph capture and
+ * 1 (default): autotune - the first call of each signature (row and column
+ * capacities in 32-wide steps up to 64 and in half octaves above, the
+ * contraction length in octaves, item count to a power of two, conjugations,
+ * stride pattern) that runs outside a graph capture and
  * without split-K times every shape once on its first instance, writing to a
  * context-owned scratch (allocated on demand, at most 256 MiB), and later
  * calls of that signature use the fastest; 2..5: always shape mode - 2 (bit 0:

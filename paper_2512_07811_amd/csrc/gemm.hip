@@ -347,6 +347,22 @@ static int tune_shape(hipStream_t st, GemmTuner& T, bool cA, bool cB, GemmArgs a
   return bv;
 }
 
+// ceil(log2 x) for x >= 1
+static int64_t octave(int64_t x) {
+  int64_t o = 0;
+  while ((int64_t(1) << o) < x) ++o;
+  return o;
+}
+// 1 or 2 for up to 32 or 64 (one or two 32-wide tiles), then one bucket per
+// half octave: (64, 90], (90, 128], (128, 181], ...
+static int64_t size_bucket(int64_t x) {
+  if (x <= 64) return (x + 31) / 32;
+  int64_t h = 0;
+  // smallest h with x <= 64 * 2^(h / 2), compared exactly as x^2 <= 4096 * 2^h
+  while ((double)x * (double)x > 4096.0 * (double)(int64_t(1) << h)) ++h;
+  return 2 + h;
+}
+
 static bool stream_capturing(hipStream_t st) {
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(st, &cs) != hipSuccess) {
@@ -378,12 +394,14 @@ void gemm_ex(hipStream_t st, int batch, int nb1, int nb2, Dim M, Dim N, Dim K, i
   if (T && T->mode >= 2) {
     v = T->mode - 2;
   } else if (T && T->mode == 1 && splits == 1) {
-    // signature: capacities to 16 (M, N) and 64 (K), items to a power of
-    // two, conjugations and which operands are unit-stride along K / N
+    // signature: M and N capacities in tile steps up to 64 and in half
+    // octaves above, K in octaves, items to a power of two, conjugations and
+    // which operands are unit-stride along K / N (ranks that drift between
+    // iterations mostly stay inside one signature, so it is timed once)
     int64_t ib = 1;
     while (ib < items) ib <<= 1;
-    const std::array<int64_t, 10> key{conjA, conjB, (Mcap + 15) / 16, (Ncap + 15) / 16,
-                                       (Kcap + 63) / 64, ib, A.cs.p ? -1 : A.cs.cst,
+    const std::array<int64_t, 10> key{conjA, conjB, size_bucket(Mcap), size_bucket(Ncap),
+                                       octave(std::max<int64_t>(Kcap, 1)), ib, A.cs.p ? -1 : A.cs.cst,
                                        B.cs.p ? -1 : B.cs.cst, C.cs.p ? -1 : C.cs.cst,
                                        g_gemm_f32 ? 1 : 0};
     auto it = T->choice.find(key);
