@@ -271,7 +271,7 @@ struct GemmTuner {
   cplx* scratch = nullptr;      // output of the timing launches
   int64_t scratch_elems = 0;
   qt_ctx owner = nullptr;       // caller-memory contexts time into their free arena
-  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipEvent_t ev[8] = {};          // one pair per tile shape
 };
 extern thread_local GemmTuner* g_tuner;
 // Set while an allocation-free entry point runs: the GEMM launcher then never

@@ -36,9 +36,9 @@ __device__ inline int acc_row(int r, int lk) {
 // One TM x TN complex output tile (TM, TN in {32, 64}) per workgroup of 4
 // waves (2 x 2 waves of TM/2 x TN/2, each TM/32 x TN/32 MFMA tiles of 16 x 16).
 // Every output element sums its K terms in the same order whatever the tile
-// shape, so the shapes give bitwise equal results.  Complex products as four
-// real MFMAs into a real and an imaginary accumulator:
-//   Re += Ar Br + (-Ai) Bi,   Im += Ar Bi + Ai Br.
+// shape, so the shapes give bitwise equal results.  FP64 complex products as
+// three real MFMAs (below); FP32 ones as four, into a real and an imaginary
+// accumulator: Re += Ar Br + (-Ai) Bi, Im += Ar Bi + Ai Br.
 // The next K panel is fetched into registers while the current one is in use.
 // Split-K (gridDim.z = splits > 1): workgroup z takes K range
 // [z kper, (z + 1) kper) with kper a multiple of the panel depth and writes its
@@ -58,7 +58,7 @@ __device__ inline int64_t xcd_tile(int64_t w, int64_t total) {
 }
 
 template <bool CA, bool CB, int TM, int TN, bool F32>
-__global__ __launch_bounds__(256) void k_gemm_ex(int nb1, int nb2, int ntn, int mtn, int nfast,
+__global__ __launch_bounds__(256, 2) void k_gemm_ex(int nb1, int nb2, int ntn, int mtn, int nfast,
                                                  Dim Md, Dim Nd, Dim Kd, Mat A, Mat B, Mat C,
                                                  cplx alpha, int accumulate, Dim lim1,
                                                  unsigned long long* counters, cplx* part,
@@ -152,13 +152,18 @@ __global__ __launch_bounds__(256) void k_gemm_ex(int nb1, int nb2, int ntn, int 
       rb[e] = u;
     }
   };
-  acc4 cre[FM][FN], cim[FM][FN];
+  // FP64: three real products per complex product (Gauss), summed apart:
+  //   c1 = sum Ar Br, c2 = sum Ai Bi, c3 = sum (Ar + Ai)(Br + Bi);
+  //   Re = c1 - c2, Im = c3 - c1 - c2.
+  // FP32 keeps the four-product form: c1 = Re, c2 = Im.
+  acc4 c1[FM][FN], c2[FM][FN], c3[FM][FN];
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int j = 0; j < FN; ++j) {
-      cre[i][j] = acc4{0, 0, 0, 0};
-      cim[i][j] = acc4{0, 0, 0, 0};
+      c1[i][j] = acc4{0, 0, 0, 0};
+      c2[i][j] = acc4{0, 0, 0, 0};
+      c3[i][j] = acc4{0, 0, 0, 0};
     }
   fetch(kbeg);
   for (int k0 = kbeg; k0 < kend; k0 += XT_K) {
@@ -187,15 +192,31 @@ __global__ __launch_bounds__(256) void k_gemm_ex(int nb1, int nb2, int ntn, int 
         fbr[t] = Br[kc + lk][wn + 16 * t + li];
         fbi[t] = Bi[kc + lk][wn + 16 * t + li];
       }
+      if constexpr (F32) {
 #pragma unroll
-      for (int i = 0; i < FM; ++i)
+        for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < FN; ++j) {
-          cre[i][j] = mfma16(far[i], fbr[j], cre[i][j]);
-          cre[i][j] = mfma16(-fai[i], fbi[j], cre[i][j]);
-          cim[i][j] = mfma16(far[i], fbi[j], cim[i][j]);
-          cim[i][j] = mfma16(fai[i], fbr[j], cim[i][j]);
-        }
+          for (int j = 0; j < FN; ++j) {
+            c1[i][j] = mfma16(far[i], fbr[j], c1[i][j]);
+            c1[i][j] = mfma16(-fai[i], fbi[j], c1[i][j]);
+            c2[i][j] = mfma16(far[i], fbi[j], c2[i][j]);
+            c2[i][j] = mfma16(fai[i], fbr[j], c2[i][j]);
+          }
+      } else {
+        real fas[FM], fbs[FN];
+#pragma unroll
+        for (int t = 0; t < FM; ++t) fas[t] = far[t] + fai[t];
+#pragma unroll
+        for (int t = 0; t < FN; ++t) fbs[t] = fbr[t] + fbi[t];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) {
+            c1[i][j] = mfma16(far[i], fbr[j], c1[i][j]);
+            c2[i][j] = mfma16(fai[i], fbi[j], c2[i][j]);
+            c3[i][j] = mfma16(fas[i], fbs[j], c3[i][j]);
+          }
+      }
     }
     __syncthreads();
   }
@@ -208,13 +229,21 @@ __global__ __launch_bounds__(256) void k_gemm_ex(int nb1, int nb2, int ntn, int 
         const int gm = m0 + wm + 16 * i + acc_row<F32>(r, lk);
         const int gn = n0 + wn + 16 * j + li;
         if (gm >= M || gn >= N) continue;
+        double vre, vim;
+        if constexpr (F32) {
+          vre = (double)c1[i][j][r];
+          vim = (double)c2[i][j][r];
+        } else {
+          vre = c1[i][j][r] - c2[i][j][r];
+          vim = c3[i][j][r] - c1[i][j][r] - c2[i][j][r];
+        }
         if (splits > 1) {
           if (gm >= Mcap || gn >= Ncap) continue;
           part[((int64_t)sk * items + z) * Mcap * Ncap + (int64_t)gm * Ncap + gn] =
-              make_double2((double)cre[i][j][r], (double)cim[i][j][r]);
+              make_double2(vre, vim);
           continue;
         }
-        cplx v = cmul(alpha, make_double2((double)cre[i][j][r], (double)cim[i][j][r]));
+        cplx v = cmul(alpha, make_double2(vre, vim));
         cplx* o = Cb + gm * crs + gn * ccs;
         if (accumulate) v = cadd(v, *o);
         *o = v;
@@ -292,9 +321,9 @@ static void launch_shape(int v, hipStream_t st, int splits, bool cA, bool cB, co
 // Largest timing output of the tuner (complex elements, 256 MiB).
 constexpr int64_t QT_TUNE_MAX_ELEMS = int64_t(1) << 24;
 
-// Times every tile shape on instance 0 of the call (output to the tuner's
-// scratch, no accumulation, no split-K, no counters) and returns the fastest;
-// 64 x 64 unless another shape is at least 3 % faster.
+// Times every tile shape once on instance 0 of the call (output to the
+// tuner's scratch, no accumulation, no split-K, no counters) and returns the
+// fastest; 64 x 64 unless another shape is at least 3 % faster.
 static int tune_shape(hipStream_t st, GemmTuner& T, bool cA, bool cB, GemmArgs a) {
   const int64_t items1 = (int64_t)a.nb1 * a.nb2;
   const int64_t need = items1 * a.Mcap * a.Ncap;
@@ -319,8 +348,13 @@ static int tune_shape(hipStream_t st, GemmTuner& T, bool cA, bool cB, GemmArgs a
     T.scratch_elems = need;
   }
   if (!out) out = T.scratch;
-  if (!T.ev[0] && (hipEventCreate(&T.ev[0]) != hipSuccess || hipEventCreate(&T.ev[1]) != hipSuccess))
-    return 0;
+  for (hipEvent_t& e : T.ev) {
+    if (!e && hipEventCreate(&e) != hipSuccess) {
+      (void)hipGetLastError();
+      e = nullptr;
+      return 0;
+    }
+  }
   const Str one{nullptr, 0, 0, 1}, zero{nullptr, 0, 0, 0};
   a.C = mat(out, 0, Str{nullptr, 0, 0, a.Ncap}, one,
             Str{nullptr, 0, 0, (int64_t)a.nb2 * a.Mcap * a.Ncap},
@@ -328,20 +362,20 @@ static int tune_shape(hipStream_t st, GemmTuner& T, bool cA, bool cB, GemmArgs a
   a.acc = 0;
   a.cnt = nullptr;
   a.items = items1;
+  // one warm-up launch (operands into L2), then each shape once between its
+  // own event pair, and a single wait at the end
+  launch_shape(0, st, 1, cA, cB, a);
+  for (int v = 0; v < 4; ++v) {
+    (void)hipEventRecord(T.ev[2 * v], st);
+    launch_shape(v, st, 1, cA, cB, a);
+    (void)hipEventRecord(T.ev[2 * v + 1], st);
+  }
+  if (hipEventSynchronize(T.ev[7]) != hipSuccess) return 0;
   float best = 0.f;
   int bv = 0;
   for (int v = 0; v < 4; ++v) {
-    launch_shape(v, st, 1, cA, cB, a);   // warm-up
-    float tv = 1e30f;
-    for (int rep = 0; rep < 2; ++rep) {
-      (void)hipEventRecord(T.ev[0], st);
-      launch_shape(v, st, 1, cA, cB, a);
-      (void)hipEventRecord(T.ev[1], st);
-      if (hipEventSynchronize(T.ev[1]) != hipSuccess) return 0;
-      float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, T.ev[0], T.ev[1]);
-      tv = std::min(tv, ms);
-    }
+    float tv = 0.f;
+    (void)hipEventElapsedTime(&tv, T.ev[2 * v], T.ev[2 * v + 1]);
     if (v == 0 || tv < 0.97f * best) { best = tv; bv = v; }
   }
   return bv;
@@ -380,10 +414,16 @@ void gemm_ex(hipStream_t st, int batch, int nb1, int nb2, Dim M, Dim N, Dim K, i
   // split K when the output has too few tiles to fill the chip and K is long
   // (decided on 64 x 64 tiles whatever the shape, so that every shape sums
   // each element in the same order)
+  // and, for a handful of tiles, when K is at least 8 panels: each workgroup
+  // of such a product waits on one global load per panel, so its time is the
+  // panel count times the load latency; four-panel splits cut that
   int splits = 1;
   const int64_t tiles = (int64_t)((Ncap + 63) / 64) * items * ((Mcap + 63) / 64);
-  if (Kcap >= 1024 && tiles < 256 && g_splitk.p) {
-    splits = (int)std::min<int64_t>({(Kcap + 255) / 256, (512 + tiles - 1) / tiles, 64});
+  if (g_splitk.p && tiles < 256) {
+    if (Kcap >= 1024)
+      splits = (int)std::min<int64_t>({(Kcap + 255) / 256, (512 + tiles - 1) / tiles, 64});
+    else if (Kcap >= 8 * XT_K && tiles <= 16)
+      splits = (int)std::min<int64_t>({Kcap / (4 * XT_K), (256 + tiles - 1) / tiles, 64});
     const int64_t per = items * Mcap * Ncap;
     while (splits > 1 && splits * per > g_splitk.elems) --splits;
   }
