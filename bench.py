@@ -49,6 +49,11 @@ CONFIGS = {
     # 1024^2 section, and the Green operator by its exponential-sum form
     "cyl1024": dict(L=10, geom="cylinders", seed=4, k0=25.5, eps=1e-6, rmax=128,
                     loads=[[1.0, 0.0, 0.0]]),
+    # 4096^3 simple-cubic lattice of 8^3 spheres (period 512, radius 0.3 of the
+    # period = 153.6 voxels), k = 20 in k = 1, load e_x: k' from the 512^3 period
+    # cell, the Green operator by cross interpolation of its entry formula
+    "lattice4096": dict(L=12, geom="lattice", period_L=9, rel_radius=0.3, k_in=20.0, k_out=1.0,
+                        k0=10.5, eps=1e-5, rmax=256, loads=[[1.0, 0.0, 0.0]]),
     # linear elasticity (Voigt strain, 6 components): a plane-strain cell of
     # 4-12 periodic rectangles (the 2D box/multibox workload repeated along z),
     # rectangles E = 10, nu = 0.25 (lam = mu = 4) in E = 1, nu = 0.3
@@ -79,6 +84,8 @@ def voxels(cfg, inst=0):
         return I.sphere(cfg["L"], cfg["frac"], cfg["k_in"], cfg["k_out"])
     if cfg["geom"] == "laminate":
         return I.laminate(cfg["L"])
+    if cfg["geom"] == "lattice":        # one period cell (the exact reduction)
+        return I.sphere_lattice_cell(cfg["period_L"], cfg["rel_radius"], cfg["k_in"], cfg["k_out"])
     if cfg["geom"] == "cylinders":      # the (N, N) section of a z-invariant cell
         return I.cylinders_section(cfg["L"], cfg["seed"])
     if cfg["geom"] == "elastic_boxes":  # Lame fields (lam, mu) of the plane-strain cell
@@ -155,6 +162,8 @@ def cpu_baseline(cfg, budget_s=20.0):
     workers = min(16, os.cpu_count() or 1)
     if kvox.ndim == 3 and kvox.shape[0] >= 256:
         workers = min(workers, 8)
+    if kvox.ndim == 3 and kvox.shape[0] >= 512:
+        workers = 1                     # one 512^3 step holds about 36 GB
     with mp.get_context("fork").Pool(workers) as pool:
         res = pool.map(_oracle_rate, [(cfg, budget_s)] * workers)
     its = sum(r[0] for r in res)
@@ -165,6 +174,8 @@ def cpu_baseline(cfg, budget_s=20.0):
                       f"one thread per process) in {workers} processes of about {budget_s:.0f} s "
                       f"each, on the same {kvox.shape[0]}^{d} microstructure and load"
                       + (" (the exact 2D reduction of the z-invariant cell)" if d == 2 else "")
+                      + (f" (the {kvox.shape[0]}^3 period cell: the exact reduction of the "
+                         f"{2 ** cfg['L']}^3 lattice)" if cfg["geom"] == "lattice" else "")
                       + "; the naive TT oracle cannot form this workload's product ranks"}
 
 
@@ -430,6 +441,10 @@ def main():
                 probs = [first] + pool.map(_instance_problem, range(1, cfg["instances"]))
         prob = first
         fields = [E for _ in probs for E in cfg["loads"]]
+    elif cfg["geom"] == "lattice":
+        prob = P.build_problem(cell=voxels(cfg), L=cfg["L"], k0=cfg["k0"], log=say)
+        probs = [prob]
+        fields = list(cfg["loads"])
     elif cfg["geom"] == "cylinders":
         prob = P.build_problem(section=voxels(cfg), k0=cfg["k0"], log=say)
         probs = [prob]

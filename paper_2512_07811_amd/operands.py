@@ -433,7 +433,7 @@ def mean_field(E, L):
 
 
 def build_problem(kvox=None, k0=None, L=None, section=None, op_eps=1e-10, sfft_eps=1e-13,
-                  shared=None, cell=None, log=None, green_eps=None):
+                  shared=None, cell=None, log=None, green_eps=None, green=None):
     """All host trains of one cell problem (k given as N^3 voxels, a z-invariant
     section, or a periodic cell tiling a 2^L grid).
 
@@ -448,6 +448,10 @@ def build_problem(kvox=None, k0=None, L=None, section=None, op_eps=1e-10, sfft_e
     for the exponential-sum build (L > 8), whose set-up time triples at 1e-12
     (the floor, ~1e-13 of ||G t||^2, is then below the rank-capped errors of
     those workloads by ten orders of magnitude).
+    green: how the Green operator is built: "dense" (TT-SVD of its 9 N^3 array),
+    "expsum" (exponential sums per axis, then split into bits) or "cross"
+    (cross interpolation of its entry formula); default dense up to 256^3,
+    expsum up to 1024^3, cross beyond.
     log: optional callable taking a progress message."""
     say = log or (lambda msg: None)
     if kvox is not None:
@@ -479,8 +483,18 @@ def build_problem(kvox=None, k0=None, L=None, section=None, op_eps=1e-10, sfft_e
         say("SFFT operator")
         # the dense Green array has 9 N^3 entries: beyond 256^3 the
         # exponential-sum build (same operator, same ranks)
-        geps = green_eps if green_eps is not None else (min(op_eps, 1e-12) if L <= 8 else op_eps)
-        G = green_tt(L, k0, geps) if L <= 8 else green_tt_expsum(L, k0, geps, log=say)
+        how = green or ("dense" if L <= 8 else "expsum" if L <= 10 else "cross")
+        geps = green_eps if green_eps is not None else (min(op_eps, 1e-12) if how == "dense"
+                                                        else op_eps)
+        if how == "dense":
+            G = green_tt(L, k0, geps)
+        elif how == "expsum":
+            G = green_tt_expsum(L, k0, geps, log=say)
+        else:
+            from .cross import green_tt_cross
+            G, cinfo = green_tt_cross(L, k0, geps, log=say)
+            say(f"Green operator by cross: {cinfo['sweeps']} sweeps, {cinfo['evaluations']} "
+                f"entries, sampled max error {cinfo['sampled_max_error']:.1e}")
         say(f"Green operator, rank {max(c.shape[0] for c in G)}")
     return {"L": L, "k0": float(k0), "kp": kp, "k2": k2, "k_sel": ksel, "S": S, "Sinv": Sinv,
             "G": G}
