@@ -259,8 +259,9 @@ extern "C" qt_status tt_add(qt_ctx ctx, double are, double aim, const qt_tt* x, 
   return qt::add_impl(ctx, are, aim, x, bre, bim, y, out);
 }
 
-// Environment sweep: E_{k+1} = sum_i A_k(i)^H E_k B_k(i), done as two GEMMs
-// per core: T = E * B_k (right unfolding), E' = A_k(left unfolding)^H * T.
+// Environment sweep: E_{k+1} = sum_i A_k(i)^H E_k B_k(i), done as two
+// structured MFMA GEMMs per core: T = E * B_k (right unfolding),
+// E' = A_k(left unfolding)^H * T.
 namespace qt {
 qt_status dot_impl(qt_ctx ctx, const qt_tt* a, const qt_tt* b, double* out, bool reserve) {
   const int n = a->n, B = b->batch;
@@ -284,13 +285,19 @@ qt_status dot_impl(qt_ctx ctx, const qt_tt* a, const qt_tt* b, double* out, bool
   for (int k = 0; k < n; ++k) {
     const int p = b->modes[k];
     // T (ra_k x p rb_{k+1}) = E (ra_k x rb_k) * Bk (rb_k x p rb_{k+1})
-    gemm(st, B, dref(a->ranks + k, sra), dref(b->ranks + k + 1, n + 1, p), dref(b->ranks + k, n + 1),
-         a->cap[k], p * b->cap[k + 1], false, E0, env, false, Bd + b->offsets[k], b->inst_stride,
-         Tb, tcap, one, false);
+    gemm_ex(st, B, 1, 1, dref(a->ranks + k, sra), dref(b->ranks + k + 1, n + 1, p),
+            dref(b->ranks + k, n + 1), a->cap[k], p * b->cap[k + 1],
+            mat(E0, env, sref(b->ranks + k, n + 1), sconst(1)), false,
+            mat(Bd + b->offsets[k], b->inst_stride, sref(b->ranks + k + 1, n + 1, p), sconst(1)),
+            false, mat(Tb, tcap, sref(b->ranks + k + 1, n + 1, p), sconst(1)), one, false,
+            Dim{nullptr, 0, 0, 1 << 30}, b->cap[k]);
     // E' (ra_{k+1} x rb_{k+1}) = Ak^H (ra_{k+1} x ra_k p) * T (ra_k p x rb_{k+1})
-    gemm(st, B, dref(a->ranks + k + 1, sra), dref(b->ranks + k + 1, n + 1),
-         dref(a->ranks + k, sra, p), a->cap[k + 1], b->cap[k + 1], true, Ad + a->offsets[k], sA,
-         false, Tb, tcap, E1, env, one, false);
+    gemm_ex(st, B, 1, 1, dref(a->ranks + k + 1, sra), dref(b->ranks + k + 1, n + 1),
+            dref(a->ranks + k, sra, p), a->cap[k + 1], b->cap[k + 1],
+            mat(Ad + a->offsets[k], sA, sconst(1), sref(a->ranks + k + 1, sra)), true,
+            mat(Tb, tcap, sref(b->ranks + k + 1, n + 1), sconst(1)), false,
+            mat(E1, env, sref(b->ranks + k + 1, n + 1), sconst(1)), one, false,
+            Dim{nullptr, 0, 0, 1 << 30}, (int64_t)a->cap[k] * p);
     std::swap(E0, E1);
   }
   k_store_scalar<<<(B + 127) / 128, 128, 0, st>>>(B, E0, env, out);

@@ -486,10 +486,13 @@ __global__ __launch_bounds__(NT) void k_qrp_panel(int j0, Dim Md, Dim Nd, cplx* 
 }
 
 // Panel width and kernel of the blocked QR for a column capacity of mcap
-// rows (512 threads, so that a lane may hold up to 24 complex rows without
-// spilling): 64 columns in 8-lane groups up to 192 rows, 32 columns in
-// 16-lane groups up to 384, 16 columns in 32-lane groups up to 576, else the
-// 32-column global-memory panel.
+// rows: 64 columns in 8-lane groups of a 512-thread workgroup up to 192
+// rows; 32 columns in 32-lane groups of 1024 threads up to 288 rows (8 or 9
+// rows per lane: a column step's dependent chain is about proportional to
+// the rows per lane, 1.9 us per column at 8 against 4.6 at 24, measured on
+// 256 x 128); 32 columns in 16-lane groups of 512 threads up to 384; 16
+// columns in 32-lane groups up to 576; else the 32-column global-memory
+// panel.
 static int qrb_nb(int mcap) {
   if (mcap <= 8 * 24) return 64;
   if (mcap <= 16 * 24) return 32;
@@ -499,13 +502,15 @@ static int qrb_nb(int mcap) {
 
 static void qrb_panel(hipStream_t st, int batch, int mcap, int j0, Dim m, Dim n, cplx* Mw,
                       int64_t sM, int ld, const QrBlkWs& ws) {
-#define QP_LAUNCH(GL, RPL)                                                                  \
-  k_qrp_panel<512, GL, RPL><<<batch, 512, 0, st>>>(j0, m, n, Mw, sM, ld, ws.V, ws.v_stride, \
-                                                   ws.tau, ws.tau_stride, ws.T, ws.t_stride)
-  if (mcap <= 8 * 12) QP_LAUNCH(8, 12);
-  else if (mcap <= 8 * 24) QP_LAUNCH(8, 24);
-  else if (mcap <= 16 * 24) QP_LAUNCH(16, 24);
-  else if (mcap <= 32 * 18) QP_LAUNCH(32, 18);
+#define QP_LAUNCH(NT, GL, RPL)                                                             \
+  k_qrp_panel<NT, GL, RPL><<<batch, NT, 0, st>>>(j0, m, n, Mw, sM, ld, ws.V, ws.v_stride, \
+                                                 ws.tau, ws.tau_stride, ws.T, ws.t_stride)
+  if (mcap <= 8 * 12) QP_LAUNCH(512, 8, 12);
+  else if (mcap <= 8 * 24) QP_LAUNCH(512, 8, 24);
+  else if (mcap <= 32 * 8) QP_LAUNCH(1024, 32, 8);
+  else if (mcap <= 32 * 9) QP_LAUNCH(1024, 32, 9);
+  else if (mcap <= 16 * 24) QP_LAUNCH(512, 16, 24);
+  else if (mcap <= 32 * 18) QP_LAUNCH(512, 32, 18);
   else
     k_qrb_panel<<<batch, QB_T, 0, st>>>(j0, m, n, Mw, sM, ld, ws.V, ws.v_stride, ws.tau,
                                         ws.tau_stride, ws.T, ws.t_stride);

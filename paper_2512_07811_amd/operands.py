@@ -462,7 +462,9 @@ def build_problem(kvox=None, k0=None, L=None, section=None, op_eps=1e-10, sfft_e
     elif cell is not None:
         # a 2^L grid tiled by a periodic cell (L given)
         sp_k = material_tt_periodic(cell, L, 0.0, op_eps)
+        say(f"material train k, rank {max(c.shape[0] for c in sp_k)}")
         sp_kp = material_tt_periodic(cell, L, k0, op_eps)
+        say(f"material train k', rank {max(c.shape[0] for c in sp_kp)}")
         sp_k2 = material_tt_periodic((np.asarray(cell, dtype=np.float64) - k0) ** 2, L, 0.0,
                                      op_eps * 1e-2)
     else:
