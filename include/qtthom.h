@@ -296,6 +296,29 @@ qt_status tt_sketch_round(qt_ctx ctx, const qt_mpo* A, const qt_tt* y, const qt_
                           const qt_round_opts* opts, const double* xnorm2, qt_tt* out,
                           double* err_out, int32_t* fail_out);
 
+/* ---- AMEn product ---------------------------------------------------------- */
+
+/* y ~ A x for a TTO A and a TT x built directly in the TT format, without the
+ * rank-(r_A r_x) product and its compression: the alternating minimal energy
+ * method of Sec. 2.1 (Dolgov and Savostyanov 2014), which Algorithm 2 applies
+ * to the Green multiply.  Each of `sweeps` sweeps takes the cores of y from
+ * the local projections of A x onto y's frames, left to right, enriched by the
+ * residual approximation z ~ A x - y (updated in the same sweep), then rounds
+ * y at eps (truncated-SVD sweep and delta rule of Sec. 2.2, cap max_rank;
+ * 0 = capacity).
+ *  y: in/out, the initial guess on entry (any ranks within its capacities),
+ *     the result on return.  y->cap[k] must be >= min(max_rank, the natural
+ *     rank bound of bond k) (QT_EINVAL otherwise).
+ *  z: in/out, the residual guess (its ranks set the enrichment width, e.g. 4
+ *     to 16); the updated residual approximation on return.
+ *  err_out: device [B] (may be null), the last sweep's rounding error of y
+ *     relative to its norm.
+ * Batches: x, y, z share the batch; A is shared or per instance (inst_group).
+ * A must be square on x's modes.  Both y and z are first rounded at eps = 0
+ * (right-orthogonal frames).  Workspace grows as needed. */
+qt_status tt_amen_mv(qt_ctx ctx, const qt_mpo* A, const qt_tt* x, qt_tt* y, qt_tt* z, double eps,
+                     int32_t max_rank, int32_t sweeps, double* err_out);
+
 /* out[b] = scale * Re <y_b, Q y_b> for an operator train Q (used with
  * Q = A^H A to get ||A y||^2 exactly without forming A y). */
 qt_status tt_sandwich(qt_ctx ctx, const qt_mpo* Q, const qt_tt* y, double scale, double* out);

@@ -42,9 +42,8 @@ def orthogonalize_right(tt):
     return cores
 
 
-def _local(A, x, k):
-    """A_k x_k as (ra, rx, p_out, ra', rx')."""
-    return np.einsum("aijb,xjy->axiby", A[k], x[k])
+def _c(spec, *ops):
+    return np.einsum(spec, *ops, optimize=True)
 
 
 def amen_mv(A, x, y0, z0, eps: float, rmax: int | None = None, sweeps: int = 2,
@@ -64,24 +63,24 @@ def amen_mv(A, x, y0, z0, eps: float, rmax: int | None = None, sweeps: int = 2,
         PzyR = [None] * (n + 1)
         PyR[n], PzR[n], PzyR[n] = one3, one3, np.ones((1, 1), dtype=np.complex128)
         for k in range(n - 1, 0, -1):
-            AX = _local(A, x, k)
-            PyR[k] = np.einsum("yiY,axiBX,YBX->yax", np.conj(y[k]), AX, PyR[k + 1])
-            PzR[k] = np.einsum("ziZ,axiBX,ZBX->zax", np.conj(z[k]), AX, PzR[k + 1])
-            PzyR[k] = np.einsum("ziZ,yiY,ZY->zy", np.conj(z[k]), y[k], PzyR[k + 1])
+            Ak, xk = A[k], x[k]
+            PyR[k] = _c("yiY,aijB,xjX,YBX->yax", np.conj(y[k]), Ak, xk, PyR[k + 1])
+            PzR[k] = _c("ziZ,aijB,xjX,ZBX->zax", np.conj(z[k]), Ak, xk, PzR[k + 1])
+            PzyR[k] = _c("ziZ,yiY,ZY->zy", np.conj(z[k]), y[k], PzyR[k + 1])
         PyL, PzL = one3, one3
         PzyL = np.ones((1, 1), dtype=np.complex128)
         ny, nz = [], []
         for k in range(n):
-            AX = _local(A, x, k)
-            yk = np.einsum("yax,axiBX,YBX->yiY", PyL, AX, PyR[k + 1])
-            zk = (np.einsum("zax,axiBX,ZBX->ziZ", PzL, AX, PzR[k + 1])
-                  - np.einsum("zy,yiY,ZY->ziZ", PzyL, yk, PzyR[k + 1]))
+            Ak, xk = A[k], x[k]
+            yk = _c("yax,aijB,xjX,YBX->yiY", PyL, Ak, xk, PyR[k + 1])
+            zk = (_c("zax,aijB,xjX,ZBX->ziZ", PzL, Ak, xk, PzR[k + 1])
+                  - _c("zy,yiY,ZY->ziZ", PzyL, yk, PzyR[k + 1]))
             if k == n - 1:
                 ny.append(yk)
                 nz.append(zk)
                 break
-            ek = (np.einsum("yax,axiBX,ZBX->yiZ", PyL, AX, PzR[k + 1])
-                  - np.einsum("yiY,ZY->yiZ", yk, PzyR[k + 1]))
+            ek = (_c("yax,aijB,xjX,ZBX->yiZ", PyL, Ak, xk, PzR[k + 1])
+                  - _c("yiY,ZY->yiZ", yk, PzyR[k + 1]))
             ry, p, rY = yk.shape
             Qy, _ = np.linalg.qr(np.concatenate([yk.reshape(ry * p, rY),
                                                  ek.reshape(ry * p, -1)], axis=1))
@@ -91,9 +90,9 @@ def amen_mv(A, x, y0, z0, eps: float, rmax: int | None = None, sweeps: int = 2,
             Qz = Qz.reshape(rz, p, -1)
             ny.append(Qy)
             nz.append(Qz)
-            PyL = np.einsum("yax,yiY,axiBX->YBX", PyL, np.conj(Qy), AX)
-            PzL = np.einsum("zax,ziZ,axiBX->ZBX", PzL, np.conj(Qz), AX)
-            PzyL = np.einsum("zy,ziZ,yiY->ZY", PzyL, np.conj(Qz), Qy)
+            PyL = _c("yax,yiY,aijB,xjX->YBX", PyL, np.conj(Qy), Ak, xk)
+            PzL = _c("zax,ziZ,aijB,xjX->ZBX", PzL, np.conj(Qz), Ak, xk)
+            PzyL = _c("zy,ziZ,yiY->ZY", PzyL, np.conj(Qz), Qy)
         y = T.round_tt(ny, eps, rmax)
         z = orthogonalize_right(nz)
         if prev is not None:

@@ -24,7 +24,7 @@ PREC_F64, PREC_F32 = 0, 1
 EXPORTS = ["qt_ctx_create", "qt_ctx_destroy", "qt_last_error", "qt_ctx_sync",
            "qt_ctx_counters", "qt_ctx_profile", "qt_ctx_profile_read", "qt_ctx_autotune",
            "tt_hadamard",
-           "tt_mpo_apply", "tt_add", "tt_round", "tt_round_noalloc", "tt_dot", "tt_sketch_round", "tt_sandwich",
+           "tt_mpo_apply", "tt_add", "tt_round", "tt_round_noalloc", "tt_dot", "tt_sketch_round", "tt_sandwich", "tt_amen_mv",
            "ls_iterate", "homogenize", "qt_mlp_num_params", "qt_mlp_train_step", "qt_mlp_infer",
            "qt_ranklog_enable", "qt_ranklog_get", "qt_set_predictor", "qt_learn_reset",
            "qt_learn_log_enable", "qt_learn_log_get", "qt_ctx_fixed_bytes",
@@ -99,6 +99,8 @@ def load_library(path: str = LIB_PATH):
     lib.tt_sketch_round.argtypes = [vp, C.POINTER(MPODesc), C.POINTER(TTDesc), C.POINTER(TTDesc),
                                     C.POINTER(RoundOpts), vp, C.POINTER(TTDesc), vp, vp]
     lib.tt_sandwich.argtypes = [vp, C.POINTER(MPODesc), C.POINTER(TTDesc), dbl, vp]
+    lib.tt_amen_mv.argtypes = [vp, C.POINTER(MPODesc), C.POINTER(TTDesc), C.POINTER(TTDesc),
+                               C.POINTER(TTDesc), dbl, i32, i32, vp]
     lib.ls_iterate.argtypes = [vp, C.POINTER(Operands), C.POINTER(TTDesc), C.POINTER(SolveOpts),
                                i32, vp]
     lib.homogenize.argtypes = [vp, C.POINTER(Operands), C.POINTER(TTDesc), C.POINTER(TTDesc),
@@ -480,6 +482,18 @@ def tt_sketch_round(ctx: Context, A: DeviceMPO, y: DeviceTT, xnorm2, out: Device
                                    C.c_void_p(xnorm2.data_ptr()), C.byref(out.desc()),
                                    C.c_void_p(err.data_ptr()), C.c_void_p(fail.data_ptr())))
     return err, fail
+
+
+def tt_amen_mv(ctx: Context, A: DeviceMPO, x: DeviceTT, y: DeviceTT, z: DeviceTT, eps: float,
+               max_rank: int = 0, sweeps: int = 2):
+    """AMEn approximation y ~ A x in place (y: initial guess in, result out; z:
+    residual guess in and out); returns the last sweep's rounding error [batch]."""
+    torch = _torch()
+    err = torch.zeros(x.batch, dtype=torch.float64, device=x.data.device)
+    _check(ctx.lib.tt_amen_mv(ctx.h, C.byref(A.desc()), C.byref(x.desc()), C.byref(y.desc()),
+                              C.byref(z.desc()), float(eps), int(max_rank), int(sweeps),
+                              C.c_void_p(err.data_ptr())))
+    return err
 
 
 @dataclass
