@@ -666,11 +666,82 @@ __global__ void k_keep_to_flags(int B, const int32_t* __restrict__ keep, int32_t
   if (b < B) lo[b] = keep[b];
 }
 
+// Buffers of the learned path: spare outputs for the fallback (layout of each
+// step's output), its ranks and errors, per-instance orientation flags and
+// norm scratch; for batches, the compacted redo of the instances that fell
+// back: their inputs (yc, ranks rc), per-instance operators (ac), norms (xc),
+// sketch R diagonals (rdc) and indices (idx).
+struct LearnBufs {
+  char* spare = nullptr;
+  int32_t* rS = nullptr;
+  double* err2 = nullptr;
+  int32_t* lo = nullptr;
+  double* ntmp = nullptr;
+  cplx* yc = nullptr;
+  int32_t* rc = nullptr;
+  cplx* ac = nullptr;
+  double* xc = nullptr;
+  double* rdc = nullptr;
+  int32_t* idx = nullptr;
+};
+
+// idx[0..nf) = the instances b with keep[b] == 0, in order (one block)
+__global__ void k_fail_index(int B, const int32_t* __restrict__ keep, int32_t* __restrict__ idx) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int j = 0;
+  for (int b = 0; b < B; ++b)
+    if (!keep[b]) idx[j++] = b;
+}
+
+// dst instance j <- src instance idx[j] / grp: `per` elements, optionally the
+// ranks (n1 per instance) and one double (xn2)
+__global__ void k_gather_inst(int64_t per, const int32_t* __restrict__ idx, int grp,
+                              const cplx* __restrict__ src, int64_t sS, cplx* __restrict__ dst,
+                              int64_t sD, int n1, const int32_t* __restrict__ rsrc,
+                              int32_t* __restrict__ rdst, const double* __restrict__ xsrc,
+                              double* __restrict__ xdst) {
+  const int j = blockIdx.y;
+  const int64_t b = idx[j] / grp;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < per;
+       e += (int64_t)gridDim.x * blockDim.x)
+    dst[j * sD + e] = src[b * sS + e];
+  if (blockIdx.x == 0) {
+    if (rdst)
+      for (int k = threadIdx.x; k < n1; k += blockDim.x) rdst[(int64_t)j * n1 + k] = rsrc[b * n1 + k];
+    if (xdst && threadIdx.x == 0) xdst[j] = xsrc[b];
+  }
+}
+
+// out instance idx[j] <- spare instance j (cores, ranks, error bound and
+// estimate, sketch R diagonals)
+__global__ void k_scatter_fallback(int64_t per, int n1, int B, int nf, const int32_t* __restrict__ idx,
+                                   const cplx* __restrict__ spare, const int32_t* __restrict__ rk2,
+                                   const double* __restrict__ err2, cplx* out, int32_t* rk,
+                                   double* err, const double* __restrict__ rdc, double* rd,
+                                   int64_t rd_per) {
+  const int j = blockIdx.y;
+  const int64_t b = idx[j];
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < per;
+       e += (int64_t)gridDim.x * blockDim.x)
+    out[b * per + e] = spare[(int64_t)j * per + e];
+  if (rd)
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < rd_per;
+         e += (int64_t)gridDim.x * blockDim.x)
+      rd[b * rd_per + e] = rdc[(int64_t)j * rd_per + e];
+  if (blockIdx.x == 0) {
+    for (int k = threadIdx.x; k < n1; k += blockDim.x) rk[b * n1 + k] = rk2[(int64_t)j * n1 + k];
+    if (threadIdx.x == 0) {
+      err[b] = err2[j];
+      err[B + b] = err2[nf + j];
+    }
+  }
+}
+
 static qt_status round_step(qt_ctx ctx, int step, const qt_mpo* A, const qt_tt* y,
                             const std::vector<int32_t>& ell_plan, const qt_round_opts& base,
                             const double* xn2, qt_tt* out, double* err_dev, uint64_t iter_id,
                             bool learned, bool logging, int32_t* lo_flags, qt_tt* spare,
-                            double* err2) {
+                            double* err2, const LearnBufs& lb) {
   const int n = y->n, B = y->batch;
   LearnCtx* L = ctx->learn;
   const bool track = L && (learned || logging);
@@ -699,13 +770,50 @@ static qt_status round_step(qt_ctx ctx, int step, const qt_mpo* A, const qt_tt* 
     QT_HIP(hipStreamSynchronize(ctx->stream));
     // kept instances: left-orthogonal fixed-rank output
     k_fill_i32<<<(B + 255) / 256, 256, 0, ctx->stream>>>(B, 1, lo_flags);
-    if (nfail > 0) {
-      qt_round_opts fo = base;
-      fo.mode = QT_ROUND_SKETCH;
+    qt_round_opts fo = base;
+    fo.mode = QT_ROUND_SKETCH;
+    const int64_t per = out->inst_stride;
+    const int64_t rd_per = (int64_t)(n + 1) * RD_MAX;
+    if (nfail > 0 && nfail < B && lb.yc) {
+      // redo only the instances that fell back, as a compacted batch: gather
+      // their inputs (and per-instance operators and norms), round them
+      // SVD-truncated into the spare train, scatter the results back
+      const int nf = nfail;
+      k_fail_index<<<1, 64, 0, ctx->stream>>>(B, L->keep, lb.idx);
+      dim3 gy((unsigned)std::min<int64_t>((y->inst_stride + 255) / 256, 64), nf);
+      k_gather_inst<<<gy, 256, 0, ctx->stream>>>(y->inst_stride, lb.idx, 1, (const cplx*)y->data,
+                                                 y->inst_stride, lb.yc, y->inst_stride, n + 1,
+                                                 y->ranks, lb.rc, xn2, lb.xc);
+      qt_tt yc = *y;
+      yc.batch = nf;
+      yc.data = lb.yc;
+      yc.ranks = lb.rc;
+      qt_mpo Ac = *A;
+      if (A->inst_stride > 0) {
+        dim3 ga((unsigned)std::min<int64_t>((A->inst_stride + 255) / 256, 64), nf);
+        k_gather_inst<<<ga, 256, 0, ctx->stream>>>(
+            A->inst_stride, lb.idx, A->inst_group > 0 ? A->inst_group : 1, (const cplx*)A->data,
+            A->inst_stride, lb.ac, A->inst_stride, 0, nullptr, nullptr, nullptr, nullptr);
+        Ac.data = lb.ac;
+        Ac.inst_group = 1;
+      }
+      qt_tt sc = *spare;
+      sc.batch = nf;
+      QT_TRY(sround_impl(ctx, &Ac, &yc, nullptr, nullptr, ell_plan, &fo, lb.xc, &sc, err2, nullptr,
+                         iter_id * 4 + step + (1ull << 40), nullptr, 0, 0, rd ? lb.rdc : nullptr,
+                         err2 + nf));
+      ctx->ws_top = mark;
+      dim3 gs((unsigned)std::min<int64_t>((per + 255) / 256, 64), nf);
+      k_scatter_fallback<<<gs, 256, 0, ctx->stream>>>(per, n + 1, B, nf, lb.idx,
+                                                      (const cplx*)spare->data, spare->ranks, err2,
+                                                      (cplx*)out->data, out->ranks, err_dev,
+                                                      lb.rdc, rd, rd_per);
+      k_keep_to_flags<<<(B + 255) / 256, 256, 0, ctx->stream>>>(B, L->keep, lo_flags);
+      learn_set_ref(ctx, step, est_dev, L->keep);
+    } else if (nfail > 0) {
       QT_TRY(sround_impl(ctx, A, y, nullptr, nullptr, ell_plan, &fo, xn2, spare, err2, nullptr,
                          iter_id * 4 + step + (1ull << 40), nullptr, 0, 0, rd, err2 + B));
       ctx->ws_top = mark;
-      const int64_t per = out->inst_stride;
       dim3 grid((unsigned)std::min<int64_t>((per + 255) / 256, 64), B);
       k_take_fallback<<<grid, 256, 0, ctx->stream>>>(per, n + 1, B, L->keep, (const cplx*)spare->data,
                                                      spare->ranks, err2, (cplx*)out->data,
@@ -719,10 +827,16 @@ static qt_status round_step(qt_ctx ctx, int step, const qt_mpo* A, const qt_tt* 
     k_fill_i32<<<(B + 255) / 256, 256, 0, ctx->stream>>>(B, 0, lo_flags);
     if (learned && L) learn_set_ref(ctx, step, est_dev, nullptr);
   }
-  // the stored sketch R diagonals are the fallback's where one ran
-  if (track)
-    learn_features(ctx, step, (use_learned && nfail == 0) ? ell : ell_plan, xn2, base.eps,
-                   base.max_rank);
+  // the stored sketch R diagonals are the fallback's where one ran (every
+  // instance's after a whole-batch redo, the failed ones' after a compacted one)
+  if (track) {
+    const bool compacted = use_learned && nfail > 0 && nfail < B && lb.yc;
+    if (compacted)
+      learn_features(ctx, step, ell, xn2, base.eps, base.max_rank, &ell_plan, L->keep);
+    else
+      learn_features(ctx, step, (use_learned && nfail == 0) ? ell : ell_plan, xn2, base.eps,
+                     base.max_rank);
+  }
   if (!use_learned && logging) learn_log(ctx, step, out->ranks);
   QT_HIP(hipGetLastError());
   return QT_OK;
@@ -758,16 +872,6 @@ static void weight_norm2(hipStream_t st, const qt_tt& t, const int32_t* lo, doub
   k_pick_norm<<<(B + 127) / 128, 128, 0, st>>>(B, lo, tmp, tmp + B, out);
 }
 
-// Buffers of the learned path: spare outputs for the fallback (layout of each
-// step's output), its ranks and errors, per-instance orientation flags and
-// norm scratch.
-struct LearnBufs {
-  char* spare = nullptr;
-  int32_t* rS = nullptr;
-  double* err2 = nullptr;
-  int32_t* lo = nullptr;
-  double* ntmp = nullptr;
-};
 
 static qt_status iterate_once_sketch(qt_ctx ctx, const qt_operands* ops, qt_tt* e,
                                      const SketchPlan& P, const qt_round_opts& ro, char* bufA,
@@ -787,13 +891,13 @@ static qt_status iterate_once_sketch(qt_ctx ctx, const qt_operands* ops, qt_tt* 
   ctx->ws_top = mark;
   qt_tt t1 = P.l1.view(bufA, rA, B);
   QT_TRY(round_step(ctx, 0, &ops->Kp, e, P.ell1, ro, xn2, &t1, err_dev, iter_id, learned, logging,
-                    lo, &sp1, lb.err2));
+                    lo, &sp1, lb.err2, lb));
   qt_tt t1r = view_caps(t1, P.c1r);
   // tau^ = R(S tau);  ||S tau|| = ||tau|| (S unitary)
   weight_norm2(st, t1r, lo, lb.ntmp, xn2);
   qt_tt t2 = P.l2.view(bufB, rB, B);
   QT_TRY(round_step(ctx, 1, &ops->S, &t1r, P.ell2, ro, xn2, &t2, err_dev, iter_id, learned, logging,
-                    lo, &sp2, lb.err2));
+                    lo, &sp2, lb.err2, lb));
   qt_tt t2r = view_caps(t2, P.c2r);
   // eps^ = R(G tau^);  ||G t||^2 = <t, G t>/k0 (scalar conductivity: k0 G is a
   // projector), or <t, G2 t> with G2 = G^H G given as an operand (elasticity)
@@ -802,7 +906,7 @@ static qt_status iterate_once_sketch(qt_ctx ctx, const qt_operands* ops, qt_tt* 
   ctx->ws_top = mark;
   qt_tt t3 = P.l3.view(bufA, rA, B);
   QT_TRY(round_step(ctx, 2, &ops->G, &t2r, P.ell3, ro, xn2, &t3, err_dev, iter_id, learned, logging,
-                    lo, &sp3, lb.err2));
+                    lo, &sp3, lb.err2, lb));
   qt_tt t3r = view_caps(t3, P.c3r);
   // t = S E - eps^;  ||t||^2 by environments (no cancellation: Gamma(0) = 0
   // makes eps^ vanish at the zero frequency, where S E lives)
@@ -819,7 +923,7 @@ static qt_status iterate_once_sketch(qt_ctx ctx, const qt_operands* ops, qt_tt* 
   // e' = R(S^H t) = E - S^H eps^
   qt_tt t4 = P.l4.view(bufA, rA, B);
   QT_TRY(round_step(ctx, 3, &ops->Sinv, &ttr, P.ell4, ro, xn2, &t4, err_dev, iter_id, learned,
-                    logging, lo, &sp4, lb.err2));
+                    logging, lo, &sp4, lb.err2, lb));
   qt_tt t4r = view_caps(t4, P.c4r);
   if (learned || logging) {
     const std::vector<int32_t>* ells[4] = {&P.ell1, &P.ell2, &P.ell3, &P.ell4};
@@ -880,6 +984,24 @@ static size_t solver_arena_bytes(size_t bytesA, size_t bytesB, size_t ws, size_t
          sizeof(double) * B * 9 + sizeof(int32_t) * B + 14 * 256;
 }
 
+static size_t learn_spare_train_bytes(const SketchPlan& P, int B) {
+  return (sizeof(cplx) * B * std::max({P.l1.stride, P.l2.stride, P.l3.stride, P.l4.stride}) + 255) &
+         ~(size_t)255;
+}
+// inputs of the four roundings: the field, t1, t2 and S E - eps^ (layouts l1, l2, l5)
+static int64_t learn_input_stride(const qt_tt* e, const SketchPlan& P) {
+  return std::max({e->inst_stride, P.l1.stride, P.l2.stride, P.l5.stride});
+}
+static int64_t learn_op_stride(const qt_operands* ops) {
+  return std::max({ops->Kp.inst_stride, ops->S.inst_stride, ops->G.inst_stride,
+                   ops->Sinv.inst_stride});
+}
+static size_t learn_compact_bytes(const qt_operands* ops, const qt_tt* e, const SketchPlan& P) {
+  const int64_t B = e->batch, n = e->n;
+  return sizeof(cplx) * B * (learn_input_stride(e, P) + learn_op_stride(ops)) +
+         sizeof(double) * B * ((n + 1) * RD_MAX + 1) + sizeof(int32_t) * B * (n + 2) + 8 * 256;
+}
+
 // Plan and arena sizes of a solve (no context needed: also the workspace query).
 static qt_status solver_plan(const qt_operands* ops, const qt_tt* e, const qt_solve_opts* opts,
                              Solver& S, size_t& bytesA, size_t& bytesB, size_t& ws,
@@ -909,11 +1031,13 @@ static qt_status solver_plan(const qt_operands* ops, const qt_tt* e, const qt_so
     S.P = plan_iteration(ops, e, rmax);
     bytesA = S.P.bytesA; bytesB = S.P.bytesB; ws = iteration_bytes(S.P, B, rmax) - S.P.bytesA - S.P.bytesB;
   }
-  // the learned path's fallback writes into a spare train of the largest step layout
+  // the learned path's fallback writes into a spare train of the largest step
+  // layout; batches also hold the buffers of the compacted redo (after it)
   spare = 0;
-  if (S.learned)
-    spare = sizeof(cplx) * B * std::max({S.SP.l1.stride, S.SP.l2.stride, S.SP.l3.stride,
-                                         S.SP.l4.stride});
+  if (S.learned) {
+    spare = learn_spare_train_bytes(S.SP, B);
+    if (B > 1) spare += learn_compact_bytes(ops, e, S.SP);
+  }
   return QT_OK;
 }
 
@@ -945,7 +1069,22 @@ static qt_status solver_setup(qt_ctx ctx, const qt_operands* ops, qt_tt* e,
   S.lb.err2 = (double*)ws_take(ctx, sizeof(double) * 2 * B);
   S.lb.lo = (int32_t*)ws_take(ctx, sizeof(int32_t) * B);
   S.lb.ntmp = (double*)ws_take(ctx, sizeof(double) * 2 * B);
-  if (spare) S.lb.spare = (char*)ws_take(ctx, spare);
+  if (spare) {
+    const size_t train = learn_spare_train_bytes(S.SP, B);
+    S.lb.spare = (char*)ws_take(ctx, train);
+    QT_CHECK(S.lb.spare, QT_ENOMEM, "iteration workspace (learned path)");
+    if (spare > train) {
+      S.lb.yc = (cplx*)ws_take(ctx, sizeof(cplx) * B * learn_input_stride(e, S.SP));
+      const int64_t as = learn_op_stride(ops);
+      S.lb.ac = as > 0 ? (cplx*)ws_take(ctx, sizeof(cplx) * B * as) : nullptr;
+      S.lb.rdc = (double*)ws_take(ctx, sizeof(double) * B * (n + 1) * RD_MAX);
+      S.lb.xc = (double*)ws_take(ctx, sizeof(double) * B);
+      S.lb.rc = (int32_t*)ws_take(ctx, sizeof(int32_t) * B * (n + 1));
+      S.lb.idx = (int32_t*)ws_take(ctx, sizeof(int32_t) * B);
+      QT_CHECK(S.lb.yc && (as == 0 || S.lb.ac) && S.lb.rdc && S.lb.xc && S.lb.rc && S.lb.idx,
+               QT_ENOMEM, "iteration workspace (compacted fallback)");
+    }
+  }
   QT_CHECK(S.lb.rS && S.lb.err2 && S.lb.lo && S.lb.ntmp && (!spare || S.lb.spare), QT_ENOMEM,
            "iteration workspace (learned path)");
   std::vector<double> inv(B);

@@ -54,8 +54,11 @@ struct LearnCtx {
 qt_status learn_ensure(qt_ctx ctx, int n, int B);
 // device bytes of the learned state of n cores and B instances
 size_t learn_state_bytes(int n, int B);
+// features of this step's roundings from their sketch R diagonals; alt /
+// alt_of (optional): widths of the instances b with alt_of[b] == 0
 void learn_features(qt_ctx ctx, int step, const std::vector<int32_t>& ell, const double* xn2,
-                    double eps, int rmax);
+                    double eps, int rmax, const std::vector<int32_t>* alt = nullptr,
+                    const int32_t* alt_of = nullptr);
 void learn_log(qt_ctx ctx, int step, const int32_t* ranks);
 // keep[b] = (err[b] <= reference of step s for instance b); counts the learned
 // roundings and the fallbacks on the device; appends to the rounding log.

@@ -21,12 +21,16 @@ struct EllArr {
 };
 
 // grid (ceil((n-1)/64), B): bond k of instance b
-__global__ void k_features(const double* __restrict__ rd, EllArr ell, const double* xn2, int n,
+// alt / alt_of (may be null): instances b with alt_of[b] == 0 had their
+// sketch at the widths alt instead of ell (the instances whose learned
+// rounding fell back and was redone at the plan widths).
+__global__ void k_features(const double* __restrict__ rd, EllArr ell, EllArr alt,
+                           const int32_t* __restrict__ alt_of, const double* xn2, int n,
                            double eps, int rmax, int step, float* __restrict__ feat) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x + 1;   // bond 1..n-1
   const int b = blockIdx.y;
   if (k >= n) return;
-  const int l = max(ell.v[k], 1);
+  const int l = max((alt_of && alt_of[b] == 0) ? alt.v[k] : ell.v[k], 1);
   const double xn = sqrt(fmax(xn2[b], 1e-300));
   float* f = feat + ((int64_t)b * QT_MAX_CORES + (k - 1)) * QT_RANK_FEATURES;
   const double* r = rd + ((int64_t)b * (n + 1) + k) * RD_MAX;
@@ -165,13 +169,15 @@ qt_status learn_ensure(qt_ctx ctx, int n, int B) {
 }
 
 void learn_features(qt_ctx ctx, int step, const std::vector<int32_t>& ell, const double* xn2,
-                    double eps, int rmax) {
+                    double eps, int rmax, const std::vector<int32_t>* alt, const int32_t* alt_of) {
   LearnCtx* L = ctx->learn;
-  EllArr e{};
+  EllArr e{}, a{};
   for (size_t k = 0; k < ell.size() && k <= QT_MAX_CORES; ++k) e.v[k] = ell[k];
+  if (alt)
+    for (size_t k = 0; k < alt->size() && k <= QT_MAX_CORES; ++k) a.v[k] = (*alt)[k];
   dim3 grid((L->n + 62) / 64, L->B);
-  k_features<<<grid, 64, 0, ctx->stream>>>(L->rdiag_at(step), e, xn2, L->n, eps, rmax, step,
-                                           L->feat_at(L->cur, step));
+  k_features<<<grid, 64, 0, ctx->stream>>>(L->rdiag_at(step), e, a, alt ? alt_of : nullptr, xn2,
+                                           L->n, eps, rmax, step, L->feat_at(L->cur, step));
 }
 
 void learn_log(qt_ctx ctx, int step, const int32_t* ranks) {

@@ -428,3 +428,46 @@ def test_capped_learned_roundings_obey_the_acceptance_rule(q, cell, trained):
         assert np.all(gap <= 20.0 * np.max(res_s[-1]))
     finally:
         ctx2.close()
+
+
+def test_partial_fallback_redoes_only_the_failed_instances(q, cell):
+    # a batch of a homogeneous cell (its field stays E: rank 1, every rounding
+    # of the always-rank-8 network is exact) and the sphere cell (rank 8 is too
+    # small): only the sphere's roundings fall back, and they are redone as a
+    # compacted batch with its own k' operator instance; each field's A_eff and
+    # residuals equal the batched SVD-truncated path's
+    import torch
+
+    from paper_2512_07811_amd import learned
+    from paper_2512_07811_amd import operands as P
+    N = 2 ** L_SMALL
+    homo = P.build_problem(kvox=np.full((N, N, N), 1.0), k0=5.5)
+    probs = [homo, cell[1]]
+    loads = [[1.0, 0.0, 0.0]]
+    c = q.Context(0)
+    try:
+        layers = f32_layers(31)
+        layers[7] = np.array([50.0] + [-50.0] * (C - 1), dtype=np.float32)
+        layers[6] = np.zeros_like(layers[6])
+        params = torch.from_numpy(learned.flat_params(layers)).cuda()
+        q.set_predictor(c, params, C, 0.9, 1.0)
+        runs = {}
+        for mode in (q.ROUND_SKETCH, q.ROUND_LEARNED):
+            ops, e = P.upload_batch(probs, loads, RMAX)
+            c.counters(reset=True)
+            A, its, res, st = q.homogenize(c, ops, e, sketch_opts(q, mode))
+            runs[mode] = (A, its, res, c.counters(reset=True))
+            assert st == q.QT_OK
+        (A_s, its_s, res_s, _), (A_l, its_l, res_l, cnt) = runs[q.ROUND_SKETCH], runs[q.ROUND_LEARNED]
+        print(f"[learned] partial fallback: {cnt['learned_fallbacks']} of "
+              f"{cnt['learned_roundings']} instance roundings, iterations {its_l.tolist()} "
+              f"(SVD-truncated {its_s.tolist()}), A_eff {A_l[:, 0].tolist()} "
+              f"vs {A_s[:, 0].tolist()}", flush=True)
+        assert 0 < cnt["learned_fallbacks"] < cnt["learned_roundings"]
+        for b in range(2):
+            assert abs(A_l[b, 0] - A_s[b, 0]) < 1e-6 * abs(A_s[b, 0])
+            assert abs(its_l[b] - its_s[b]) <= 2
+        # the homogeneous cell's flux is k E exactly
+        assert abs(A_l[0, 0] - 1.0) < 1e-10
+    finally:
+        c.close()
