@@ -386,7 +386,11 @@ qt_status ls_iterate(qt_ctx ctx, const qt_operands* ops, qt_tt* e, const qt_solv
  *   (batch = e->batch); A_eff[b][c] is then the mean flux or the mean stress
  *   component c: column j of the effective tensor for the load e_j.
  * e: field batch used as the iterate (capacities as for ls_iterate).
- * A_eff: host [B][d]; iters: host [B] (iterations to convergence);
+ * A_eff: host [B][d], each field's from its iterate at the iteration where
+ *   its residual first fell below tol (fields of a batch that converge early
+ *   keep iterating with the others, but their A_eff is taken then, as a
+ *   separate solve would take it; fields that do not converge: the last
+ *   iterate); iters: host [B] (iterations to convergence);
  * residuals: host [max_iter][B] (may be NULL). */
 qt_status homogenize(qt_ctx ctx, const qt_operands* ops, const qt_tt* k_sel, qt_tt* e,
                      const qt_solve_opts* opts, double* A_eff, int32_t* iters,

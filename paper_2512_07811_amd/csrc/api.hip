@@ -1407,8 +1407,38 @@ qt_status homogenize(qt_ctx ctx, const qt_operands* ops, const qt_tt* k_sel, qt_
   QT_TRY(tt_copy(ctx, &ops->E, e));
   QT_TRY(qt_learn_reset(ctx));   // a new field: no previous-iteration features
   std::vector<double> hres(B);
-  std::vector<int> done(B, 0);
+  std::vector<int> done(B, 0), taken(B, 0);
   for (int b = 0; b < B; ++b) iters[b] = opts->max_iter;
+  // A_eff[b][c] = Re <k_sel[c], e_b> / N^3 for the instances with take[b]
+  // (the iterate of each field when it converges: fields of a batch that
+  // converge early go on iterating with the others, so their A_eff is taken
+  // at that iteration, as a separate solve of the field would take it)
+  std::vector<double> hd(2 * B);
+  const double N3 = std::ldexp(1.0, 3 * ops->L);
+  auto take_aeff = [&](const std::vector<int>& take) -> qt_status {
+    const size_t mark = ctx->ws_top;
+    double* dd = (double*)ws_take(ctx, sizeof(double) * 2 * B);
+    QT_CHECK(dd, QT_ENOMEM, "homogenize: workspace");
+    const size_t top = ctx->ws_top;
+    for (int c = 0; c < d; ++c) {
+      ctx->ws_top = top;
+      // dot workspace must fit in what setup reserved: environments are small
+      qt_status s = dot_impl(ctx, &k_sel[c], e, dd, false);
+      if (s == QT_ENOMEM || ctx->ws_top > ctx->ws_size) {
+        ctx->ws_top = mark;
+        set_error("homogenize: dot workspace");
+        return QT_ENOMEM;
+      }
+      if (s != QT_OK) { ctx->ws_top = mark; return s; }
+      QT_HIP(hipMemcpyAsync(hd.data(), dd, sizeof(double) * 2 * B, hipMemcpyDeviceToHost, ctx->stream));
+      QT_HIP(hipStreamSynchronize(ctx->stream));
+      for (int b = 0; b < B; ++b)
+        if (take[b]) A_eff[(int64_t)b * d + c] = hd[2 * b] / N3;
+    }
+    ctx->ws_top = mark;
+    for (int b = 0; b < B; ++b) taken[b] |= take[b];
+    return QT_OK;
+  };
   int it = 0;
   bool all = false;
   for (it = 1; it <= opts->max_iter && !all; ++it) {
@@ -1416,31 +1446,20 @@ qt_status homogenize(qt_ctx ctx, const qt_operands* ops, const qt_tt* k_sel, qt_
     QT_HIP(hipMemcpyAsync(hres.data(), dres, sizeof(double) * B, hipMemcpyDeviceToHost, ctx->stream));
     QT_TRY(check_status(ctx));
     all = true;
+    std::vector<int> now(B, 0);
+    bool any = false;
     for (int b = 0; b < B; ++b) {
       if (residuals) residuals[(int64_t)(it - 1) * B + b] = hres[b];
-      if (!done[b] && hres[b] < opts->tol) { done[b] = 1; iters[b] = it; }
+      if (!done[b] && hres[b] < opts->tol) { done[b] = 1; iters[b] = it; now[b] = 1; any = true; }
       all = all && done[b];
     }
+    if (any) QT_TRY(take_aeff(now));
   }
-  // A_eff[b][c] = Re <k_sel[c], e_b> / N^3
-  const size_t mark = ctx->ws_top;
-  double* dd = (double*)ws_take(ctx, sizeof(double) * 2 * B);
-  QT_CHECK(dd, QT_ENOMEM, "homogenize: workspace");
-  std::vector<double> hd(2 * B);
-  const double N3 = std::ldexp(1.0, 3 * ops->L);
-  for (int c = 0; c < d; ++c) {
-    ctx->ws_top = mark + 256 * ((sizeof(double) * 2 * B + 255) / 256);
-    // dot workspace must fit in what setup reserved: environments are small
-    qt_status s = dot_impl(ctx, &k_sel[c], e, dd, false);
-    if (s == QT_ENOMEM || ctx->ws_top > ctx->ws_size) {
-      set_error("homogenize: dot workspace");
-      return QT_ENOMEM;
-    }
-    QT_TRY(s);
-    QT_HIP(hipMemcpyAsync(hd.data(), dd, sizeof(double) * 2 * B, hipMemcpyDeviceToHost, ctx->stream));
-    QT_HIP(hipStreamSynchronize(ctx->stream));
-    for (int b = 0; b < B; ++b) A_eff[(int64_t)b * d + c] = hd[2 * b] / N3;
-  }
+  // fields that did not converge: the last iterate
+  std::vector<int> rest(B, 0);
+  bool any_rest = false;
+  for (int b = 0; b < B; ++b) { rest[b] = !taken[b]; any_rest = any_rest || rest[b]; }
+  if (any_rest) QT_TRY(take_aeff(rest));
   QT_TRY(check_status(ctx));
   return all ? QT_OK : QT_NOT_CONVERGED;
 }

@@ -65,3 +65,28 @@ def test_plain_iteration_rejects_per_instance_operators(q, ctx, cells):
     ops, e = P.upload_batch(probs, LOADS, 0)
     with pytest.raises(q.QtError):
         q.ls_iterate(ctx, ops, e, opts(q, q.ROUND_SVD), 1)
+
+
+def test_early_converged_fields_keep_their_own_a_eff(q, ctx, cells):
+    # one cell, loads e_x and e_y: at tol 1e-4 the dense oracle converges in
+    # 14 and 15 iterations, so in the batch e_x converges first and goes on
+    # iterating with e_y; its A_eff must still be that of iteration 14, as in
+    # its separate solve (the SVD rounding draws nothing at random)
+    from paper_2512_07811_amd import operands as P
+    kv, probs = cells
+    loads = [[1.0, 0.0, 0.0], [0.0, 1.0, 0.0]]
+    its_dense = [ms.solve(kv[0], K0, E, tol=1e-4, max_iter=200)[1] for E in loads]
+    assert its_dense == [14, 15]
+    o = q.solve_opts(1e-10, 0, tol=1e-4, max_iter=120, mode=q.ROUND_SVD)
+    ops, e = P.upload(probs[0], loads, 0)
+    A, its, _, st = q.homogenize(ctx, ops, e, o)
+    assert st == q.QT_OK
+    print(f"[batch] iterations batched {list(its)}, dense {its_dense}", flush=True)
+    assert list(its) == its_dense
+    for j, E in enumerate(loads):
+        ops1, e1 = P.upload(probs[0], [E], 0)
+        A1, its1, _, st1 = q.homogenize(ctx, ops1, e1, o)
+        assert st1 == q.QT_OK and int(its1[0]) == its_dense[j]
+        d = np.max(np.abs(A[j] - A1[0])) / np.max(np.abs(A1[0]))
+        print(f"[batch] load {j}: batched vs separate A_eff {d:.2e}", flush=True)
+        assert d < 1e-9
