@@ -8,6 +8,9 @@ namespace qt {
 struct PolarSizes {
   int ncap = 1, mcap = 1, lcap = 1;
   int64_t y = 1, g = 1, c = 1, r = 1, tau = 1;   // elements per instance
+  // blocked-QR workspace of the subspace iteration's ncap x lcap QRs (zero
+  // when one workgroup's registers or LDS hold them)
+  int64_t qb_v = 0, qb_t = 0, qb_w = 0, qb_tau = 0;
 };
 PolarSizes polar_sizes(int ncap, int mcap, int lcap);
 size_t polar_ws_bytes(int B, const PolarSizes& s);
@@ -18,6 +21,7 @@ struct PolarWs {
   double* tau;
   double* nrm;     // [3][B]
   int32_t* sq;     // [B]
+  QrBlkWs qb;      // V null: the QRs run in one workgroup
 };
 qt_status polar_ws_take(qt_ctx ctx, int B, const PolarSizes& s, PolarWs& w);
 // Quintic steps that bring relative singular values down to a twentieth of

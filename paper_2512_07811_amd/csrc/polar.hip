@@ -45,12 +45,37 @@ PolarSizes polar_sizes(int ncap, int mcap, int lcap) {
   s.c = (int64_t)ncap * lcap;
   s.r = (int64_t)lcap * lcap;
   s.tau = lcap + 4;
+  // every bond's QR is (rows x min(rows, lcap)) with rows <= ncap, and the
+  // blocked QR's panel width depends on the rows: the largest need over them
+  for (int m = 1; m <= ncap; ++m) {
+    const int c = std::min(m, lcap);
+    if (!qr_blocked_wanted(m, c)) continue;
+    int64_t v, t, w;
+    qr_blocked_ws_elems(m, c, &v, &t, &w);
+    s.qb_v = std::max(s.qb_v, v);
+    s.qb_t = std::max(s.qb_t, t);
+    s.qb_w = std::max(s.qb_w, w);
+    s.qb_tau = std::max(s.qb_tau, qr_blocked_tau_elems(m, c));
+  }
   return s;
 }
 
+// The blocked-QR workspace of w covers an ncap x lcap factorization.
+static bool polar_qb_fits(const PolarWs& w, int ncap, int lcap) {
+  if (!w.qb.V || !qr_blocked_wanted(ncap, lcap)) return false;
+  int64_t v, t, q;
+  qr_blocked_ws_elems(ncap, lcap, &v, &t, &q);
+  return v <= w.s.qb_v && t <= w.s.qb_t && q <= w.s.qb_w &&
+         qr_blocked_tau_elems(ncap, lcap) <= w.s.qb_tau;
+}
+
 size_t polar_ws_bytes(int B, const PolarSizes& s) {
-  return sizeof(cplx) * B * (2 * s.y + 5 * s.g + 5 * s.c + s.r) + sizeof(double) * B * (s.tau + 4) +
-         sizeof(int32_t) * B + 16 * 256;
+  size_t b = sizeof(cplx) * B * (2 * s.y + 5 * s.g + 5 * s.c + s.r) +
+             sizeof(double) * B * (s.tau + 4) + sizeof(int32_t) * B + 16 * 256;
+  if (s.qb_v > 0)
+    b += sizeof(cplx) * B * (s.qb_v + s.qb_t + 2 * s.qb_w) + sizeof(double) * B * s.qb_tau +
+         sizeof(int32_t) * B + 6 * 256;
+  return b;
 }
 
 qt_status polar_ws_take(qt_ctx ctx, int B, const PolarSizes& s, PolarWs& w) {
@@ -74,6 +99,22 @@ qt_status polar_ws_take(qt_ctx ctx, int B, const PolarSizes& s, PolarWs& w) {
   QT_CHECK(w.Y0 && w.Y1 && w.G && w.P && w.H && w.Z0 && w.Z1 && w.Om && w.V && w.W && w.C &&
                w.Wq && w.R && w.tau && w.nrm && w.sq,
            QT_ENOMEM, "polar rounding: workspace too small");
+  w.qb = QrBlkWs{};
+  if (s.qb_v > 0) {
+    QrBlkWs& q = w.qb;
+    q.V = (cplx*)ws_take(ctx, sizeof(cplx) * B * s.qb_v);
+    q.v_stride = s.qb_v;
+    q.T = (cplx*)ws_take(ctx, sizeof(cplx) * B * s.qb_t);
+    q.t_stride = s.qb_t;
+    q.W1 = (cplx*)ws_take(ctx, sizeof(cplx) * B * s.qb_w);
+    q.W2 = (cplx*)ws_take(ctx, sizeof(cplx) * B * s.qb_w);
+    q.w_stride = s.qb_w;
+    q.tau = (double*)ws_take(ctx, sizeof(double) * B * s.qb_tau);
+    q.tau_stride = s.qb_tau;
+    q.s_dev = (int32_t*)ws_take(ctx, sizeof(int32_t) * B);
+    QT_CHECK(q.V && q.T && q.W1 && q.W2 && q.tau && q.s_dev, QT_ENOMEM,
+             "polar rounding: blocked QR workspace too small");
+  }
   return QT_OK;
 }
 
@@ -295,7 +336,16 @@ void polar_trunc(hipStream_t st, int B, int ncap, int mcap, Dim n, Dim m, const 
   gemm_ex(st, B, 1, 1, n, l, n, ncap, lcap, mat(Z, sG, sconst(ldG), s1), false,
           mat(w.Om, sC, sconst(lcap), s1), false, mat(w.V, sC, sl, s1), one, false,
           Dim{nullptr, 0, 0, 1 << 30}, ncap);
-  qr_auto(st, B, ncap, lcap, n, l, w.V, sC, w.Wq, sC, w.tau, s.tau, w.C, sC, w.R, s.r, w.sq, 1);
+  // C = Q of the n x l block M (panels + MFMA GEMMs when one workgroup cannot
+  // hold it: the work matrix is Wq either way)
+  const bool blocked = polar_qb_fits(w, ncap, lcap);
+  auto qr_c = [&](const cplx* M) {
+    if (blocked)
+      qr_blocked(st, B, ncap, lcap, n, l, M, sC, w.Wq, sC, w.qb, w.C, sC, w.R, s.r, w.sq, 1);
+    else
+      qr_auto(st, B, ncap, lcap, n, l, M, sC, w.Wq, sC, w.tau, s.tau, w.C, sC, w.R, s.r, w.sq, 1);
+  };
+  qr_c(w.V);
   // C <- qr(P+ H^2 C): inside range(P+) the directions converge at the rate
   // (sigma_{l+1} / sigma_l)^2 per step towards the l largest (the rank cap)
   for (int it = 0; it < PSUB_STEPS; ++it) {
@@ -308,7 +358,7 @@ void polar_trunc(hipStream_t st, int B, int ncap, int mcap, Dim n, Dim m, const 
     gemm_ex(st, B, 1, 1, n, l, n, ncap, lcap, mat(Z, sG, sconst(ldG), s1), false,
             mat(w.V, sC, sl, s1), false, mat(w.W, sC, sl, s1), one, false,
             Dim{nullptr, 0, 0, 1 << 30}, ncap);
-    qr_auto(st, B, ncap, lcap, n, l, w.W, sC, w.Wq, sC, w.tau, s.tau, w.C, sC, w.R, s.r, w.sq, 1);
+    qr_c(w.W);
   }
   // ---- core = C^H U^H (l x m, packed), carry = H C (n x l, packed)
   gemm_ex(st, B, 1, 1, l, m, n, lcap, mcap, mat(w.C, sC, s1, sl), true,

@@ -150,3 +150,29 @@ def test_polar_round_large_orders_against_svd_rounding(q, ctx):
           f"{float(e_p[0]):.3e} ({dt * 1e3:.1f} ms)", flush=True)
     assert all(a >= s for a, s in zip(rp, rs))
     assert float(e_p[0]) <= eps * (1 + 1e-9)
+
+
+def test_polar_round_matches_oracle_at_rank_128(q, ctx):
+    # rank-128 bonds: the subspace iteration's 128 x l QRs exceed one
+    # workgroup's LDS and run as blocked panel QRs with MFMA updates; the
+    # spectra keep 41 % away from every cutoff, so the kept directions are the
+    # oracle's
+    modes = [3] + [2] * 14
+    R = [1, 3, 6, 12, 24, 48, 96, 128, 128, 96, 48, 24, 12, 6, 3, 1]
+    eps = 1e-7
+    x = I.graded_tt(modes, R, decay=0.95, seed=90)
+    assert min_gap(x, eps) > 0.4
+    X = q.DeviceTT.from_cores([x])
+    err, _ = q.tt_round(ctx, X, eps, 0, mode=q.ROUND_POLAR, seed=4)
+    ctx.sync()
+    out = X.to_cores()[0]
+    err = float(err.cpu().numpy()[0])
+    ref, info = PO.round_polar(x, eps, return_info=True)
+    print(f"[polar] rank 128: ranks {T.ranks(out)} oracle {info['ranks']}, err {err:.4e} "
+          f"oracle {info['err']:.4e}, vs oracle {rel(T.full(out), T.full(ref)):.2e}", flush=True)
+    assert max(T.ranks(out)) == 128
+    assert T.ranks(out) == info["ranks"]
+    assert rel(T.full(out), T.full(ref)) < 1e-10
+    assert abs(err - info["err"]) <= 1e-9 * info["err"] + 1e-14
+    for c in out[1:]:
+        assert np.allclose(T.right_gram(c), np.eye(c.shape[0]), atol=1e-12)
