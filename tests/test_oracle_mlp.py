@@ -1,4 +1,5 @@
-"""Pins of the rank-predictor MLP oracle: finite differences and Adam."""
+"""Pins of the rank-predictor MLP oracle: finite differences, Adam and the
+quantile class rule on known class probabilities."""
 import numpy as np
 
 from oracle import mlp
@@ -57,3 +58,17 @@ def test_training_separates_toy_classes():
     assert l < 0.5 * l0
     pred = mlp.predict_class(P, x, quantile=0.5)
     assert np.mean(pred == y) > 0.85
+
+
+def test_predict_class_takes_the_quantile_of_known_probabilities():
+    # zero weights: every hidden unit is tanh(0) = 0, so the logits are the
+    # last bias; with bias log p the class probabilities are p, and the class
+    # is the first one whose cumulative probability reaches the quantile
+    P = mlp.init_params(3, 4, seed=1)
+    for k in P:
+        P[k] = np.zeros_like(P[k])
+    last = max(int(k[1:]) for k in P if k.startswith("b"))
+    P[f"b{last}"] = np.log(np.array([0.1, 0.2, 0.3, 0.4]))   # cdf 0.1, 0.3, 0.6, 1.0
+    x = I.rng(5).standard_normal((7, 3))
+    for q, c in ((0.05, 0), (0.25, 1), (0.55, 2), (0.9, 3), (0.95, 3)):
+        assert mlp.predict_class(P, x, quantile=q).tolist() == [c] * 7
