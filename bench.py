@@ -615,6 +615,7 @@ def main():
             ms_, n_ = ctx.profile_read()
             c1 = ctx.counters()
             cls_ms[cname] = {"ms": ms_ / iters, "launches": n_ / iters,
+                             "svd_calls": (c1["svd_calls"] - c0["svd_calls"]) / iters,
                              "gemm_flops": (c1["gemm_flops"] - c0["gemm_flops"]) / iters,
                              "gemm_bytes": (c1["gemm_bytes"] - c0["gemm_bytes"]) / iters,
                              "fallbacks": c1["learned_fallbacks"] - c0["learned_fallbacks"]}
@@ -636,6 +637,7 @@ def main():
         split[args.mode] = class_split(opts, restore=False)
         ctx.counters(reset=True)
     comparison = accuracy = None
+    cnt_sk = None
     if args.mode == "learned" and not args.no_compare:
         dt_sk, res_sk, cnt_sk = window(sk_opts, "SVD-truncated")
         A_sk = a_eff(qtt, ctx, ops, e, ops.L)
@@ -723,10 +725,17 @@ def main():
         main = split[args.mode]
         qr_model, svd_model = iteration_model(ops, (e.modes, e.cap), cfg["rmax"], args.oversample)
         # the dominant class of the timed window: the class-timing iterations
-        # run past it, and their SVDs come only from fallbacks, so the SVD
-        # class takes part only when the window itself ran SVDs
-        cand = [k for k in main if k != "svd" or cnt["svd_calls"] > 0]
-        dom = max(cand, key=lambda k: main[k]["ms"])
+        # run past it, and their SVDs come only from fallbacks, whose number
+        # differs from the window's; the SVD class's time is scaled to the
+        # window's SVD calls per step
+        w_svd = cnt["svd_calls"] / args.steps
+        s_svd = main["svd"]["svd_calls"]
+
+        def window_ms(k):
+            if k != "svd":
+                return main[k]["ms"]
+            return main[k]["ms"] * w_svd / s_svd if s_svd > 0 else 0.0
+        dom = max(main, key=window_ms)
         g = main["gemm"]
         g_ach = g["gemm_flops"] / (g["ms"] * 1e-3) / 1e12 if g["ms"] > 0 else None
         classes = {"gemm": {"achieved": g_ach, "flops_per_step": g["gemm_flops"],
@@ -737,6 +746,14 @@ def main():
                    "qr": {"achieved": qr_model * B / (main["qr"]["ms"] * 1e-3) / 1e12
                           if main["qr"]["ms"] > 0 else None, "flops_per_step": qr_model * B,
                           "model": "Householder QR of every sketch with Q formed, 4 roundings"}}
+        if cnt_sk and cnt_sk["svd_calls"] > 0 and main["svd"]["ms"] > 0:
+            # the SVD model of a full SVD-truncated step, scaled to the
+            # class-timing iterations' share of its SVD calls
+            share = main["svd"]["svd_calls"] / (cnt_sk["svd_calls"] / args.steps)
+            classes["svd"] = {"achieved": svd_model * B * share / (main["svd"]["ms"] * 1e-3) / 1e12,
+                              "flops_per_step": svd_model * B * share,
+                              "model": "square SVD 21N^3 per block (x4 complex) on the "
+                                       "fallbacks' SVD calls"}
         ach = classes[dom]["achieved"] if dom in classes else None
         out["roofline"] = {
             "kernel": {"gemm": "structured GEMM (k_gemm_ex with its split-K sums)",
@@ -750,6 +767,7 @@ def main():
             "launches_per_step": {k: v["launches"] for k, v in main.items()},
             "classes": classes, "dominant_class": dom,
             "class_timing_fallbacks": {k: v["fallbacks"] for k, v in main.items()},
+            "svd_ms_per_step_window": window_ms("svd"),
         }
         if "svd_truncated" in split:
             sv = split["svd_truncated"]
