@@ -414,9 +414,11 @@ __device__ inline cplx group_sum(cplx v) {
 
 // RPL = 0: 16-lane groups stream their pair's columns from X in chunks, once
 // for the dot products and once for the rotation.  RPL > 0 (orders up to
-// 32 RPL): 32-lane groups keep the pair's columns in registers between the
-// dot products and the rotation, one load and one store per element.
-template <int RPL>
+// GL RPL): GL-lane groups keep the pair's columns in registers between the
+// dot products and the rotation, one load and one store per element.  The
+// 64 groups of 16 lanes take the 64 pairs of a step of order <= 128 in one
+// pass and those of orders <= 144 in two; 32-lane groups orders up to 256.
+template <int RPL, int GL>
 __global__ __launch_bounds__(1024) void k_jacobi_glb(
     Dim Md, Dim Cd, const cplx* __restrict__ Rin, int64_t sR, cplx* __restrict__ Xw, int64_t sX,
     cplx* __restrict__ Ul, int64_t sU, cplx* __restrict__ core, int64_t sCore, int32_t* l_out,
@@ -456,7 +458,8 @@ __global__ __launch_bounds__(1024) void k_jacobi_glb(
   const double negl = SL_NEGL * fro;
   const double jtol = SL_EPS * (double)nb, jtol2 = jtol * jtol;
   const int nbp = (nb + 1) & ~1;
-  constexpr int GL = RPL > 0 ? 32 : 16;   // lanes per pair
+  static_assert(GL == 16 || GL == 32, "pair groups of 16 or 32 lanes");
+  static_assert(RPL > 0 || GL == 16, "the streaming variant uses 16-lane groups");
   const int g = tid % GL, grp = tid / GL, ngrp = blockDim.x / GL;
   bool converged = nb < 2;
   int sweeps_done = 0;
@@ -680,14 +683,19 @@ bool svd_trunc_fast(hipStream_t st, int batch, int mcap, int ccap, Dim m, Dim c,
     k_jacobi_lds<SL_NB_BIG><<<batch, 1024, 0, st>>>(m, c, Rw, sR, Uw, sQ, core, sCore, l_out,
                                                      l_stride, delta, disc2, lmax, max_sweeps,
                                                      status, svlog, svstride, counters);
+#define QT_JGLB(RPL, GL)                                                                     \
+  k_jacobi_glb<RPL, GL><<<batch, 1024, 0, st>>>(m, c, Rw, sR, Xw, sR, Uw, sQ, core, sCore, l_out, \
+                                                l_stride, delta, disc2, lmax, max_sweeps,     \
+                                                status, svlog, svstride, counters)
+  else if (nbcap <= 16 * 8)
+    QT_JGLB(8, 16);
+  else if (nbcap <= 16 * 9)
+    QT_JGLB(9, 16);
   else if (nbcap <= 32 * SG_RPL)
-    k_jacobi_glb<SG_RPL><<<batch, 1024, 0, st>>>(m, c, Rw, sR, Xw, sR, Uw, sQ, core, sCore, l_out,
-                                                 l_stride, delta, disc2, lmax, max_sweeps, status,
-                                                 svlog, svstride, counters);
+    QT_JGLB(SG_RPL, 32);
   else
-    k_jacobi_glb<0><<<batch, 1024, 0, st>>>(m, c, Rw, sR, Xw, sR, Uw, sQ, core, sCore, l_out,
-                                            l_stride, delta, disc2, lmax, max_sweeps, status,
-                                            svlog, svstride, counters);
+    QT_JGLB(0, 16);
+#undef QT_JGLB
   // finishing products on the MFMA GEMM (each instance's sizes are zero in the
   // product of the orientation it does not have):
   //   core  = U[:, :l]^H Q^H  (l x nc)  for A^H = Q R;

@@ -159,6 +159,29 @@ def test_round_jacobi_orders_101_to_256_match_oracle(q, ctx, eps):
 
 
 @pytest.mark.parametrize("eps", [0.0, 1e-9])
+def test_round_jacobi_orders_128_and_136_match_oracle(q, ctx, eps):
+    # SVD blocks of orders 136 and 128: the global-memory Jacobi's 16-lane
+    # pair groups (nine and eight elements per lane; a step's pairs in two
+    # passes and in one)
+    modes = [3] + [2] * 14
+    ranks = [1, 3, 6, 12, 24, 48, 96, 136, 128, 64, 32, 16, 8, 4, 2, 1]
+    xs = [I.graded_tt(modes, ranks, decay=0.96, seed=180 + b) for b in range(2)]
+    X = q.DeviceTT.from_cores(xs)
+    err, nrm = q.tt_round(ctx, X, eps, 0)
+    ctx.sync()
+    out = X.to_cores()
+    nrm = nrm.cpu().numpy()
+    for b in range(2):
+        ref, info = T.round_tt(xs[b], eps, None, return_info=True)
+        assert T.ranks(out[b]) == T.ranks(ref)
+        assert rel(T.full(out[b]), T.full(ref)) < 1e-10
+        assert abs(nrm[b] - info["norm"]) < 1e-12 * info["norm"]
+        for c in out[b][1:]:
+            G = T.right_gram(c)
+            assert np.allclose(G, np.eye(G.shape[0]), atol=1e-12)
+
+
+@pytest.mark.parametrize("eps", [0.0, 1e-9])
 def test_round_large_ranks_matches_oracle(q, ctx, eps):
     # bond ranks up to 100: the right sweep's SVD orders exceed the LDS Jacobi
     # (68) and the left sweep's matrices exceed LDS, so the global-memory QR
