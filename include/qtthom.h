@@ -314,8 +314,10 @@ qt_status tt_sketch_round(qt_ctx ctx, const qt_mpo* A, const qt_tt* y, const qt_
  *  err_out: device [B] (may be null), the last sweep's rounding error of y
  *     relative to its norm.
  * Batches: x, y, z share the batch; A is shared or per instance (inst_group).
- * A must be square on x's modes.  Both y and z are first rounded at eps = 0
- * (right-orthogonal frames).  Workspace grows as needed. */
+ * A must be square on x's modes.  Both y and z are first made
+ * right-orthogonal by a QR sweep from their last cores (exact: ranks become
+ * min(r_k, p_k r_{k+1})), and z again after every sweep.  Workspace grows as
+ * needed. */
 qt_status tt_amen_mv(qt_ctx ctx, const qt_mpo* A, const qt_tt* x, qt_tt* y, qt_tt* z, double eps,
                      int32_t max_rank, int32_t sweeps, double* err_out);
 

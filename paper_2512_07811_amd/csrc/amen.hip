@@ -22,7 +22,8 @@
 //                                     - Phi^{zy}_L y_k Phi^{zy}_R)
 //   last core          the local solutions of y and z
 // then one TT rounding of y at eps (the SVD rounding's delta rule and cap),
-// which leaves y right-orthogonal, and a rounding of z at eps = 0.
+// which leaves y right-orthogonal, and a right orthogonalization of z (QR
+// sweep from its last core; y and z get the same one before the first sweep).
 #include "kernels.h"
 #include "round.h"
 
@@ -198,14 +199,14 @@ size_t amen_bytes(const Sizes& s) {
 qt_status amen_impl(qt_ctx ctx, const qt_mpo* A, const qt_tt* x, qt_tt* y, qt_tt* z, double eps,
                     int max_rank, int sweeps, double* err_out) {
   // the sweep projects onto right-orthogonal frames: bring y and z there
-  // (an exact rounding: its right truncated-SVD sweep at eps = 0)
+  // (an exact right orthogonalization: a QR sweep from the last core)
+  qt_round_opts r0{};
+  r0.mode = QT_ROUND_SVD;
   {
-    qt_round_opts r0{};
-    r0.mode = QT_ROUND_SVD;
     const size_t m0 = ctx->ws_top;
-    QT_TRY(round_impl(ctx, y, &r0, nullptr, nullptr, false, nullptr, 0, 0));
+    QT_TRY(round_impl(ctx, y, &r0, nullptr, nullptr, false, nullptr, 0, 0, true));
     ctx->ws_top = m0;
-    QT_TRY(round_impl(ctx, z, &r0, nullptr, nullptr, false, nullptr, 0, 0));
+    QT_TRY(round_impl(ctx, z, &r0, nullptr, nullptr, false, nullptr, 0, 0, true));
     ctx->ws_top = m0;
   }
   const Sizes s = amen_sizes(A, x, y, z);
@@ -474,9 +475,7 @@ qt_status amen_impl(qt_ctx ctx, const qt_mpo* A, const qt_tt* x, qt_tt* y, qt_tt
     QT_TRY(round_impl(ctx, &ty, &ro, sw + 1 == sweeps ? err_out : nullptr, nullptr, false, nullptr,
                       0, 0));
     ctx->ws_top = mark;
-    ro.eps = 0.0;
-    ro.max_rank = 0;
-    QT_TRY(round_impl(ctx, &tz, &ro, nullptr, nullptr, false, nullptr, 0, 0));
+    QT_TRY(round_impl(ctx, &tz, &r0, nullptr, nullptr, false, nullptr, 0, 0, true));
     ctx->ws_top = mark;
     for (int k = 0; k < n; ++k) {
       copy(st, B, dref(rk_y + k, rs, s.p[k]), dref(rk_y + k + 1, rs),

@@ -104,7 +104,7 @@ bool svd_trunc_fast(hipStream_t st, int batch, int mcap, int ccap, Dim m, Dim c,
                     double* tau, int64_t sT, const QrBlkWs* qb, cplx* core, int64_t sCore, cplx* carry,
                     int64_t sCarry, int32_t* l_out, int l_stride, const double* delta,
                     double* disc2, int lmax, int max_sweeps, int32_t* status, double* svlog,
-                    int64_t svstride, unsigned long long* counters);
+                    int64_t svstride, unsigned long long* counters, bool exact = false);
 
 // Frobenius norm of a packed rows x cols matrix per instance; also sets
 // delta[b] = eps * norm / sqrt(nb_bonds) (0 when nb_bonds == 0) and disc2[b] = 0.

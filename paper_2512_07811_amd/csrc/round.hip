@@ -85,7 +85,7 @@ RoundWs round_ws_layout(const qt_tt* x, int lmax_cap, bool polar) {
 
 qt_status round_impl(qt_ctx ctx, qt_tt* x, const qt_round_opts* o, double* err_out,
                      double* norm_out, bool left_only, double* svlog, int64_t svstride_bond,
-                     int64_t svstride_inst) {
+                     int64_t svstride_inst, bool orth_only) {
   const int n = x->n, B = x->batch;
   hipStream_t st = ctx->stream;
   const int lmax_cap = o->max_rank > 0 ? o->max_rank : (1 << 30);
@@ -135,6 +135,19 @@ qt_status round_impl(qt_ctx ctx, qt_tt* x, const qt_round_opts* o, double* err_o
     return QT_OK;
   }
   k_init_left<<<B, 64, 0, st>>>(n, B, rk, rkl);
+  if (orth_only) {
+    // exact right orthogonalization: the right sweep's QRs from x's own last
+    // core, no left sweep, nothing truncated, no error or norm
+    QT_CHECK(!polar && !err_out && !norm_out && !svlog, QT_EINVAL,
+             "right orthogonalization: SVD mode without error outputs");
+    SweepBufs buf{scratch, Bsv, Vb, Cb, w.slot, w.vv, w.carry};
+    QT_TRY(take_sweep_extra(ctx, B, w, buf));
+    buf.exact = true;
+    QT_TRY(right_sweep_impl(ctx, x, rkl, X + x->offsets[n - 1], sX, buf, delta, disc2, lmax_cap,
+                            sweeps, nullptr, 0, 0));
+    QT_HIP(hipGetLastError());
+    return QT_OK;
+  }
   // ---- left orthogonalization sweep
   for (int k = 0; k < n - 1; ++k) {
     const int p = x->modes[k];
@@ -259,7 +272,7 @@ qt_status right_sweep_impl(qt_ctx ctx, qt_tt* x, const int32_t* rkl, const cplx*
                                    buf.tau, buf.nbmax, buf.qb.V ? &buf.qb : nullptr,
                                    X + x->offsets[k], sX, buf.C,
                                    buf.carry, rk + k, rs, delta, disc2, lmax, nsw, ctx->status,
-                                   svk, svi, ctx->counters);
+                                   svk, svi, ctx->counters, buf.exact);
     QT_CHECK(ok, QT_ECAPACITY, "rounding: SVD block above 1024 columns");
     if (prof) g_prof->end();
     const int pp = x->modes[k - 1];

@@ -61,6 +61,8 @@ struct SweepBufs {
   const PolarWs* polar = nullptr;
   int polar_nq = 0;
   uint64_t polar_seed = 0;
+  // exact right orthogonalization: the SVD blocks' QR only, nothing truncated
+  bool exact = false;
 };
 qt_status take_sweep_extra(qt_ctx ctx, int B, const RoundWs& w, SweepBufs& buf);
 qt_status right_sweep_impl(qt_ctx ctx, qt_tt* x, const int32_t* rkl, const cplx* center,

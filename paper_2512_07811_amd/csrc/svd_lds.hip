@@ -642,13 +642,29 @@ __global__ void k_qr2_prep(Dim Md, Dim Cd, const cplx* __restrict__ R, int64_t s
   }
 }
 
+// Identity factors of an exact (untruncated) block: rank l = min(m, c); a
+// wide instance gets U = I (l x l, row r = column r of U) in Uw, a tall one
+// the core I (c x c, rows of V^H).
+__global__ void k_orth_identity(Dim Md, Dim Cd, cplx* __restrict__ Uw, int64_t sU,
+                                cplx* __restrict__ core, int64_t sCore, int32_t* l_out,
+                                int l_stride) {
+  const int b = blockIdx.x;
+  const int m = dimv(Md, b), c = dimv(Cd, b);
+  const bool tall = m >= c;
+  const int l = tall ? c : m;
+  cplx* dst = tall ? core + b * sCore : Uw + b * sU;
+  for (int64_t e = threadIdx.x; e < (int64_t)l * l; e += blockDim.x)
+    dst[e] = make_double2(e / l == e % l ? 1.0 : 0.0, 0.0);
+  if (threadIdx.x == 0) l_out[(int64_t)b * l_stride] = l;
+}
+
 bool svd_trunc_fast(hipStream_t st, int batch, int mcap, int ccap, Dim m, Dim c, const cplx* A,
                     int64_t sA, cplx* Qw, cplx* Uw, int64_t sQ, cplx* Rw, cplx* Xw, int64_t sR,
                     double* tau, int64_t sT, const QrBlkWs* qb, cplx* core, int64_t sCore,
                     cplx* carry, int64_t sCarry, int32_t* l_out, int l_stride,
                     const double* delta, double* disc2, int lmax, int max_sweeps,
                     int32_t* status, double* svlog, int64_t svstride,
-                    unsigned long long* counters) {
+                    unsigned long long* counters, bool exact) {
   const int mbcap = std::max(mcap, ccap), nbcap = std::min(mcap, ccap);
   if (nbcap > SG_NB) return false;
   // blocks beyond one workgroup's LDS with >= 256 columns: panel + GEMM QRs
@@ -664,6 +680,11 @@ bool svd_trunc_fast(hipStream_t st, int batch, int mcap, int ccap, Dim m, Dim c,
   // the first nb <= sT - 4)
   int32_t* fd = reinterpret_cast<int32_t*>(tau + sT - 4);
   const int ds = (int)(2 * sT);
+  if (exact) {
+    // no truncation: U = I for wide instances (core = Q^H of A^H = Q R,
+    // carry = A Q = R^H), core = I for tall ones (carry = A), rank min(m, c)
+    k_orth_identity<<<batch, 256, 0, st>>>(m, c, Uw, sQ, core, sCore, l_out, l_stride);
+  } else {
   // wide instances: R2 of the second QR (R^H = Q2 R2) over R, Q2 not formed
   k_qr2_prep<<<batch, 256, 0, st>>>(m, c, Rw, sR, Xw, sR, fd, ds);
   const Dim d2 = dref(fd + 6, ds);
@@ -696,6 +717,7 @@ bool svd_trunc_fast(hipStream_t st, int batch, int mcap, int ccap, Dim m, Dim c,
   else
     QT_JGLB(0, 16);
 #undef QT_JGLB
+  }
   // finishing products on the MFMA GEMM (each instance's sizes are zero in the
   // product of the orientation it does not have):
   //   core  = U[:, :l]^H Q^H  (l x nc)  for A^H = Q R;
