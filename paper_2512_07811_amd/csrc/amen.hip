@@ -472,8 +472,10 @@ qt_status amen_impl(qt_ctx ctx, const qt_mpo* A, const qt_tt* x, qt_tt* y, qt_tt
     ro.max_rank = max_rank;
     ro.mode = QT_ROUND_SVD;
     ctx->ws_top = mark;
+    // the sweep left y's cores 0..n-2 as Q factors (orthonormal columns, the
+    // padding's zeroed): the rounding needs no left QR sweep
     QT_TRY(round_impl(ctx, &ty, &ro, sw + 1 == sweeps ? err_out : nullptr, nullptr, false, nullptr,
-                      0, 0));
+                      0, 0, false, true));
     ctx->ws_top = mark;
     QT_TRY(round_impl(ctx, &tz, &r0, nullptr, nullptr, false, nullptr, 0, 0, true));
     ctx->ws_top = mark;

@@ -24,9 +24,12 @@ RoundWs round_ws_layout(const qt_tt* x, int lmax_cap, bool polar = false);
 // orth_only: no rounding, an exact right orthogonalization of x (cores 1..n-1
 // with orthonormal rows, ranks min(r_k, p_k r_{k+1})) by the right sweep's QRs
 // (SVD mode, no error, norm or log outputs).
+// left_orth: the caller guarantees that cores 0..n-2 have orthonormal or zero
+// columns; the left QR sweep is skipped (the truncation sweep and its delta
+// rule start from the last core, whose norm is ||x||).
 qt_status round_impl(qt_ctx ctx, qt_tt* x, const qt_round_opts* o, double* err_out,
                      double* norm_out, bool left_only, double* svlog, int64_t svstride_bond,
-                     int64_t svstride_inst, bool orth_only = false);
+                     int64_t svstride_inst, bool orth_only = false, bool left_orth = false);
 qt_status hadamard_impl(qt_ctx ctx, const qt_tt* a, const qt_tt* b, qt_tt* out);
 qt_status mpo_impl(qt_ctx ctx, const qt_mpo* A, const qt_tt* x, qt_tt* out);
 qt_status add_impl(qt_ctx ctx, double are, double aim, const qt_tt* x, double bre, double bim,

@@ -85,7 +85,7 @@ RoundWs round_ws_layout(const qt_tt* x, int lmax_cap, bool polar) {
 
 qt_status round_impl(qt_ctx ctx, qt_tt* x, const qt_round_opts* o, double* err_out,
                      double* norm_out, bool left_only, double* svlog, int64_t svstride_bond,
-                     int64_t svstride_inst, bool orth_only) {
+                     int64_t svstride_inst, bool orth_only, bool left_orth) {
   const int n = x->n, B = x->batch;
   hipStream_t st = ctx->stream;
   const int lmax_cap = o->max_rank > 0 ? o->max_rank : (1 << 30);
@@ -145,6 +145,27 @@ qt_status round_impl(qt_ctx ctx, qt_tt* x, const qt_round_opts* o, double* err_o
     buf.exact = true;
     QT_TRY(right_sweep_impl(ctx, x, rkl, X + x->offsets[n - 1], sX, buf, delta, disc2, lmax_cap,
                             sweeps, nullptr, 0, 0));
+    QT_HIP(hipGetLastError());
+    return QT_OK;
+  }
+  if (left_orth) {
+    // cores 0..n-2 already have orthonormal (or zero) columns: ||x|| is the
+    // last core's norm, and the truncation sweep starts from that core
+    QT_CHECK(!left_only, QT_EINVAL, "rounding: left_orth with left_only");
+    norm_delta(st, B, dref(rkl + n - 1, rs), dconst(x->modes[n - 1]), X + x->offsets[n - 1], sX,
+               norm, delta, disc2, o->eps, n - 1);
+    SweepBufs buf{scratch, Bsv, Vb, Cb, w.slot, w.vv, w.carry};
+    QT_TRY(take_sweep_extra(ctx, B, w, buf));
+    PolarWs pw{};
+    if (polar) {
+      QT_TRY(polar_ws_take(ctx, B, w.pol, pw));
+      buf.polar = &pw;
+      buf.polar_nq = polar_quintic_steps(o->eps, n - 1, std::min(w.pol.ncap, w.pol.mcap));
+      buf.polar_seed = o->seed;
+    }
+    QT_TRY(right_sweep_impl(ctx, x, rkl, X + x->offsets[n - 1], sX, buf, delta, disc2, lmax_cap,
+                            sweeps, svlog, svstride_bond, svstride_inst));
+    finalize_err(st, B, disc2, norm, err_out, norm_out);
     QT_HIP(hipGetLastError());
     return QT_OK;
   }
