@@ -410,6 +410,21 @@ def green_step(qtt, ctx, ops, prev, e, cfg, args):
                     "norm <tau^, Gamma^ tau^> it needs for its error budget"}
 
 
+def dominant_class(cls_ms, window_svd_calls_per_step):
+    """The kernel class with the most time per iteration of the timed window.
+    `cls_ms` holds per-iteration averages of the class-timing iterations, which
+    run past the window: their SVDs come only from fallbacks, whose number
+    differs from the window's, so the SVD class's time is scaled to the
+    window's SVD calls per step.  Returns (class, the SVD class's scaled ms)."""
+    s_svd = cls_ms["svd"]["svd_calls"]
+
+    def window_ms(k):
+        if k != "svd":
+            return cls_ms[k]["ms"]
+        return cls_ms[k]["ms"] * window_svd_calls_per_step / s_svd if s_svd > 0 else 0.0
+    return max(cls_ms, key=window_ms), window_ms("svd")
+
+
 def under_profiler() -> bool:
     """rocprofv3 preloads its library, which initialises the GPU before this
     program starts: no worker processes may be forked then."""
@@ -724,18 +739,7 @@ def main():
     if split:
         main = split[args.mode]
         qr_model, svd_model = iteration_model(ops, (e.modes, e.cap), cfg["rmax"], args.oversample)
-        # the dominant class of the timed window: the class-timing iterations
-        # run past it, and their SVDs come only from fallbacks, whose number
-        # differs from the window's; the SVD class's time is scaled to the
-        # window's SVD calls per step
-        w_svd = cnt["svd_calls"] / args.steps
-        s_svd = main["svd"]["svd_calls"]
-
-        def window_ms(k):
-            if k != "svd":
-                return main[k]["ms"]
-            return main[k]["ms"] * w_svd / s_svd if s_svd > 0 else 0.0
-        dom = max(main, key=window_ms)
+        dom, svd_window_ms = dominant_class(main, cnt["svd_calls"] / args.steps)
         g = main["gemm"]
         g_ach = g["gemm_flops"] / (g["ms"] * 1e-3) / 1e12 if g["ms"] > 0 else None
         classes = {"gemm": {"achieved": g_ach, "flops_per_step": g["gemm_flops"],
@@ -767,7 +771,7 @@ def main():
             "launches_per_step": {k: v["launches"] for k, v in main.items()},
             "classes": classes, "dominant_class": dom,
             "class_timing_fallbacks": {k: v["fallbacks"] for k, v in main.items()},
-            "svd_ms_per_step_window": window_ms("svd"),
+            "svd_ms_per_step_window": svd_window_ms,
         }
         if "svd_truncated" in split:
             sv = split["svd_truncated"]

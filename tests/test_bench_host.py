@@ -1,4 +1,5 @@
-"""Host-side checks of bench.py (no GPU): the one-GPU guard and the tt_round flop model."""
+"""Host-side checks of bench.py (no GPU): the one-GPU guard, the tt_round flop model
+and the choice of the dominant kernel class."""
 import json
 import os
 import subprocess
@@ -39,3 +40,19 @@ def test_round_flop_model_interior_core():
         return bench.round_model_flops(modes, rk, rk)
     per_core = 4.0 * (4 + (4 - 2 / 3) + (4 - 2 / 3) + 21 + 4 + 4) * R ** 3
     assert fl(26) - fl(25) == pytest.approx(per_core, rel=1e-12)
+
+
+def test_dominant_class_scales_the_svd_class_to_the_window():
+    # class-timing iterations with 4 fallbacks' SVDs (120 SVD calls per
+    # iteration, 300 ms) against a window without any: the GEMM dominates
+    cls = {"gemm": {"ms": 75.0, "svd_calls": 120.0}, "qr": {"ms": 19.0, "svd_calls": 120.0},
+           "svd": {"ms": 300.0, "svd_calls": 120.0}}
+    assert bench.dominant_class(cls, 0.0) == ("gemm", 0.0)
+    # a window with as many SVD calls as those iterations keeps the SVD's time
+    assert bench.dominant_class(cls, 120.0) == ("svd", 300.0)
+    # a third of them: 100 ms, still above the GEMM
+    dom, ms = bench.dominant_class(cls, 40.0)
+    assert dom == "svd" and ms == pytest.approx(100.0)
+    # no SVDs in the class-timing iterations: the SVD class cannot dominate
+    cls["svd"] = {"ms": 0.0, "svd_calls": 0.0}
+    assert bench.dominant_class(cls, 3.0) == ("gemm", 0.0)
