@@ -96,3 +96,19 @@ def test_rank_cap_is_near_the_best_capped_rounding():
     best = T.round_tt(T.mpo_apply(A, x), 1e-13, rmax=5)
     assert max(T.ranks(y)) <= 5
     assert rel(T.full(y), ref) <= 1.05 * rel(T.full(best), ref)
+
+
+def test_right_orthogonalization_keeps_the_train_and_orthonormalizes_its_rows():
+    # ranks above the natural bound on the right (8 > 2 * 2 at the last bonds)
+    # shrink to min(r_k, p_k r_{k+1}); the tensor is unchanged
+    x = I.random_tt(MODES, [1, 3, 6, 12, 12, 8, 8, 8, 1], seed=51)
+    y = AM.orthogonalize_right(x)
+    assert rel(T.full(y), T.full(x)) < 1e-13
+    for c in y[1:]:
+        r, p, r2 = c.shape
+        M = c.reshape(r, p * r2)
+        assert np.allclose(M @ M.conj().T, np.eye(r), atol=1e-13)
+    r_in, ranks = [1, 3, 6, 12, 12, 8, 8, 8, 1], T.ranks(y)
+    for k in range(len(MODES) - 1, 0, -1):
+        assert ranks[k] == min(r_in[k], MODES[k] * ranks[k + 1])
+    assert ranks[-2] == 2 and ranks[-3] == 4
