@@ -4,7 +4,8 @@ The reference is T.full of T.mpo_apply (the exact TT x TTO contraction, pinned
 in test_oracle_tt.py) or the dense matrix-vector product: exact recovery once
 the frames cover the product's rank, convergence by enrichment from a rank-1
 start, the tolerance, the Hadamard product through the diagonal lift, the
-identity operator and the rank cap.
+identity operator and the rank cap; and the right orthogonalization the
+sweeps start from (the tensor kept, orthonormal rows, ranks min(r_k, p_k r_{k+1})).
 """
 import numpy as np
 import pytest
